@@ -1,0 +1,182 @@
+"""FP64 CPU oracle for checkerboard Metropolis sweeps of the 2-d XY model.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``; never by the product library.
+
+The arithmetic lives in ``xy_oracle.c`` (plain C, FP64); this module builds it
+with gcc when needed and marshals numpy arrays through ctypes.  Every function
+follows the definitions stated in that file's header: the XY Hamiltonian of
+section 1.2 (eq. 1) with J = 1 and Boltzmann weight exp(-beta H), single-site
+Metropolis over the red then the black sublattice, Philox4x32-10 streams.
+
+Angles use the natural layout ``theta[y, x]`` (an ``(L, L)`` float64 array).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "xy_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+PREC_F64, PREC_F32, PREC_F16 = 0, 1, 2
+_PREC = {"f64": PREC_F64, "f32": PREC_F32, "f16": PREC_F16}
+
+
+def build(force: bool = False) -> str:
+    """Compile ``xy_oracle.c`` into ``liboracle.so`` with gcc (single-threaded)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        dp = ctypes.POINTER(ctypes.c_double)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_u01.argtypes = [ctypes.c_uint32]
+        L.orc_u01.restype = ctypes.c_double
+        L.orc_site_words.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_uint32, ctypes.c_uint32, u32p]
+        L.orc_site_words.restype = None
+        L.orc_round_f16.argtypes = [ctypes.c_double]
+        L.orc_round_f16.restype = ctypes.c_double
+        L.orc_propose.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.orc_propose.restype = ctypes.c_double
+        L.orc_hot_start.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, dp]
+        L.orc_hot_start.restype = None
+        L.orc_measure.argtypes = [ctypes.c_int, dp, dp]
+        L.orc_measure.restype = None
+        L.orc_energy.argtypes = [ctypes.c_int, dp]
+        L.orc_energy.restype = ctypes.c_double
+        L.orc_sweep.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_uint32, ctypes.c_int, dp, dp, dp, u8p, dp]
+        L.orc_sweep.restype = ctypes.c_int64
+        L.orc_run.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                              ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, dp, dp]
+        L.orc_run.restype = ctypes.c_int64
+        L.orc_clock_sweep.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_uint32, i32p]
+        L.orc_clock_sweep.restype = ctypes.c_int64
+        L.orc_clock_run.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64, i32p, dp]
+        L.orc_clock_run.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _prec(p) -> int:
+    return _PREC[p] if isinstance(p, str) else int(p)
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def u01(w: int) -> float:
+    return lib().orc_u01(int(w) & 0xFFFFFFFF)
+
+
+def site_words(seed: int, L: int, x: int, y: int, sweep: int, purpose: int):
+    w = (ctypes.c_uint32 * 2)()
+    lib().orc_site_words(seed, L, x, y, sweep, purpose, w)
+    return int(w[0]), int(w[1])
+
+
+def round_f16(v: float) -> float:
+    return lib().orc_round_f16(float(v))
+
+
+def propose(theta: float, delta: float, u1: float, prec="f64") -> float:
+    return lib().orc_propose(float(theta), float(delta), float(u1), _prec(prec))
+
+
+def hot_start(seed: int, L: int, prec="f64") -> np.ndarray:
+    th = np.zeros((L, L), dtype=np.float64)
+    lib().orc_hot_start(seed, L, _prec(prec), _dp(th))
+    return th
+
+
+def measure(theta: np.ndarray) -> np.ndarray:
+    """FP64 [Cx, Cy, Ix, Iy, Mx, My] of a natural-layout (L, L) state."""
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.zeros(6, dtype=np.float64)
+    lib().orc_measure(th.shape[0], _dp(th), _dp(out))
+    return out
+
+
+def energy(theta: np.ndarray) -> float:
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    return lib().orc_energy(th.shape[0], _dp(th))
+
+
+def sweep(seed: int, theta: np.ndarray, beta: float, delta: float, sweep_index: int,
+          prec="f64", diagnostics: bool = False):
+    """One sweep in place.  Returns the accept count, or with ``diagnostics``
+    a dict of per-site dE, threshold T (decision is dE < T), decision and
+    proposed angle, all in the natural layout."""
+    L = theta.shape[0]
+    assert theta.dtype == np.float64 and theta.flags.c_contiguous
+    if not diagnostics:
+        return lib().orc_sweep(seed, L, beta, delta, sweep_index, _prec(prec), _dp(theta),
+                               None, None, None, None)
+    dE = np.zeros((L, L)); thr = np.zeros((L, L)); prop = np.zeros((L, L))
+    dec = np.zeros((L, L), dtype=np.uint8)
+    acc = lib().orc_sweep(seed, L, beta, delta, sweep_index, _prec(prec), _dp(theta),
+                          _dp(dE), _dp(thr), dec.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                          _dp(prop))
+    return {"accepts": acc, "dE": dE, "thr": thr, "dec": dec.astype(bool), "prop": prop}
+
+
+def run(seed: int, theta: np.ndarray, beta: float, delta: float, n_sweeps: int,
+        measure_every: int = 1, sweep0: int = 0, prec="f64") -> np.ndarray:
+    """n_sweeps sweeps in place; returns records (n_rec, 8):
+    [sweep count after, accepts, Cx, Cy, Ix, Iy, Mx, My]."""
+    L = theta.shape[0]
+    assert theta.dtype == np.float64 and theta.flags.c_contiguous
+    nrec = n_sweeps // measure_every if measure_every > 0 else 0
+    rec = np.zeros((max(nrec, 1), 8), dtype=np.float64)
+    got = lib().orc_run(seed, L, beta, delta, sweep0, n_sweeps, measure_every, _prec(prec),
+                        _dp(theta), _dp(rec))
+    return rec[:got]
+
+
+def clock_run(seed: int, ks: np.ndarray, q: int, beta: float, n_sweeps: int,
+              measure_every: int = 1, sweep0: int = 0) -> np.ndarray:
+    L = ks.shape[0]
+    assert ks.dtype == np.int32 and ks.flags.c_contiguous
+    nrec = n_sweeps // measure_every
+    rec = np.zeros((max(nrec, 1), 8), dtype=np.float64)
+    got = lib().orc_clock_run(seed, L, q, beta, sweep0, n_sweeps, measure_every,
+                              ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(rec))
+    return rec[:got]
+
+
+def clock_sweep(seed: int, ks: np.ndarray, q: int, beta: float, sweep_index: int) -> int:
+    L = ks.shape[0]
+    return lib().orc_clock_sweep(seed, L, q, beta, sweep_index,
+                                 ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
