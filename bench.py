@@ -1,0 +1,221 @@
+#!/usr/bin/env python
+"""Benchmark: checkerboard Metropolis sweeps of the 2-d XY model on one MI355X.
+
+Workload (default): one L = 4096 lattice (16.8 M sites, FP32 angles), beta = 1.12,
+delta = 1.0, hot start from seed 1; W warm-up steps (thermalisation) then K timed
+steps; one step = 10 sweeps plus one FP64 record of the energy, magnetisation and
+helicity sums (measured every 10 sweeps).  Defaults W = 100, K = 1000 reproduce the
+configuration's 10^3 thermalisation + 10^4 measured sweeps.
+
+Prints one JSON line.  `value` is site-updates per second (Gupd/s) of the timed
+region, inputs resident in HBM.  `roofline` covers the dominant kernel (the fused
+LDS-tiled sweep), timed with HIP events on the stream it runs on.  `cpu_baseline`
+is the FP64 C oracle on a bounded sample of the same workload on one host core.
+`extra` holds the other configurations of the metric: the HBM-streaming L = 16384
+lattice, the batched 96-lattice temperature scan against per-lattice launches,
+and the FP16-storage variant.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0                    # MI355X HBM3E
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock: 39.3 T lane-instr/s
+ALG_BYTES_FUSED = 8.0                    # bytes per site-update of one fused sweep: read 4 + write 4 (FP32)
+ALG_BYTES_STREAM = 12.0                  # two half-sweep passes: read both colours, write one, per half
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-extra", action="store_true", help="skip the L=16384, batched and FP16 legs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps of the L=4096 sample")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only the main workload's sweeps (for profiler runs)")
+    return ap.parse_args()
+
+
+def timed(fn, stream):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)            # ms
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_0811_2111_amd import workloads, xy
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    cfg = workloads.SINGLE_4096
+    L, me = cfg["L"], cfg["measure_every"]
+    N = L * L
+    lat = xy.Lattice(L, seed=cfg["seed"], beta=cfg["beta"], delta=cfg["delta"])
+    plan = lat.plan
+    obs_w = torch.empty((max(args.warmup, 1), 8), dtype=torch.float64, device="cuda")
+    obs_t = torch.empty((max(args.steps, 1), 8), dtype=torch.float64, device="cuda")
+    if args.warmup:
+        lat.sweep(me * args.warmup, me, out=obs_w)
+    ms = timed(lambda: lat.sweep(me * args.steps, me, out=obs_t), stream)
+    updates = float(N) * me * args.steps
+    gupd = updates / (ms * 1e-3) / 1e9
+    rec = xy.records(obs_t[: args.steps])
+    e_mean = float(-(rec["cx"] + rec["cy"]).mean() / N)
+    acc_rate = float(rec["n_accept"].mean() / N)
+
+    # dominant kernel: average duration of one fused launch (no measurement), events on the stream
+    nrep = 40
+    ms_k = timed(lambda: lat.sweep(nrep * plan[3] * 2), stream)
+    launches = nrep * 2 if plan[0] == 2 else nrep * 2 * plan[3] * 2
+    per_launch_ms = ms_k / launches
+    sweeps_per_launch = plan[3] if plan[0] == 2 else 0.5
+    upd_per_launch = N * sweeps_per_launch
+    alg_bytes = (ALG_BYTES_FUSED if plan[0] == 2 else ALG_BYTES_STREAM / 2) * upd_per_launch
+    achieved_gbs = alg_bytes / (per_launch_ms * 1e-3) / 1e9
+    gupd_kernel = upd_per_launch / (per_launch_ms * 1e-3) / 1e9
+    out = {
+        "metric": "site-updates/sec (Gupd/s) at 1 MI355X; % HBM roofline; batched vs per-lattice speedup",
+        "value": round(gupd, 3),
+        "unit": "Gupd/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / max(args.steps, 1), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (hot start from Philox seed 1)",
+        "config": {"workload": "XY checkerboard Metropolis, L=4096 single lattice, beta=1.12, delta=1.0, "
+                               "10 sweeps + FP64 E/M/helicity record per step",
+                   "L": L, "beta": cfg["beta"], "delta": cfg["delta"], "sweeps_per_step": me,
+                   "plan": {"kind": "fused" if plan[0] == 2 else "stream", "tile_x": plan[1], "tile_y": plan[2],
+                            "sweeps_per_pass": plan[3]},
+                   "parallelism": "single GPU"},
+        "roofline": {
+            "kernel": "k_fused (LDS-tiled fused red+black sweep)" if plan[0] == 2 else "k_half_sweep",
+            "bound": "hbm",
+            "achieved": round(achieved_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "alg_bytes_per_update": ALG_BYTES_FUSED if plan[0] == 2 else ALG_BYTES_STREAM,
+            "avg_launch_ms": round(per_launch_ms, 5),
+            "kernel_gupd_s": round(gupd_kernel, 2),
+        },
+        "observables": {"E_per_site": round(e_mean, 6), "accept_rate": round(acc_rate, 4)},
+    }
+
+    if not args.kernel_only and not args.no_extra:
+        out["extra"] = extra_legs(stream)
+
+    if not args.kernel_only and not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sweeps)
+
+    print(json.dumps(out), flush=True)
+
+
+def extra_legs(stream):
+    import torch
+
+    from paper_0811_2111_amd import workloads, xy
+    ex = {}
+    # HBM-streaming lattice
+    c4 = workloads.SINGLE_16384
+    L = c4["L"]
+    lat = xy.Lattice(L, seed=c4["seed"], beta=c4["beta"], delta=c4["delta"])
+    obs = torch.empty((c4["sweeps"], 8), dtype=torch.float64, device="cuda")
+    lat.sweep(4, 1, out=obs[:4])
+    ms = timed(lambda: lat.sweep(c4["sweeps"], c4["measure_every"], out=obs), stream)
+    g = float(L) * L * c4["sweeps"] / (ms * 1e-3) / 1e9
+    ex["L16384_hbm_streaming"] = {
+        "gupd_s": round(g, 2), "sweeps": c4["sweeps"], "ms": round(ms, 2), "plan": list(lat.plan),
+        "alg_GBps_8B": round(g * 8.0, 1), "frac_hbm_8B": round(g * 8.0 / HBM_PEAK_GBS, 4),
+        "effective_frac_12B": round(g * 12.0 / HBM_PEAK_GBS, 4)}
+    del lat, obs
+    torch.cuda.empty_cache()
+
+    # batched temperature scan vs per-lattice launches
+    sc = workloads.temperature_scan()
+    n = len(sc["Ls"])
+    sites = sum(L * L for L in sc["Ls"])
+    tune = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+    tile = tune.autotune(20)
+    del tune
+    b = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+    b.set_tile(*tile)
+    nrec = sc["sweeps"] // sc["measure_every"]
+    bobs = torch.empty((n, nrec, 8), dtype=torch.float64, device="cuda")
+    b.sweep(20)
+    ms_b = timed(lambda: b.sweep(sc["sweeps"], sc["measure_every"], out=bobs), stream)
+    g_b = float(sites) * sc["sweeps"] / (ms_b * 1e-3) / 1e9
+    del b, bobs
+    per_sweeps = 1000
+    lats = [xy.Lattice(L, seed=s, beta=bb, delta=d) for L, s, bb, d in
+            zip(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])]
+    for lt in lats:
+        lt.sweep(20)
+
+    def per_lattice():
+        for lt in lats:
+            lt.sweep(per_sweeps, sc["measure_every"])
+    ms_p = timed(per_lattice, stream)
+    g_p = float(sites) * per_sweeps / (ms_p * 1e-3) / 1e9
+    ex["batched_scan_96"] = {
+        "lattices": n, "sites": sites, "sweeps": sc["sweeps"], "tile": list(tile),
+        "batched_gupd_s": round(g_b, 2), "batched_ms": round(ms_b, 2),
+        "per_lattice_gupd_s": round(g_p, 2), "per_lattice_sweeps_timed": per_sweeps,
+        "speedup": round(g_b / g_p, 2)}
+    del lats
+    torch.cuda.empty_cache()
+
+    # FP16 vs FP32 storage at L = 8192
+    pc = workloads.PRECISION
+    res = {}
+    for prec in ("fp32", "fp16"):
+        lt = xy.Lattice(pc["L"], seed=pc["seed"], beta=1.0, delta=pc["delta"], precision=prec)
+        lt.sweep(4)
+        ms_x = timed(lambda: lt.sweep(200, 10), stream)
+        res[prec] = round(float(pc["L"]) ** 2 * 200 / (ms_x * 1e-3) / 1e9, 2)
+        del lt
+    ex["L8192_storage_gupd_s"] = res
+    return ex
+
+
+def cpu_baseline(cfg, sweeps):
+    import oracle
+    L = cfg["L"]
+    th = oracle.hot_start(cfg["seed"], L, "f32")
+    t0 = time.perf_counter()
+    oracle.run(cfg["seed"], th, cfg["beta"], cfg["delta"], sweeps, 0, prec="f32")
+    dt = time.perf_counter() - t0
+    return {"value": round(float(L) * L * sweeps / dt / 1e9, 6), "unit": "Gupd/s", "cores": 1, "kind": "oracle",
+            "sample": "%d sweeps of the L=%d lattice from its hot start (%.1f s on one core)" % (sweeps, L, dt)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * xy.h -- C ABI of the MI355X (gfx950) checkerboard Metropolis library for the
+ * 2-d XY model.
+ *
+ * Model (section 1.2, eq. 1 of Anselmi, Conti, Di Renzo, "GPU computing for 2-d
+ * spin systems: CUDA vs OpenGL", Lattice 2008): H = -J sum_<ij> cos(theta_i -
+ * theta_j) over nearest-neighbour pairs of a periodic L x L square lattice, each
+ * pair counted once, J = 1, Boltzmann weight exp(-beta H).  The paper samples it
+ * with hybrid Monte Carlo; this library runs the same ensemble with
+ * checkerboard single-site Metropolis:
+ *
+ *   one sweep = every red site ((x+y) even), then every black site; a site
+ *   proposes theta' = theta + delta (2 u1 - 1), wrapped into [0, 2 pi), and
+ *   accepts iff u2 < exp(-beta dE), dE = -J sum_nn [cos(theta' - theta_j) -
+ *   cos(theta - theta_j)].
+ *
+ * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed mod 2^32,
+ * seed >> 32), one call per two same-colour sites of a half-row: counter =
+ * (y * P + (k >> 1), sweep, colour, purpose) with k the half-row index and
+ * P = ceil(L/4); words (X0, X1) for even k and (X2, X3) for odd k; u = (2 (w >> 9)
+ * + 1) 2^-24.  Purpose 0 drives the updates, purpose 1 (sweep 0) the hot start
+ * theta = 2 pi u.  The stream depends on (seed, site, sweep) only, so every
+ * schedule, tile shape and batch composition gives the same trajectory bit for
+ * bit, and a run can be resumed from a saved state and sweep counter.
+ *
+ * FP32 proposal arithmetic, rounded exactly as written: step = fl(delta_f * r),
+ * t = fl(theta + step), t < 0 -> fl(t + 2pi_f), t >= 2pi_f -> fl(t - 2pi_f),
+ * with delta_f and 2pi_f the FP32 roundings of delta and 2 pi.  FP16 storage
+ * (XY_FP16) rounds t to IEEE binary16 (nearest-even) before dE is evaluated.
+ * Energies and decisions are FP32 on the device; observables are accumulated
+ * in FP64 (the paper's "global sums of the energy", section 1.2).
+ *
+ * State layout (device memory, owned by the caller): two half-lattices,
+ * colour c = 0 (red) then c = 1 (black), each L rows of L/2 entries, row-major:
+ *     elem(c, y, k) = state[(c * L + y) * (L/2) + k],  x = 2k + ((c + y) & 1),
+ * stored as float (XY_FP32) or IEEE binary16 (XY_FP16), radians in [0, 2 pi).
+ *
+ * Conventions for every function:
+ *   - returns XY_OK (0) or a negative error code; nothing throws or aborts;
+ *   - a handle stays valid after any error;
+ *   - all device memory (state, workspace, observables, debug buffers) belongs
+ *     to the caller and must outlive the handle; the library never allocates
+ *     device memory; host objects (handles, graphs) are freed by *_free;
+ *   - work is enqueued on the caller's HIP stream and the call returns; launch
+ *     and configuration errors are returned at once, asynchronous kernel faults
+ *     surface at the caller's next synchronisation;
+ *   - a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef XY_H
+#define XY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define XY_OK      0
+#define XY_EINVAL (-1)  /* L odd or < 4, L*L >= 2^31, beta not finite or < 0, delta not in (0, pi],
+                           bad precision / start / plan / measure_every, n_sweeps < 0 */
+#define XY_ESIZE  (-2)  /* a buffer is shorter than xy_state_bytes / xy_batch_state_bytes asks */
+#define XY_ERANGE (-3)  /* sweep counter would pass 2^32 - 1 */
+#define XY_EHIP   (-4)  /* a HIP runtime call failed; xy_last_hip_error() names it */
+#define XY_ESTATE (-5)  /* NULL handle, NULL required pointer, or handle already freed */
+#define XY_ENOMEM (-6)  /* host allocation of a handle failed */
+#define XY_EBARRIER (-7) /* a batch barrier wait hit its spin limit: the GPU did not hold every
+                            workgroup of the persistent launch at once; results are invalid */
+
+enum { XY_FP32 = 0, XY_FP16 = 1 };
+enum { XY_HOT = 0, XY_COLD = 1 };
+
+/* One measured configuration: raw FP64 sums over the lattice (64 bytes).
+ *   cx = sum cos(theta(x,y) - theta(x+1,y)),  cy = sum cos(theta(x,y) - theta(x,y+1)),
+ *   ix = sum sin(theta(x,y) - theta(x+1,y)),  iy = sum sin(theta(x,y) - theta(x,y+1)),
+ *   mx = sum cos theta,  my = sum sin theta,
+ *   sweep = sweep counter after the measured sweep, n_accept = accepted proposals in it
+ *   (0 for xy_measure).  Derived: E = -(cx + cy), |m| = hypot(mx, my) / N, helicity
+ *   modulus = (<cx + cy> - beta <ix^2 + iy^2>) / (2N). */
+typedef struct xy_obs {
+    uint64_t sweep;
+    uint64_t n_accept;
+    double cx, cy, ix, iy, mx, my;
+} xy_obs;
+
+/* Execution schedule of a sweep.  The trajectory does not depend on it.
+ *   XY_PLAN_STREAM: two in-place half-sweep launches per sweep (any even L >= 4).
+ *   XY_PLAN_FUSED : one launch per `sweeps_per_pass` sweeps; a workgroup loads a
+ *                   tile_x x tile_y tile plus a halo of 2*sweeps_per_pass sites into
+ *                   LDS, runs the red and black half-sweeps there (recomputing the
+ *                   halo's red sites with their owners' random numbers) and writes
+ *                   the tile to the other buffer of a ping-pong pair.  Needs
+ *                   L % 4 == 0, tile_x % 4 == 0, tile_x | L, tile_y | L.
+ *   XY_PLAN_AUTO  : the tuned plan for (L, precision) if one is cached, else a default. */
+enum { XY_PLAN_AUTO = 0, XY_PLAN_STREAM = 1, XY_PLAN_FUSED = 2 };
+typedef struct xy_plan {
+    int32_t kind;
+    int32_t tile_x;
+    int32_t tile_y;
+    int32_t sweeps_per_pass;   /* 1 or 2 */
+} xy_plan;
+
+typedef struct xy_lattice xy_lattice;
+typedef struct xy_batch xy_batch;
+
+/* Bytes of device memory a lattice needs: *state for the angles (layout above),
+ * *workspace for the ping-pong copy and the reduction partials.  Either output
+ * pointer may be NULL. */
+int xy_state_bytes(int32_t L, int32_t precision, size_t* state, size_t* workspace);
+
+/* Create a lattice on the caller's stream (hipStream_t passed as void*, NULL =
+ * the null stream) and initialise the angles: XY_HOT draws theta = 2 pi u from
+ * the purpose-1 stream (formed in FP64, rounded to the storage format; FP16 via
+ * FP32), XY_COLD sets theta = 0.  The sweep counter starts at 0.
+ * beta >= 0 finite; 0 < delta <= pi. */
+int xy_init(xy_lattice** out, uint64_t seed, int32_t L, double beta, double delta,
+            int32_t start, int32_t precision,
+            void* state_dev, size_t state_len, void* work_dev, size_t work_len,
+            void* hip_stream);
+
+/* Same as xy_init but keeps the angles already in state_dev (a checkpoint) and
+ * sets the sweep counter to `sweep`. */
+int xy_attach(xy_lattice** out, uint64_t seed, int32_t L, double beta, double delta,
+              int32_t precision, uint64_t sweep,
+              void* state_dev, size_t state_len, void* work_dev, size_t work_len,
+              void* hip_stream);
+
+/* Run n_sweeps sweeps from the handle's sweep counter.  If measure_every > 0 and
+ * obs_dev != NULL, after every sweep j (1-based within this call) with
+ * j % measure_every == 0 one xy_obs is written to obs_dev[j / measure_every - 1]
+ * (device memory, floor(n_sweeps / measure_every) records).  On return the
+ * angles are in state_dev. */
+int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs_dev);
+
+/* Measure the current state into obs_dev[0] (device memory). */
+int xy_measure(xy_lattice* h, xy_obs* obs_dev);
+
+int xy_set_params(xy_lattice* h, double beta, double delta);
+int xy_get_sweep(const xy_lattice* h, uint64_t* sweep);
+int xy_set_sweep(xy_lattice* h, uint64_t sweep);
+int xy_set_stream(xy_lattice* h, void* hip_stream);
+int xy_set_plan(xy_lattice* h, const xy_plan* plan);
+int xy_get_plan(const xy_lattice* h, xy_plan* plan);
+int xy_free(xy_lattice* h);
+
+/* Test support: run ONE sweep with the streaming schedule and write, per site in
+ * the state layout (red half then black half), accept_dev[i] = 1/0 and dE_dev[i] =
+ * the FP32 energy change of the proposal.  Either output may be NULL. */
+int xy_debug_sweep(xy_lattice* h, uint8_t* accept_dev, float* dE_dev);
+
+/* Time each candidate plan for `sweeps_per_trial` sweeps (after one untimed
+ * trial) on the handle's stream and select the fastest; *best receives it and
+ * the handle keeps it.  The trials advance the handle's state and counter: run
+ * it on a scratch lattice.  If cache_path != NULL the result is merged into that
+ * JSON file under the key "gfx950/L/precision". */
+int xy_autotune(xy_lattice* h, int32_t sweeps_per_trial, const char* cache_path, xy_plan* best);
+
+/* Look up a tuned plan for (L, precision) in the JSON cache file; XY_EINVAL if
+ * the file or the entry is missing. */
+int xy_tuned_plan(const char* cache_path, int32_t L, int32_t precision, xy_plan* plan);
+
+/* ----------------------------------------------------------------- batches
+ * n lattices of sizes L[i] >= 4, L[i] % 4 == 0 (possibly different), with their own seed,
+ * beta and delta, advanced together by one persistent kernel per call, captured
+ * once into a HIP graph and replayed.  Lattice i's angles start at element
+ * offset sum_{j<i} L[j]^2 of state_dev, in the single-lattice layout.  A lattice
+ * follows exactly the trajectory it would follow alone with the same seed. */
+int xy_batch_state_bytes(int32_t n, const int32_t* L, int32_t precision,
+                         size_t* state, size_t* workspace);
+int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_t* L,
+                  const double* beta, const double* delta, int32_t start, int32_t precision,
+                  void* state_dev, size_t state_len, void* work_dev, size_t work_len,
+                  void* hip_stream);
+/* obs_dev: n * floor(n_sweeps / measure_every) records, lattice-major
+ * (record r of lattice i at obs_dev[i * n_rec + r]). */
+int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs* obs_dev);
+int xy_batch_get_sweep(const xy_batch* b, uint64_t* sweep);
+/* Tile shape of the batch's work list (every L[i] is a multiple of it).  The
+ * shape does not change the trajectory.  xy_batch_set_tile: XY_EINVAL if the
+ * shape is not one of the batch's candidates (64x32, 64x16, 32x16 when every L
+ * allows; else the largest of 16x16, 8x8, 4x4 that divides every L). */
+int xy_batch_set_tile(xy_batch* b, int32_t tile_x, int32_t tile_y);
+int xy_batch_get_tile(const xy_batch* b, int32_t* tile_x, int32_t* tile_y);
+/* Time every candidate tile shape for `sweeps_per_trial` sweeps (after one
+ * untimed trial that also captures the graph) and keep the fastest.  The trials
+ * advance the batch: run it on a scratch batch of the same sizes. */
+int xy_batch_autotune(xy_batch* b, int32_t sweeps_per_trial, int32_t* tile_x, int32_t* tile_y);
+/* Wait for the batch's stream and report whether any launch so far hit a barrier
+ * spin limit (XY_EBARRIER) -- a guard for GPUs shared with other work. */
+int xy_batch_status(xy_batch* b);
+int xy_batch_free(xy_batch* b);
+
+const char* xy_strerror(int code);
+/* Name of the last failing HIP call and its error string (thread-local). */
+const char* xy_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XY_H */

@@ -77,6 +77,12 @@ def lib():
         L.orc_clock_run.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64, i32p, dp]
         L.orc_clock_run.restype = ctypes.c_int64
+        L.orc_site_update_explicit.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_uint32, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, dp, dp, dp, dp, dp]
+        L.orc_site_update_explicit.restype = ctypes.c_int
+        L.orc_hot_start_site.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_hot_start_site.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -180,3 +186,20 @@ def clock_sweep(seed: int, ks: np.ndarray, q: int, beta: float, sweep_index: int
     L = ks.shape[0]
     return lib().orc_clock_sweep(seed, L, q, beta, sweep_index,
                                  ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+
+
+def hot_start_site(seed: int, L: int, x: int, y: int, prec="f64") -> float:
+    """Hot-start angle of site (x, y), without building the whole lattice."""
+    return lib().orc_hot_start_site(seed, L, x, y, _prec(prec))
+
+
+def site_update(seed: int, L: int, x: int, y: int, sweep_index: int, beta: float, delta: float,
+                theta: float, neighbours, prec="f64"):
+    """One Metropolis update of site (x, y) from explicit inputs (its angle and its
+    four neighbours).  Returns (new angle, accepted, dE, threshold T, proposal)."""
+    nb = np.ascontiguousarray(np.asarray(neighbours, dtype=np.float64).reshape(4))
+    out = np.zeros(4, dtype=np.float64)
+    acc = lib().orc_site_update_explicit(seed, L, x, y, sweep_index, _prec(prec), float(beta), float(delta),
+                                         float(theta), _dp(nb), _dp(out[0:]), _dp(out[1:]), _dp(out[2:]),
+                                         _dp(out[3:]))
+    return float(out[0]), bool(acc), float(out[1]), float(out[2]), float(out[3])

@@ -169,20 +169,25 @@ double orc_propose(double theta, double delta, double u1, int prec)
  * Initial states.
  * ------------------------------------------------------------------------- */
 
+/* Hot-start angle of one site (the value orc_hot_start stores there). */
+double orc_hot_start_site(uint64_t seed, int L, int x, int y, int prec)
+{
+    uint32_t w[2];
+    orc_site_words(seed, L, x, y, 0u, 1u, w);
+    double t = 2.0 * ORC_PI * orc_u01(w[0]);
+    if (prec == ORC_PREC_F16) t = orc_round_f16((double)(float)t);
+    else if (prec == ORC_PREC_F32) t = (double)(float)t;
+    return t;
+}
+
 /* Hot start: theta = 2 pi u(X_a) from the purpose-1 stream of sweep 0,
  * formed in FP64 and then rounded to the storage format (FP16 storage goes
  * through FP32 first). */
 void orc_hot_start(uint64_t seed, int L, int prec, double* theta)
 {
     for (int y = 0; y < L; ++y)
-        for (int x = 0; x < L; ++x) {
-            uint32_t w[2];
-            orc_site_words(seed, L, x, y, 0u, 1u, w);
-            double t = 2.0 * ORC_PI * orc_u01(w[0]);
-            if (prec == ORC_PREC_F16) t = orc_round_f16((double)(float)t);
-            else if (prec == ORC_PREC_F32) t = (double)(float)t;
-            theta[y * L + x] = t;
-        }
+        for (int x = 0; x < L; ++x)
+            theta[y * L + x] = orc_hot_start_site(seed, L, x, y, prec);
 }
 
 /* ---------------------------------------------------------------------------
@@ -221,33 +226,42 @@ double orc_energy(int L, const double* theta)
 }
 
 /* ---------------------------------------------------------------------------
- * One Metropolis site update.  dE = -J sum_nn [cos(theta' - theta_j) -
- * cos(theta - theta_j)]; accept iff u2 < exp(-beta dE).  Optional per-site
- * outputs: dE, the threshold T = -ln(u2)/beta (decision is dE < T), and the
- * decision itself.
+ * One Metropolis site update from explicit inputs: the site's angle t_old and
+ * its four neighbours nb[] (any order).  dE = -J sum_nn [cos(theta' - theta_j)
+ * - cos(theta - theta_j)]; accept iff u2 < exp(-beta dE).  Writes the angle the
+ * site holds afterwards, and optionally dE, the threshold T = -ln(u2)/beta (the
+ * decision is dE < T), and the proposal.  Returns 1 if accepted.
  * ------------------------------------------------------------------------- */
-static int site_update(uint64_t seed, int L, double beta, double delta, uint32_t sweep,
-                       int prec, double* theta, int x, int y,
-                       double* dE_out, double* thr_out, uint8_t* dec_out, double* prop_out)
+int orc_site_update_explicit(uint64_t seed, int L, int x, int y, uint32_t sweep, int prec,
+                             double beta, double delta, double t_old, const double nb[4],
+                             double* t_out, double* dE_out, double* thr_out, double* prop_out)
 {
     uint32_t w[2];
     orc_site_words(seed, L, x, y, sweep, 0u, w);
     double u1 = orc_u01(w[0]);
     double u2 = orc_u01(w[1]);
-    double t_old = theta[y * L + x];
     double t_new = orc_propose(t_old, delta, u1, prec);
-    int xl = (x + L - 1) % L, xr = (x + 1) % L;
-    int yu = (y + L - 1) % L, yd = (y + 1) % L;
-    double nb[4] = { theta[y * L + xl], theta[y * L + xr], theta[yu * L + x], theta[yd * L + x] };
     double dE = 0.0;
     for (int j = 0; j < 4; ++j)
         dE -= cos(t_new - nb[j]) - cos(t_old - nb[j]);
     int accept = u2 < exp(-beta * dE);
     if (dE_out) *dE_out = dE;
     if (thr_out) *thr_out = (beta > 0.0) ? -log(u2) / beta : INFINITY;
-    if (dec_out) *dec_out = (uint8_t)accept;
     if (prop_out) *prop_out = t_new;
-    if (accept) theta[y * L + x] = t_new;
+    *t_out = accept ? t_new : t_old;
+    return accept;
+}
+
+static int site_update(uint64_t seed, int L, double beta, double delta, uint32_t sweep,
+                       int prec, double* theta, int x, int y,
+                       double* dE_out, double* thr_out, uint8_t* dec_out, double* prop_out)
+{
+    int xl = (x + L - 1) % L, xr = (x + 1) % L;
+    int yu = (y + L - 1) % L, yd = (y + 1) % L;
+    double nb[4] = { theta[y * L + xl], theta[y * L + xr], theta[yu * L + x], theta[yd * L + x] };
+    int accept = orc_site_update_explicit(seed, L, x, y, sweep, prec, beta, delta, theta[y * L + x],
+                                          nb, &theta[y * L + x], dE_out, thr_out, prop_out);
+    if (dec_out) *dec_out = (uint8_t)accept;
     return accept;
 }
 

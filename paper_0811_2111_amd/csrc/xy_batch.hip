@@ -1,0 +1,626 @@
+// xy_batch.hip -- many lattices of uneven size and temperature in one persistent launch.
+//
+// The replicas of the paper's GLSL variant (four lattices, possibly at different
+// temperatures, in one RGBA texture, section 3.2) and its remark that the device
+// must be "sufficiently filled" motivate running a whole temperature scan as one
+// launch: small lattices alone cannot fill 256 CUs.
+//
+// Work list: every lattice is cut into TX x TY tiles; the tiles of all lattices,
+// lattice by lattice, form one list that is split into contiguous ranges, one per
+// workgroup.  The grid never exceeds what the GPU holds at once, so every
+// workgroup is resident and the per-lattice barriers below cannot deadlock.
+// One pass = one fused sweep of a tile (state -> ping-pong or back).  Before a
+// workgroup starts pass p on a lattice it waits until every workgroup that owns
+// tiles of that lattice has finished pass p-1 (an epoch counter per lattice),
+// which orders both the new reads after the old writes and the new writes after
+// the old halo reads.  Lattices never wait for each other.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "xy.h"
+#include "xy_launch.hpp"
+#include "xy_runtime.hpp"
+#include "xy_tile.hpp"
+
+using namespace xyd;
+
+namespace xyb {
+
+struct LatDesc {
+    long long off;        // element offset of the lattice in the state buffer
+    int L;
+    int tiles_x;
+    int first_tile;
+    int ntiles;
+    int arrivals;         // workgroups owning tiles of this lattice
+    int reducer;          // workgroup that reduces this lattice's measurements
+    uint32_t key0, key1;
+    float delta, nbl2e;
+};
+
+struct Ctrl {
+    uint32_t sweep0;      // absolute sweep index of the next pass (advanced by k_batch_advance)
+    uint32_t timed_out;   // set if a barrier wait gave up (never cleared by the kernel)
+    uint32_t pad[62];
+};
+
+// Spin limit of one barrier wait: 2^27 polls with s_sleep 2 (~128 cycles each),
+// several seconds at 2.4 GHz, far beyond any legitimate wait.  A wait that gives
+// up flags ctrl->timed_out and lets the workgroup run on, so every wave exits.
+static constexpr unsigned kSpinLimit = 1u << 27;
+
+// barrier wait: spin until *ctr >= target (agent-scope acquire)
+__device__ __forceinline__ void wait_at_least(unsigned* ctr, unsigned target, Ctrl* ctrl)
+{
+    if (threadIdx.x == 0) {
+        unsigned spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins == kSpinLimit) {
+                __hip_atomic_store(&ctrl->timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void arrive(unsigned* ctr)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int lattice_of(const LatDesc* d, int n, int tile)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d[mid].first_tile <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Reduce the partials of lattice i for one measured pass (fixed order) into its record.
+template <int NT>
+__device__ void reduce_lattice(const LatDesc& d, const double* part, xy_obs* out, uint64_t sweep_after, double* red)
+{
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int t = threadIdx.x; t < d.ntiles; t += NT) {
+        const double* q = part + (size_t)(d.first_tile + t) * 8;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) v[k] += q[k];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 7; ++k) red[wid * 7 + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s[7];
+        for (int k = 0; k < 7; ++k) {
+            s[k] = 0.0;
+            for (int w = 0; w < NT / 64; ++w) s[k] += red[w * 7 + k];
+        }
+        xy_obs o;
+        o.sweep = sweep_after;
+        o.n_accept = (uint64_t)s[6];
+        o.cx = s[0]; o.cy = s[1]; o.ix = s[2]; o.iy = s[3]; o.mx = s[4]; o.my = s[5];
+        *out = o;
+    }
+    __syncthreads();
+}
+
+template <typename T, int TX, int TY, int NT>
+__global__ void __launch_bounds__(NT)
+k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ lat, int nlat, int total_tiles,
+        unsigned* __restrict__ bar, Ctrl* __restrict__ ctrl, int npass, int measure_every,
+        double* __restrict__ part /* [2][total_tiles][8] */, xy_obs* __restrict__ obs, int nrec)
+{
+    extern __shared__ __align__(16) char smem[];
+    using S = TileShape<TX, TY, 1, NT>;
+    double* red = (double*)(smem + S::lds_bytes);   // 7 doubles per wave, after the tile's LDS
+    const int G = gridDim.x, w = blockIdx.x;
+    const int t0 = (int)((long long)total_tiles * w / G);
+    const int t1 = (int)((long long)total_tiles * (w + 1) / G);
+    const uint32_t sweep0 = ctrl->sweep0;
+    const int ilo = t1 > t0 ? lattice_of(lat, nlat, t0) : 0;
+    const int ihi = t1 > t0 ? lattice_of(lat, nlat, t1 - 1) : -1;
+    // measured passes: pass p is measured if (p + 1) % measure_every == 0
+    auto measured = [&](int p) { return measure_every > 0 && obs != nullptr && ((p + 1) % measure_every) == 0; };
+
+    for (int p = 0; p < npass; ++p) {
+        T* src = (p & 1) ? pp : state;
+        T* dst = (p & 1) ? state : pp;
+        const bool meas = measured(p);
+        double* pslot = part + (size_t)((p / (measure_every > 0 ? measure_every : 1)) & 1) * total_tiles * 8;
+        for (int i = ilo; i <= ihi; ++i) {
+            const LatDesc d = lat[i];
+            if (p > 0) {
+                wait_at_least(&bar[i], (unsigned)p * (unsigned)d.arrivals, ctrl);
+                // measurement of pass p-1 is complete: the reducer writes its record
+                if (measured(p - 1) && d.reducer == w) {
+                    const int r = p / measure_every - 1;
+                    const double* prev = part + (size_t)(((p - 1) / measure_every) & 1) * total_tiles * 8;
+                    reduce_lattice<NT>(d, prev, obs + (size_t)i * nrec + r, (uint64_t)sweep0 + (uint64_t)p, red);
+                }
+            }
+            const int a = max(t0, d.first_tile), b = min(t1, d.first_tile + d.ntiles);
+            const Params prm{d.delta, 6.283185307179586f, d.nbl2e};
+            for (int t = a; t < b; ++t) {
+                const int lt = t - d.first_tile;
+                const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
+                tile_program<T, TX, TY, 1, NT>(src + d.off, dst + d.off, d.L, tx * TX, ty * TY, sweep0 + (uint32_t)p,
+                                               d.key0, d.key1, prm, meas ? 1u : 0u, pslot + (size_t)t * 8, 0, smem,
+                                               red);
+            }
+        }
+        for (int i = ilo; i <= ihi; ++i) arrive(&bar[i]);
+    }
+
+    // Epilogue: wait for the last pass, write the last record, and if the pass
+    // count is odd copy this workgroup's tiles back into the caller's buffer.
+    if (npass > 0) {
+        for (int i = ilo; i <= ihi; ++i) {
+            const LatDesc d = lat[i];
+            wait_at_least(&bar[i], (unsigned)npass * (unsigned)d.arrivals, ctrl);
+            if (measured(npass - 1) && d.reducer == w) {
+                const int r = npass / measure_every - 1;
+                const double* prev = part + (size_t)(((npass - 1) / measure_every) & 1) * total_tiles * 8;
+                reduce_lattice<NT>(d, prev, obs + (size_t)i * nrec + r, (uint64_t)sweep0 + (uint64_t)npass, red);
+            }
+            if (npass & 1) {
+                const int a = max(t0, d.first_tile), b = min(t1, d.first_tile + d.ntiles);
+                const int Hh = d.L >> 1;
+                for (int t = a; t < b; ++t) {
+                    const int lt = t - d.first_tile;
+                    const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
+                    for (int idx = threadIdx.x; idx < 2 * TY * (TX / 2); idx += NT) {
+                        const int c = idx / (TY * (TX / 2));
+                        const int rem = idx - c * (TY * (TX / 2));
+                        const int rr = rem / (TX / 2), k = rem - rr * (TX / 2);
+                        const size_t e = (size_t)d.off + ((size_t)c * d.L + ty * TY + rr) * Hh + tx * (TX / 2) + k;
+                        state[e] = pp[e];
+                    }
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_batch_advance(Ctrl* ctrl, uint32_t n) { ctrl->sweep0 += n; }
+
+__global__ void k_zero_u32(unsigned* p, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+__global__ void k_set_sweep(Ctrl* ctrl, uint32_t v)
+{
+    ctrl->sweep0 = v;
+    ctrl->timed_out = 0u;
+}
+
+}  // namespace xyb
+
+// ===================================================================== host side
+namespace xyb {
+
+struct Shape {
+    int tx, ty;
+};
+// Batch tile shapes, largest first.  Shapes of at least 512 sites are preferred;
+// the small ones exist so that any batch of L % 4 == 0 lattices can run.
+static const Shape kShapes[] = {{64, 32}, {64, 16}, {32, 16}, {16, 16}, {8, 8}, {4, 4}};
+static constexpr int kNT = 256;
+
+static std::vector<Shape> candidates(int n, const int32_t* L)
+{
+    std::vector<Shape> big, all;
+    for (const Shape& s : kShapes) {
+        bool ok = true;
+        for (int i = 0; i < n && ok; ++i) ok = (L[i] % s.tx == 0) && (L[i] % s.ty == 0);
+        if (!ok) continue;
+        all.push_back(s);
+        if (s.tx * s.ty >= 512) big.push_back(s);
+    }
+    if (!big.empty()) return big;
+    if (!all.empty()) return {all.front()};
+    return {};
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, part_off, total;
+    long long max_tiles;
+};
+
+static Layout layout(int n, const int32_t* L, int precision)
+{
+    Layout lo{};
+    const size_t elem = precision == XY_FP16 ? 2 : 4;
+    long long sites = 0;
+    for (int i = 0; i < n; ++i) sites += (long long)L[i] * L[i];
+    lo.state_bytes = (size_t)sites * elem;
+    std::vector<Shape> c = candidates(n, L);
+    int min_area = 1 << 30;
+    for (const Shape& s : c) min_area = std::min(min_area, s.tx * s.ty);
+    lo.max_tiles = c.empty() ? 0 : sites / min_area;
+    lo.pp_off = 0;
+    lo.ctrl_off = align256(lo.state_bytes);
+    lo.bar_off = lo.ctrl_off + 256;
+    lo.desc_off = align256(lo.bar_off + (size_t)n * sizeof(unsigned));
+    lo.part_off = align256(lo.desc_off + (size_t)n * sizeof(LatDesc));
+    lo.total = lo.part_off + (size_t)2 * lo.max_tiles * 8 * sizeof(double);
+    return lo;
+}
+
+template <typename T, int TX, int TY>
+static void* kernel_ptr()
+{
+    return (void*)k_batch<T, TX, TY, kNT>;
+}
+
+static void* batch_kernel(int precision, Shape s, size_t* lds)
+{
+#define XYB_CASE(TXV, TYV)                                                                         \
+    if (s.tx == TXV && s.ty == TYV) {                                                              \
+        *lds = TileShape<TXV, TYV, 1, kNT>::lds_bytes + TileShape<TXV, TYV, 1, kNT>::red_bytes;    \
+        return precision == XY_FP16 ? kernel_ptr<__half, TXV, TYV>() : kernel_ptr<float, TXV, TYV>(); \
+    }
+    XYB_CASE(64, 32)
+    XYB_CASE(64, 16)
+    XYB_CASE(32, 16)
+    XYB_CASE(16, 16)
+    XYB_CASE(8, 8)
+    XYB_CASE(4, 4)
+#undef XYB_CASE
+    return nullptr;
+}
+
+}  // namespace xyb
+
+using namespace xyb;
+
+static const uint32_t kBatchMagic = 0x58594254u;  // "XYBT"
+
+struct xy_batch {
+    uint32_t magic;
+    int n;
+    std::vector<int32_t> L;
+    std::vector<uint64_t> seed;
+    std::vector<double> beta, delta;
+    int precision;
+    char* state;
+    char* work;
+    size_t state_len, work_len;
+    hipStream_t stream;
+    hipStream_t cap;       // private stream used only for graph capture
+    uint64_t sweep;
+    Layout lo;
+    Shape shape;
+    int grid;
+    int total_tiles;
+    std::vector<LatDesc> desc;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int64_t g_n;
+    int32_t g_me;
+    xy_obs* g_obs;
+    int g_grid;
+};
+
+static bool blive(const xy_batch* b) { return b && b->magic == kBatchMagic; }
+
+static void drop_graph(xy_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Plan the work list for shape s: tiles per lattice, grid size (all workgroups
+// resident), contiguous tile ranges, barrier arrival counts and reducers.
+static int plan_batch(xy_batch* b, Shape s)
+{
+    size_t lds = 0;
+    void* k = batch_kernel(b->precision, s, &lds);
+    if (!k) return XY_EINVAL;
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return xyr::hip_fail(e, "hipFuncSetAttribute");
+    int dev = 0, cus = 0, per_cu = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return xyr::hip_fail(e, "hipGetDevice");
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+        return xyr::hip_fail(e, "hipDeviceGetAttribute");
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kNT, lds)) != hipSuccess)
+        return xyr::hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+    if (per_cu < 1) return XY_EINVAL;
+    int total = 0;
+    b->desc.assign(b->n, LatDesc{});
+    long long off = 0;
+    for (int i = 0; i < b->n; ++i) {
+        LatDesc& d = b->desc[i];
+        d.off = off;
+        d.L = b->L[i];
+        d.tiles_x = d.L / s.tx;
+        d.first_tile = total;
+        d.ntiles = (d.L / s.tx) * (d.L / s.ty);
+        xyk::SweepArgs a = xyr::sweep_args(b->seed[i], d.L, b->precision, b->beta[i], b->delta[i]);
+        d.key0 = a.key0;
+        d.key1 = a.key1;
+        d.delta = a.delta;
+        d.nbl2e = a.nbl2e;
+        total += d.ntiles;
+        off += (long long)d.L * d.L;
+    }
+    if ((long long)total > b->lo.max_tiles) return XY_EINVAL;
+    // every workgroup must be resident at once for the barriers; keep a margin of
+    // one resident slot in ten in case part of the GPU is busy with other work
+    const int G = std::max(1, std::min(total, std::max(1, cus * per_cu * 9 / 10)));
+    for (int i = 0; i < b->n; ++i) {
+        LatDesc& d = b->desc[i];
+        // workgroups w with [t0(w), t1(w)) intersecting [first, first + ntiles)
+        int wlo = -1, whi = -1;
+        for (int w = 0; w < G; ++w) {
+            const long long t0 = (long long)total * w / G, t1 = (long long)total * (w + 1) / G;
+            if (t1 <= t0) continue;
+            if (t0 < d.first_tile + d.ntiles && t1 > d.first_tile) {
+                if (wlo < 0) wlo = w;
+                whi = w;
+            }
+        }
+        d.arrivals = whi - wlo + 1;
+        d.reducer = wlo;
+    }
+    b->shape = s;
+    b->grid = G;
+    b->total_tiles = total;
+    e = hipMemcpyAsync(b->work + b->lo.desc_off, b->desc.data(), sizeof(LatDesc) * b->n, hipMemcpyHostToDevice,
+                       b->stream);
+    if (e != hipSuccess) return xyr::hip_fail(e, "hipMemcpyAsync(desc)");
+    if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return xyr::hip_fail(e, "hipStreamSynchronize");
+    drop_graph(b);
+    return XY_OK;
+}
+
+static hipError_t enqueue_batch(xy_batch* b, hipStream_t s, int npass, int32_t me, xy_obs* obs)
+{
+    size_t lds = 0;
+    void* k = batch_kernel(b->precision, b->shape, &lds);
+    unsigned* bar = (unsigned*)(b->work + b->lo.bar_off);
+    Ctrl* ctrl = (Ctrl*)(b->work + b->lo.ctrl_off);
+    const LatDesc* desc = (const LatDesc*)(b->work + b->lo.desc_off);
+    double* part = (double*)(b->work + b->lo.part_off);
+    const int nrec = me > 0 ? npass / me : 0;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, bar, b->n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void* pp = b->work + b->lo.pp_off;
+    void* st = b->state;
+    int nlat = b->n, tt = b->total_tiles;
+    void* args[] = {&st, &pp, &desc, &nlat, &tt, &bar, &ctrl, &npass, &me, &part, &obs, (void*)&nrec};
+    e = hipLaunchKernel(k, dim3(b->grid), dim3(kNT), args, lds, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(1), 0, s, ctrl, (uint32_t)npass);
+    return hipGetLastError();
+}
+
+extern "C" {
+
+int xy_batch_state_bytes(int32_t n, const int32_t* L, int32_t precision, size_t* state, size_t* workspace)
+{
+    if (n <= 0 || !L || (precision != XY_FP32 && precision != XY_FP16)) return XY_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!xyr::valid_L(L[i]) || L[i] % 4 != 0) return XY_EINVAL;
+    if (candidates(n, L).empty()) return XY_EINVAL;
+    Layout lo = layout(n, L, precision);
+    if (state) *state = lo.state_bytes;
+    if (workspace) *workspace = lo.total;
+    return XY_OK;
+}
+
+int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_t* L, const double* beta,
+                  const double* delta, int32_t start, int32_t precision, void* state_dev, size_t state_len,
+                  void* work_dev, size_t work_len, void* hip_stream)
+{
+    if (!out) return XY_ESTATE;
+    *out = nullptr;
+    if (!seeds || !L || !beta || !delta) return XY_ESTATE;
+    size_t need_s = 0, need_w = 0;
+    int rc = xy_batch_state_bytes(n, L, precision, &need_s, &need_w);
+    if (rc != XY_OK) return rc;
+    if (start != XY_HOT && start != XY_COLD) return XY_EINVAL;
+    for (int i = 0; i < n; ++i)
+        if (!xyr::valid_beta_delta(beta[i], delta[i])) return XY_EINVAL;
+    if (!state_dev || !work_dev) return XY_ESTATE;
+    if (state_len < need_s || work_len < need_w) return XY_ESIZE;
+    xy_batch* b = new (std::nothrow) xy_batch;
+    if (!b) return XY_ENOMEM;
+    b->magic = kBatchMagic;
+    b->n = n;
+    b->L.assign(L, L + n);
+    b->seed.assign(seeds, seeds + n);
+    b->beta.assign(beta, beta + n);
+    b->delta.assign(delta, delta + n);
+    b->precision = precision;
+    b->state = (char*)state_dev;
+    b->work = (char*)work_dev;
+    b->state_len = state_len;
+    b->work_len = work_len;
+    b->stream = (hipStream_t)hip_stream;
+    b->cap = nullptr;
+    b->sweep = 0;
+    b->lo = layout(n, L, precision);
+    b->graph = nullptr;
+    b->exec = nullptr;
+    b->g_n = -1;
+    b->g_me = -1;
+    b->g_obs = nullptr;
+    b->g_grid = 0;
+    auto fail = [&](int code) {
+        drop_graph(b);
+        if (b->cap) (void)hipStreamDestroy(b->cap);
+        b->magic = 0;
+        delete b;
+        return code;
+    };
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        b->cap = nullptr;
+        return fail(xyr::hip_fail(e, "hipStreamCreate"));
+    }
+    rc = plan_batch(b, candidates(n, L).front());
+    if (rc != XY_OK) return fail(rc);
+    for (int i = 0; i < n; ++i) {
+        const size_t eb = precision == XY_FP16 ? 2 : 4;
+        e = xyk::launch_init(b->state + b->desc[i].off * eb, L[i], precision, (uint32_t)(seeds[i] & 0xffffffffu),
+                             (uint32_t)(seeds[i] >> 32), start == XY_HOT, b->stream);
+        if (e != hipSuccess) return fail(xyr::hip_fail(e, "xy_batch_init: launch"));
+    }
+    hipLaunchKernelGGL(k_set_sweep, dim3(1), dim3(1), 0, b->stream, (Ctrl*)(b->work + b->lo.ctrl_off), 0u);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(xyr::hip_fail(e, "xy_batch_init: launch"));
+    *out = b;
+    return XY_OK;
+}
+
+int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs* obs_dev)
+{
+    if (!blive(b)) return XY_ESTATE;
+    if (n_sweeps < 0 || measure_every < 0) return XY_EINVAL;
+    if (b->sweep + (uint64_t)n_sweeps >= 0xffffffffull) return XY_ERANGE;
+    if (n_sweeps == 0) return XY_OK;
+    // barrier targets are pass * arrivals in 32 bits: split very long calls
+    int max_arr = 1;
+    for (const LatDesc& d : b->desc) max_arr = std::max(max_arr, d.arrivals);
+    const int64_t chunk = std::max<int64_t>(1, (int64_t)(0xffffffffu / (unsigned)max_arr) - 1);
+    if (n_sweeps > chunk) {
+        if (measure_every > 0 && obs_dev) return XY_EINVAL;  // records would be split across calls
+        for (int64_t done = 0; done < n_sweeps;) {
+            const int64_t m = std::min(chunk, n_sweeps - done);
+            int rc = xy_batch_sweep(b, m, 0, nullptr);
+            if (rc != XY_OK) return rc;
+            done += m;
+        }
+        return XY_OK;
+    }
+    const int32_t me = (obs_dev && measure_every > 0) ? measure_every : 0;
+    xy_obs* obs = me ? obs_dev : nullptr;
+    hipError_t e;
+    if (!b->exec || b->g_n != n_sweeps || b->g_me != me || b->g_obs != obs || b->g_grid != b->grid) {
+        drop_graph(b);
+        if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return xyr::hip_fail(e, "hipStreamBeginCapture");
+        hipError_t le = enqueue_batch(b, b->cap, (int)n_sweeps, me, obs);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return xyr::hip_fail(le, "batch launch (capture)");
+        }
+        if (e != hipSuccess) return xyr::hip_fail(e, "hipStreamEndCapture");
+        b->graph = g;
+        if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            b->exec = nullptr;
+            drop_graph(b);
+            return xyr::hip_fail(e, "hipGraphInstantiate");
+        }
+        b->g_n = n_sweeps;
+        b->g_me = me;
+        b->g_obs = obs;
+        b->g_grid = b->grid;
+    }
+    if ((e = hipGraphLaunch(b->exec, b->stream)) != hipSuccess) return xyr::hip_fail(e, "hipGraphLaunch");
+    b->sweep += (uint64_t)n_sweeps;
+    return XY_OK;
+}
+
+int xy_batch_get_sweep(const xy_batch* b, uint64_t* sweep)
+{
+    if (!blive(b) || !sweep) return XY_ESTATE;
+    *sweep = b->sweep;
+    return XY_OK;
+}
+
+int xy_batch_autotune(xy_batch* b, int32_t sweeps_per_trial, int32_t* tile_x, int32_t* tile_y)
+{
+    if (!blive(b)) return XY_ESTATE;
+    if (sweeps_per_trial < 2) return XY_EINVAL;
+    std::vector<Shape> cands = candidates(b->n, b->L.data());
+    hipEvent_t e0, e1;
+    hipError_t e;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return xyr::hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return xyr::hip_fail(e, "hipEventCreate");
+    }
+    double best = 1e300;
+    Shape bs = b->shape;
+    int rc = XY_OK;
+    for (const Shape& s : cands) {
+        if ((rc = plan_batch(b, s)) != XY_OK) break;
+        if ((rc = xy_batch_sweep(b, sweeps_per_trial, 0, nullptr)) != XY_OK) break;   // warm-up, capture
+        if ((e = hipEventRecord(e0, b->stream)) != hipSuccess) { rc = xyr::hip_fail(e, "hipEventRecord"); break; }
+        if ((rc = xy_batch_sweep(b, sweeps_per_trial, 0, nullptr)) != XY_OK) break;
+        if ((e = hipEventRecord(e1, b->stream)) != hipSuccess) { rc = xyr::hip_fail(e, "hipEventRecord"); break; }
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) { rc = xyr::hip_fail(e, "hipEventSynchronize"); break; }
+        float ms = 0.f;
+        if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) { rc = xyr::hip_fail(e, "hipEventElapsedTime"); break; }
+        if (ms < best) {
+            best = ms;
+            bs = s;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != XY_OK) return rc;
+    if ((rc = plan_batch(b, bs)) != XY_OK) return rc;
+    if (tile_x) *tile_x = bs.tx;
+    if (tile_y) *tile_y = bs.ty;
+    return XY_OK;
+}
+
+int xy_batch_set_tile(xy_batch* b, int32_t tile_x, int32_t tile_y)
+{
+    if (!blive(b)) return XY_ESTATE;
+    for (const Shape& s : candidates(b->n, b->L.data()))
+        if (s.tx == tile_x && s.ty == tile_y) return plan_batch(b, s);
+    return XY_EINVAL;
+}
+
+int xy_batch_get_tile(const xy_batch* b, int32_t* tile_x, int32_t* tile_y)
+{
+    if (!blive(b)) return XY_ESTATE;
+    if (tile_x) *tile_x = b->shape.tx;
+    if (tile_y) *tile_y = b->shape.ty;
+    return XY_OK;
+}
+
+int xy_batch_status(xy_batch* b)
+{
+    if (!blive(b)) return XY_ESTATE;
+    Ctrl c;
+    hipError_t e = hipMemcpyAsync(&c, b->work + b->lo.ctrl_off, sizeof(Ctrl), hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return xyr::hip_fail(e, "xy_batch_status");
+    return c.timed_out ? XY_EBARRIER : XY_OK;
+}
+
+int xy_batch_free(xy_batch* b)
+{
+    if (!blive(b)) return XY_ESTATE;
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    b->magic = 0;
+    delete b;
+    return XY_OK;
+}
+
+}  // extern "C"

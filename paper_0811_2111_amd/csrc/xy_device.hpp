@@ -1,0 +1,152 @@
+// xy_device.hpp -- device-side building blocks shared by every sweep kernel.
+//
+// Every kernel updates a site through xy_site_update() below, with the
+// neighbour sums formed in one fixed order, so the trajectory is bitwise the
+// same whatever kernel, tile shape or batch runs it.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xyd {
+
+// --------------------------------------------------------------- Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): ten rounds of two 32x32->64 products of
+// words 0 and 2 with the round multipliers, high halves mixed into the other
+// words with the key, key advanced by the Weyl increments between rounds.
+// Uniform counter words and keys stay in scalar registers; on gfx950 each
+// round costs two v_mad_u64_u32 and four v_xor_b32 on the per-lane words.
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n1 = (uint32_t)p1;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// u = (2 (w >> 9) + 1) 2^-24, exact in FP32.
+__device__ __forceinline__ float u01(uint32_t w)
+{
+    return (float)(((w >> 9) << 1) | 1u) * 0x1p-24f;
+}
+
+// 2u - 1 = (2 (w >> 9) + 1 - 2^23) 2^-23, exact in FP32.
+__device__ __forceinline__ float sym11(uint32_t w)
+{
+    return (float)((int32_t)(((w >> 9) << 1) | 1u) - 0x800000) * 0x1p-23f;
+}
+
+// ------------------------------------------------------------- sin / cos / exp
+// theta is always in [0, 2 pi_f), so the hardware transcendental unit, which
+// takes its argument in revolutions, needs no range reduction.
+__device__ __forceinline__ void sincos_rev(float theta, float& s, float& c)
+{
+    const float rev = __fmul_rn(theta, 0.159154943091895335768883763372514362f);
+    s = __builtin_amdgcn_sinf(rev);
+    c = __builtin_amdgcn_cosf(rev);
+}
+
+// ------------------------------------------------------------------- storage
+template <typename T> struct store;
+template <> struct store<float> {
+    static __device__ __forceinline__ float ld(float v) { return v; }
+    static __device__ __forceinline__ float st(float v) { return v; }
+    // value as it will be stored (FP32: unchanged)
+    static __device__ __forceinline__ float rnd(float v) { return v; }
+};
+template <> struct store<__half> {
+    static __device__ __forceinline__ float ld(__half v) { return __half2float(v); }
+    static __device__ __forceinline__ __half st(float v) { return __float2half_rn(v); }
+    static __device__ __forceinline__ float rnd(float v) { return __half2float(__float2half_rn(v)); }
+};
+
+struct Params {
+    float delta;    // FP32 rounding of delta
+    float two_pi;   // FP32 rounding of 2 pi
+    float nbl2e;    // -beta * log2(e), FP32
+};
+
+// One Metropolis update.  (c, s) = (cos, sin) of theta; (sx, sy) = sums of
+// the four neighbours' (cos, sin), formed by the caller as (left + right) +
+// (up + down).  w1 drives the proposal, w2 the acceptance.  Returns 1 if the
+// proposal is accepted; the new angle and its (cos, sin) come back in th, c, s.
+template <typename T>
+__device__ __forceinline__ int site_update(float& th, float& c, float& s, float sx, float sy,
+                                           uint32_t w1, uint32_t w2, const Params& p,
+                                           float* dE_out = nullptr)
+{
+    const float step = __fmul_rn(p.delta, sym11(w1));
+    float t = __fadd_rn(th, step);
+    if (t < 0.0f) t = __fadd_rn(t, p.two_pi);
+    if (t >= p.two_pi) t = __fsub_rn(t, p.two_pi);
+    t = store<T>::rnd(t);
+    float sn, cn;
+    sincos_rev(t, sn, cn);
+    const float dc = __fsub_rn(cn, c);
+    const float ds = __fsub_rn(sn, s);
+    const float dE = -__fmaf_rn(dc, sx, __fmul_rn(ds, sy));
+    if (dE_out) *dE_out = dE;
+    const int acc = u01(w2) < __builtin_amdgcn_exp2f(__fmul_rn(p.nbl2e, dE));
+    th = acc ? t : th;
+    c = acc ? cn : c;
+    s = acc ? sn : s;
+    return acc;
+}
+
+__device__ __forceinline__ float nsum(float l, float r, float u, float d)
+{
+    return __fadd_rn(__fadd_rn(l, r), __fadd_rn(u, d));
+}
+
+// Bond and magnetisation terms a black site contributes to a measurement: its
+// four bonds (every bond has exactly one black end) and its own spin plus that
+// of the red site to its right (a bijection black -> red).
+struct Meas {
+    float cx, cy, ix, iy, mx, my;
+};
+
+__device__ __forceinline__ void meas_black(Meas& m, float cb, float sb, float cl, float sl, float cr,
+                                           float sr, float cu, float su, float cd, float sd)
+{
+    // bond (x-1 -> x): cos(tl - tb), sin(tl - tb); bond (x -> x+1): cos(tb - tr), sin(tb - tr)
+    m.cx += __fmaf_rn(cl, cb, __fmul_rn(sl, sb)) + __fmaf_rn(cb, cr, __fmul_rn(sb, sr));
+    m.ix += __fmaf_rn(sl, cb, -__fmul_rn(cl, sb)) + __fmaf_rn(sb, cr, -__fmul_rn(cb, sr));
+    m.cy += __fmaf_rn(cu, cb, __fmul_rn(su, sb)) + __fmaf_rn(cb, cd, __fmul_rn(sb, sd));
+    m.iy += __fmaf_rn(su, cb, -__fmul_rn(cu, sb)) + __fmaf_rn(sb, cd, -__fmul_rn(cb, sd));
+    m.mx += cb + cr;
+    m.my += sb + sr;
+}
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace xyd

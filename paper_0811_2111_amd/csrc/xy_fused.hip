@@ -1,0 +1,94 @@
+// xy_fused.hip -- single-lattice fused sweep: one workgroup per tile, M sweeps per launch.
+#include <hip/hip_runtime.h>
+
+#include "xy_launch.hpp"
+#include "xy_tile.hpp"
+
+using namespace xyd;
+
+namespace xyk {
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
+// Remap so that each XCD works on one contiguous band of tile rows and the halo
+// rows two neighbouring tiles share stay in that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles)
+{
+    if ((ntiles & 7) != 0) return b;
+    const int per = ntiles >> 3;
+    return (b & 7) * per + (b >> 3);
+}
+
+template <typename T, int TX, int TY, int M, int NT>
+__global__ void __launch_bounds__(NT)
+k_fused(const T* __restrict__ src, T* __restrict__ dst, int L, uint32_t sweep0, uint32_t k0, uint32_t k1, Params p,
+        unsigned meas_mask, double* __restrict__ partials)
+{
+    extern __shared__ __align__(16) char smem[];
+    using Sh = TileShape<TX, TY, M, NT>;
+    const int tiles_x = L / TX;
+    const int ntiles = tiles_x * (L / TY);
+    const int b = xcd_tile((int)blockIdx.x, ntiles);
+    const int ty = b / tiles_x, tx = b - ty * tiles_x;
+    tile_program<T, TX, TY, M, NT>(src, dst, L, tx * TX, ty * TY, sweep0, k0, k1, p, meas_mask,
+                                   partials + (size_t)b * 8, (size_t)ntiles * 8, smem, (double*)(smem + Sh::lds_bytes));
+}
+
+template <typename T, int TX, int TY, int M, int NT>
+static hipError_t run_fused(const SweepArgs& a, unsigned meas_mask, double* partials, hipStream_t s)
+{
+    using Sh = TileShape<TX, TY, M, NT>;
+    static bool attr_set = false;
+    auto kern = k_fused<T, TX, TY, M, NT>;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(Sh::lds_bytes + Sh::red_bytes));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int ntiles = (a.L / TX) * (a.L / TY);
+    const Params p{a.delta, a.two_pi, a.nbl2e};
+    hipLaunchKernelGGL(kern, dim3(ntiles), dim3(NT), Sh::lds_bytes + Sh::red_bytes, s, (const T*)a.src, (T*)a.dst,
+                       a.L, a.sweep, a.key0, a.key1, p, meas_mask, partials);
+    return hipGetLastError();
+}
+
+// The tile shapes the autotuner chooses from.
+#define XY_FUSED_SHAPES(X) \
+    X(64, 16, 1, 256)      \
+    X(64, 32, 1, 256)      \
+    X(128, 16, 1, 256)     \
+    X(128, 32, 1, 256)     \
+    X(128, 64, 1, 256)     \
+    X(256, 16, 1, 256)     \
+    X(256, 32, 1, 256)     \
+    X(64, 32, 2, 256)      \
+    X(128, 32, 2, 256)
+
+bool fused_supported(int L, int tile_x, int tile_y, int m)
+{
+    if (L < 4 || (L % 4) != 0 || tile_x <= 0 || tile_y <= 0) return false;
+    if (L % tile_x != 0 || L % tile_y != 0) return false;
+    if (2 * m > L || m > L / 2) return false;
+#define X(tx, ty, mm, nt) \
+    if (tile_x == tx && tile_y == ty && m == mm) return true;
+    XY_FUSED_SHAPES(X)
+#undef X
+    return false;
+}
+
+int fused_tiles(int L, int tile_x, int tile_y) { return (L / tile_x) * (L / tile_y); }
+
+hipError_t launch_fused(const SweepArgs& a, int tile_x, int tile_y, int m, unsigned meas_mask, double* partials,
+                        hipStream_t s)
+{
+#define X(tx, ty, mm, nt)                                                                          \
+    if (tile_x == tx && tile_y == ty && m == mm) {                                                 \
+        if (a.precision == XY_FP16) return run_fused<__half, tx, ty, mm, nt>(a, meas_mask, partials, s); \
+        return run_fused<float, tx, ty, mm, nt>(a, meas_mask, partials, s);               \
+    }
+    XY_FUSED_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace xyk

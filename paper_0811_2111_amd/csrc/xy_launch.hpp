@@ -1,0 +1,62 @@
+// xy_launch.hpp -- host-side launchers of the HIP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "xy.h"
+
+namespace xyk {
+
+struct SweepArgs {
+    void* src;          // state read by the sweep
+    void* dst;          // state written (== src for in-place schedules)
+    int L;
+    int precision;      // XY_FP32 / XY_FP16
+    uint32_t key0, key1;
+    uint32_t sweep;     // absolute index of the (first) sweep
+    float delta, two_pi, nbl2e;
+};
+
+// Workspace carve-up shared by the runtime and the launchers.
+struct Work {
+    void* pingpong;                 // second state buffer (fused schedule)
+    unsigned long long* counter;    // accept counter (one u64)
+    double* partials;               // per-workgroup measurement partials, 8 doubles each
+    int max_partials;
+};
+
+size_t state_bytes(int L, int precision);
+size_t work_bytes(int L, int precision);
+Work carve(void* work, int L, int precision);
+int max_partials_for(int L);
+
+hipError_t launch_init(void* st, int L, int precision, uint32_t k0, uint32_t k1, int hot, hipStream_t s);
+
+// One half-sweep of `colour`, in place.  counter != NULL adds the accepts to it;
+// dbg_acc / dbg_dE != NULL write per-site decisions and FP32 dE in the state layout.
+hipError_t launch_half_sweep(const SweepArgs& a, int colour, unsigned long long* counter,
+                             uint8_t* dbg_acc, float* dbg_dE, hipStream_t s);
+
+// FP64 partial sums of the observables of state `st` into partials[0..*nparts).
+hipError_t launch_measure(const void* st, int L, int precision, double* partials, int max_parts,
+                          int* nparts, hipStream_t s);
+
+// Reduce partials in a fixed order, take the accept counter (and clear it) plus
+// the accepts in slot 6 of the partials, write one xy_obs record.
+hipError_t launch_finalize(const double* partials, int nparts, unsigned long long* counter,
+                           xy_obs* out, uint64_t sweep_after, hipStream_t s);
+
+// Fused tiled sweep(s): `m` sweeps (1 or 2) per launch from a.src to a.dst.
+// meas_mask bit j set: measure after sub-sweep j into the 8-double record
+// partials[(j * ntiles + tile) * 8] (slot 6 = the tile's accepts).
+hipError_t launch_fused(const SweepArgs& a, int tile_x, int tile_y, int m, unsigned meas_mask,
+                        double* partials, hipStream_t s);
+int fused_tiles(int L, int tile_x, int tile_y);
+bool fused_supported(int L, int tile_x, int tile_y, int m);
+
+// Fill n u64 words with zero (kernel, not a memset node: safe inside graphs).
+hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+
+}  // namespace xyk
