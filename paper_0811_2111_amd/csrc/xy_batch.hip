@@ -25,6 +25,7 @@
 #include "xy_launch.hpp"
 #include "xy_runtime.hpp"
 #include "xy_tile.hpp"
+#include "xy_tile1.hpp"
 
 using namespace xyd;
 
@@ -124,7 +125,7 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
         double* __restrict__ part /* [2][total_tiles][8] */, xy_obs* __restrict__ obs, int nrec)
 {
     extern __shared__ __align__(16) char smem[];
-    using S = TileShape<TX, TY, 1, NT>;
+    using S = Tile1<TX, TY, NT>;
     double* red = (double*)(smem + S::lds_bytes);   // 7 doubles per wave, after the tile's LDS
     const int G = gridDim.x, w = blockIdx.x;
     const int t0 = (int)((long long)total_tiles * w / G);
@@ -156,9 +157,9 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
             for (int t = a; t < b; ++t) {
                 const int lt = t - d.first_tile;
                 const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
-                tile_program<T, TX, TY, 1, NT>(src + d.off, dst + d.off, d.L, tx * TX, ty * TY, sweep0 + (uint32_t)p,
-                                               d.key0, d.key1, prm, meas ? 1u : 0u, pslot + (size_t)t * 8, 0, smem,
-                                               red);
+                tile1_program<T, TX, TY, NT>(src + d.off, dst + d.off, d.L, tx * TX, ty * TY, sweep0 + (uint32_t)p,
+                                             d.key0, d.key1, prm, meas, pslot + (size_t)t * 8, smem, red);
+                __syncthreads();   // the next tile reuses the LDS
             }
         }
         for (int i = ilo; i <= ihi; ++i) arrive(&bar[i]);
@@ -272,7 +273,7 @@ static void* batch_kernel(int precision, Shape s, size_t* lds)
 {
 #define XYB_CASE(TXV, TYV)                                                                         \
     if (s.tx == TXV && s.ty == TYV) {                                                              \
-        *lds = TileShape<TXV, TYV, 1, kNT>::lds_bytes + TileShape<TXV, TYV, 1, kNT>::red_bytes;    \
+        *lds = Tile1<TXV, TYV, kNT>::lds_bytes + Tile1<TXV, TYV, kNT>::red_bytes;                  \
         return precision == XY_FP16 ? kernel_ptr<__half, TXV, TYV>() : kernel_ptr<float, TXV, TYV>(); \
     }
     XYB_CASE(64, 32)

@@ -3,6 +3,7 @@
 
 #include "xy_launch.hpp"
 #include "xy_tile.hpp"
+#include "xy_tile1.hpp"
 
 using namespace xyd;
 
@@ -18,36 +19,48 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles)
     return (b & 7) * per + (b >> 3);
 }
 
+// LDS bytes of a fused launch: the single-sweep tile keeps (cos, sin) only, the
+// two-sweep tile also the angles.
+template <int TX, int TY, int M, int NT>
+constexpr size_t fused_lds()
+{
+    if constexpr (M == 1) return Tile1<TX, TY, NT>::lds_bytes;
+    else return TileShape<TX, TY, M, NT>::lds_bytes;
+}
+
 template <typename T, int TX, int TY, int M, int NT>
 __global__ void __launch_bounds__(NT)
 k_fused(const T* __restrict__ src, T* __restrict__ dst, int L, uint32_t sweep0, uint32_t k0, uint32_t k1, Params p,
         unsigned meas_mask, double* __restrict__ partials)
 {
     extern __shared__ __align__(16) char smem[];
-    using Sh = TileShape<TX, TY, M, NT>;
     const int tiles_x = L / TX;
     const int ntiles = tiles_x * (L / TY);
     const int b = xcd_tile((int)blockIdx.x, ntiles);
     const int ty = b / tiles_x, tx = b - ty * tiles_x;
-    tile_program<T, TX, TY, M, NT>(src, dst, L, tx * TX, ty * TY, sweep0, k0, k1, p, meas_mask,
-                                   partials + (size_t)b * 8, (size_t)ntiles * 8, smem, (double*)(smem + Sh::lds_bytes));
+    double* red = (double*)(smem + fused_lds<TX, TY, M, NT>());
+    if constexpr (M == 1)
+        tile1_program<T, TX, TY, NT>(src, dst, L, tx * TX, ty * TY, sweep0, k0, k1, p, (meas_mask & 1u) != 0,
+                                     partials + (size_t)b * 8, smem, red);
+    else
+        tile_program<T, TX, TY, M, NT>(src, dst, L, tx * TX, ty * TY, sweep0, k0, k1, p, meas_mask,
+                                       partials + (size_t)b * 8, (size_t)ntiles * 8, smem, red);
 }
 
 template <typename T, int TX, int TY, int M, int NT>
 static hipError_t run_fused(const SweepArgs& a, unsigned meas_mask, double* partials, hipStream_t s)
 {
-    using Sh = TileShape<TX, TY, M, NT>;
+    constexpr size_t lds = fused_lds<TX, TY, M, NT>() + (size_t)(NT / 64) * 7 * sizeof(double);
     static bool attr_set = false;
     auto kern = k_fused<T, TX, TY, M, NT>;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)(Sh::lds_bytes + Sh::red_bytes));
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const int ntiles = (a.L / TX) * (a.L / TY);
     const Params p{a.delta, a.two_pi, a.nbl2e};
-    hipLaunchKernelGGL(kern, dim3(ntiles), dim3(NT), Sh::lds_bytes + Sh::red_bytes, s, (const T*)a.src, (T*)a.dst,
+    hipLaunchKernelGGL(kern, dim3(ntiles), dim3(NT), lds, s, (const T*)a.src, (T*)a.dst,
                        a.L, a.sweep, a.key0, a.key1, p, meas_mask, partials);
     return hipGetLastError();
 }
