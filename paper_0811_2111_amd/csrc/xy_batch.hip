@@ -54,26 +54,34 @@ struct Ctrl {
 // up flags ctrl->timed_out and lets the workgroup run on, so every wave exits.
 static constexpr unsigned kSpinLimit = 1u << 27;
 
-// barrier wait: spin until *ctr >= target (agent-scope acquire)
+// Barrier wait: thread 0 polls the counter with relaxed loads (no cache
+// maintenance per poll), then one agent-scope acquire fence makes the other
+// workgroups' writes visible before the workgroup reads them.
 __device__ __forceinline__ void wait_at_least(unsigned* ctr, unsigned target, Ctrl* ctrl)
 {
     if (threadIdx.x == 0) {
         unsigned spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins == kSpinLimit) {
                 __hip_atomic_store(&ctrl->timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
 
+// Barrier arrival: the workgroup's writes are ordered before one agent-scope
+// release fence, then a relaxed increment.
 __device__ __forceinline__ void arrive(unsigned* ctr)
 {
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 __device__ __forceinline__ int lattice_of(const LatDesc* d, int n, int tile)
@@ -157,8 +165,9 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
             for (int t = a; t < b; ++t) {
                 const int lt = t - d.first_tile;
                 const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
-                tile1_program<T, TX, TY, NT>(src + d.off, dst + d.off, d.L, tx * TX, ty * TY, sweep0 + (uint32_t)p,
-                                             d.key0, d.key1, prm, meas, pslot + (size_t)t * 8, smem, red);
+                tile1_program<T, TX, TY, NT>(src + d.off, dst + d.off, (unsigned)((size_t)d.L * d.L * sizeof(T)), d.L,
+                                             tx * TX, ty * TY, sweep0 + (uint32_t)p, d.key0, d.key1, prm, meas,
+                                             pslot + (size_t)t * 8, smem, red);
                 __syncthreads();   // the next tile reuses the LDS
             }
         }
@@ -419,8 +428,8 @@ extern "C" {
 int xy_batch_state_bytes(int32_t n, const int32_t* L, int32_t precision, size_t* state, size_t* workspace)
 {
     if (n <= 0 || !L || (precision != XY_FP32 && precision != XY_FP16)) return XY_EINVAL;
-    for (int i = 0; i < n; ++i)
-        if (!xyr::valid_L(L[i]) || L[i] % 4 != 0) return XY_EINVAL;
+    for (int i = 0; i < n; ++i)   // tiles address each lattice with 32-bit byte offsets
+        if (!xyr::valid_L(L[i]) || L[i] % 4 != 0 || (long long)L[i] * L[i] * 4 >= (1LL << 32)) return XY_EINVAL;
     if (candidates(n, L).empty()) return XY_EINVAL;
     Layout lo = layout(n, L, precision);
     if (state) *state = lo.state_bytes;

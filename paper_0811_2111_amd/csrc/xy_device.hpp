@@ -41,16 +41,23 @@ __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
     return {c0, c1, c2, c3};
 }
 
-// u = (2 (w >> 9) + 1) 2^-24, exact in FP32.
-__device__ __forceinline__ float u01(uint32_t w)
+// f = 1 + (w >> 9) 2^-23 in [1, 2): the top 23 bits of w as the mantissa of a
+// float with exponent 0, built by one funnel shift (alignbit).
+__device__ __forceinline__ float one_two(uint32_t w)
 {
-    return (float)(((w >> 9) << 1) | 1u) * 0x1p-24f;
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, w, 9));
 }
 
-// 2u - 1 = (2 (w >> 9) + 1 - 2^23) 2^-23, exact in FP32.
+// u = (2 (w >> 9) + 1) 2^-24 = f - (1 - 2^-24), exact in FP32 (Sterbenz).
+__device__ __forceinline__ float u01(uint32_t w)
+{
+    return __fsub_rn(one_two(w), 0x1.fffffep-1f);
+}
+
+// 2u - 1 = (2 (w >> 9) + 1 - 2^23) 2^-23 = (2f - 3) + 2^-23, each step exact.
 __device__ __forceinline__ float sym11(uint32_t w)
 {
-    return (float)((int32_t)(((w >> 9) << 1) | 1u) - 0x800000) * 0x1p-23f;
+    return __fadd_rn(__fmaf_rn(one_two(w), 2.0f, -3.0f), 0x1p-23f);
 }
 
 // ------------------------------------------------------------- sin / cos / exp

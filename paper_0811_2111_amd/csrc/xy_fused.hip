@@ -40,8 +40,8 @@ k_fused(const T* __restrict__ src, T* __restrict__ dst, int L, uint32_t sweep0, 
     const int ty = b / tiles_x, tx = b - ty * tiles_x;
     double* red = (double*)(smem + fused_lds<TX, TY, M, NT>());
     if constexpr (M == 1)
-        tile1_program<T, TX, TY, NT>(src, dst, L, tx * TX, ty * TY, sweep0, k0, k1, p, (meas_mask & 1u) != 0,
-                                     partials + (size_t)b * 8, smem, red);
+        tile1_program<T, TX, TY, NT>(src, dst, (unsigned)((size_t)L * L * sizeof(T)), L, tx * TX, ty * TY, sweep0,
+                                     k0, k1, p, (meas_mask & 1u) != 0, partials + (size_t)b * 8, smem, red);
     else
         tile_program<T, TX, TY, M, NT>(src, dst, L, tx * TX, ty * TY, sweep0, k0, k1, p, meas_mask,
                                        partials + (size_t)b * 8, (size_t)ntiles * 8, smem, red);
@@ -80,6 +80,8 @@ static hipError_t run_fused(const SweepArgs& a, unsigned meas_mask, double* part
 bool fused_supported(int L, int tile_x, int tile_y, int m)
 {
     if (L < 4 || (L % 4) != 0 || tile_x <= 0 || tile_y <= 0) return false;
+    // buffer descriptors address the FP32 state with 32-bit byte offsets
+    if ((long long)L * L * 4 >= (1LL << 32)) return false;
     if (L % tile_x != 0 || L % tile_y != 0) return false;
     if (2 * m > L || m > L / 2) return false;
 #define X(tx, ty, mm, nt) \

@@ -1,61 +1,99 @@
 // xy_tile1.hpp -- one fused sweep of one tile, register-resident angles, (cos, sin) in LDS.
 //
-// The single-sweep (M = 1) form of the tile program.  For a TX x TY tile at
-// (x0, y0), kb = x0 / 2:
-//   * black entries of rows y0-2 .. y0+TY+1 and red entries of rows y0-1 .. y0+TY,
-//     columns kb-1 .. kb+TX/2, are what the sweep reads (the red ones of the outer
-//     ring are recomputed with their owners' random numbers);
-//   * every angle is loaded from HBM exactly once, as aligned pairs (entries 2j,
-//     2j+1 of a half-row, the two sites of one Philox call) plus one column of
-//     single entries on each side;
-//   * a thread keeps the angles of the pairs it loads in registers and updates
-//     those same pairs, so angles never pass through LDS; LDS holds only
-//     (cos, sin) per entry, read as 16-byte pairs;
-//   * updated angles go straight from registers to the destination buffer, and
-//     the measurement of a measured sweep is folded into the black update.
-// The arithmetic of every site update is xyd::site_update with the neighbour
-// sums in the order (left + right) + (up + down), as in every other kernel.
+// The single-sweep form of the tile program.  For a TX x TY tile at (x0, y0),
+// kb = x0 / 2:
+//   * the sweep reads black entries of rows y0-2 .. y0+TY+1 and red entries of
+//     rows y0-1 .. y0+TY, columns kb-1 .. kb+TX/2 (the red ones of the outer ring
+//     are recomputed with their owners' random numbers, so the tile needs no
+//     other tile's results);
+//   * every angle is loaded once, as aligned pairs (entries 2j, 2j+1 of a
+//     half-row, the two sites of one Philox call) plus a column of single
+//     entries on each side;
+//   * the thread that loads a pair keeps its angles in registers and updates it,
+//     so angles never pass through LDS; LDS holds (cos, sin) per entry, read as
+//     16-byte pairs;
+//   * lanes are laid out so that all rows a wave touches have the same parity:
+//     the position of a site's horizontal neighbours in the other half-lattice
+//     depends only on that parity, so a whole wave takes one branch and needs no
+//     per-lane selects;
+//   * global traffic uses buffer instructions with 32-bit offsets (the state must
+//     be below 4 GiB), updated angles go straight from registers to the
+//     destination, and a measured sweep folds its sums into the black update.
+// Every site update is xyd::site_update with neighbour sums in the order
+// (left + right) + (up + down), as in every other kernel.
 #pragma once
 
 #include "xy_device.hpp"
 
 namespace xyd {
 
-template <typename T> struct pair_io;
-template <> struct pair_io<float> {
-    using P = float2;
-    static __device__ __forceinline__ float2 ld(const float* p) { return *(const float2*)p; }
-    static __device__ __forceinline__ void st(float* p, float a, float b) { *(float2*)p = make_float2(a, b); }
-};
-template <> struct pair_io<__half> {
-    using P = __half2;
-    static __device__ __forceinline__ float2 ld(const __half* p)
+typedef unsigned int xu2 __attribute__((ext_vector_type(2)));
+
+template <typename T> struct bio;
+template <> struct bio<float> {
+    static __device__ __forceinline__ float2 ld2(__amdgpu_buffer_rsrc_t r, unsigned off_elems)
     {
-        const __half2 h = *(const __half2*)p;
-        return make_float2(__low2float(h), __high2float(h));
+        const xu2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off_elems * 4u, 0, 0);
+        return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
     }
-    static __device__ __forceinline__ void st(__half* p, float a, float b)
+    static __device__ __forceinline__ float ld1(__amdgpu_buffer_rsrc_t r, unsigned off_elems)
     {
-        *(__half2*)p = __floats2half2_rn(a, b);
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off_elems * 4u, 0, 0));
     }
+    static __device__ __forceinline__ void st2(__amdgpu_buffer_rsrc_t r, unsigned off_elems, float a, float b)
+    {
+        xu2 v;
+        v.x = __float_as_uint(a);
+        v.y = __float_as_uint(b);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, off_elems * 4u, 0, 0);
+    }
+    static constexpr unsigned bytes = 4;
 };
+template <> struct bio<__half> {
+    static __device__ __forceinline__ float2 ld2(__amdgpu_buffer_rsrc_t r, unsigned off_elems)
+    {
+        const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, off_elems * 2u, 0, 0);
+        return make_float2(__half2float(__ushort_as_half((unsigned short)(v & 0xffffu))),
+                           __half2float(__ushort_as_half((unsigned short)(v >> 16))));
+    }
+    static __device__ __forceinline__ float ld1(__amdgpu_buffer_rsrc_t r, unsigned off_elems)
+    {
+        const unsigned short v = __builtin_amdgcn_raw_buffer_load_b16(r, off_elems * 2u, 0, 0);
+        return __half2float(__ushort_as_half(v));
+    }
+    static __device__ __forceinline__ void st2(__amdgpu_buffer_rsrc_t r, unsigned off_elems, float a, float b)
+    {
+        const unsigned v = (unsigned)__half_as_ushort(__float2half_rn(a)) |
+                           ((unsigned)__half_as_ushort(__float2half_rn(b)) << 16);
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, off_elems * 2u, 0, 0);
+    }
+    static constexpr unsigned bytes = 2;
+};
+
+// Raw buffer resource over `bytes` bytes at `base` (gfx9 descriptor word 3).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
 
 template <int TX, int TY, int NT>
 struct Tile1 {
-    static_assert(TX >= 4 && (TX & (TX - 1)) == 0, "tile_x must be a power of two >= 4");
-    static constexpr int TQ = TX / 4;                 // Philox pairs per core half-row
+    static_assert(TX >= 4 && (TX & (TX - 1)) == 0 && TX <= 256, "tile_x: power of two in [4, 256]");
+    static_assert(NT % 128 == 0, "at least two waves");
+    static constexpr int TQ = TX / 4;                  // Philox pairs per core half-row
     static constexpr int LGQ = __builtin_ctz(TQ);
-    static constexpr int RR = TY + 2;                 // red rows y0-1 .. y0+TY
-    static constexpr int RB = TY + 4;                 // black rows y0-2 .. y0+TY+1
-    static constexpr int WS = TX / 2 + 4;             // LDS row stride in (cos, sin) entries; col(k) = k - kb + 2
-    static constexpr int NRED = RR * TQ;
-    static constexpr int NPAIR = NRED + RB * TQ;
-    static constexpr int NPI = (NPAIR + NT - 1) / NT;  // pair items per thread
+    static constexpr int NW = NT / 64;                 // waves
+    static constexpr int RP = NT / TQ;                 // rows covered by one pass of the workgroup
+    static constexpr int RR = TY + 2;                  // red rows y0-1 .. y0+TY
+    static constexpr int RB = TY + 4;                  // black rows y0-2 .. y0+TY+1
+    static constexpr int NQR = (RR + RP - 1) / RP;     // red pair items per thread
+    static constexpr int NQB = (RB + RP - 1) / RP;     // black pair items per thread
+    static constexpr int WS = TX / 2 + 4;              // LDS row stride in (cos, sin) entries; col(k) = k - kb + 2
     static constexpr int NEDGE = RR + 2 * RB;          // red: the one needed side per row; black: both
-    static_assert(NEDGE <= NT, "edge column must fit one pass");
+    static_assert(NEDGE <= NT, "edge columns must fit one pass");
     static constexpr int BLACK0 = RR * WS;             // black plane offset in LDS entries
     static constexpr size_t lds_bytes = (size_t)(RR + RB) * WS * sizeof(float2);
-    static constexpr size_t red_bytes = (size_t)(NT / 64) * 7 * sizeof(double);
+    static constexpr size_t red_bytes = (size_t)NW * 7 * sizeof(double);
 };
 
 // 7-value workgroup sum in a fixed order; thread 0 receives the totals.
@@ -82,55 +120,171 @@ __device__ __forceinline__ void block_sum7(double v[7], double* red)
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// Neighbour (cos, sin) of the two entries of a pair at LDS column c0 (even) of
-// the other colour's row `row`: h = entries c0, c0+1 (one 16-byte read), side =
-// entry c0-1 (o = 0) or c0+2 (o = 1).
+// Neighbours of the pair at LDS column c0 (even) in the other colour's row `row`.
+// O = row parity of the updated sites: left/right neighbours of entry k are the
+// other colour's entries k + O - 1 and k + O.
+template <int O>
 struct PairNb {
     float2 la, ra, lb, rb, ua, ub, da, db;
+    __device__ __forceinline__ PairNb(const float2* __restrict__ plane, int WS, int row, int c0)
+    {
+        const float4 h = *(const float4*)&plane[row * WS + c0];
+        const float2 side = plane[row * WS + (O ? c0 + 2 : c0 - 1)];
+        const float4 u = *(const float4*)&plane[(row - 1) * WS + c0];
+        const float4 d = *(const float4*)&plane[(row + 1) * WS + c0];
+        const float2 hl = make_float2(h.x, h.y), hh = make_float2(h.z, h.w);
+        la = O ? hl : side;
+        ra = O ? hh : hl;
+        lb = O ? hh : hl;
+        rb = O ? side : hh;
+        ua = make_float2(u.x, u.y);
+        ub = make_float2(u.z, u.w);
+        da = make_float2(d.x, d.y);
+        db = make_float2(d.z, d.w);
+    }
 };
 
-__device__ __forceinline__ PairNb pair_neighbours(const float2* __restrict__ plane, int WS, int row, int c0, int o)
+struct MeasAcc {
+    float cx = 0.f, cy = 0.f, ix = 0.f, iy = 0.f, mx = 0.f, my = 0.f;
+};
+
+__device__ __forceinline__ void meas_acc(MeasAcc& m, float cb, float sb, float2 l, float2 r, float2 u, float2 d)
 {
-    const float4 h = *(const float4*)&plane[row * WS + c0];
-    const float2 side = plane[row * WS + (o ? c0 + 2 : c0 - 1)];
-    const float4 u = *(const float4*)&plane[(row - 1) * WS + c0];
-    const float4 d = *(const float4*)&plane[(row + 1) * WS + c0];
-    const float2 hl = make_float2(h.x, h.y), hh = make_float2(h.z, h.w);
-    PairNb n;
-    n.la = o ? hl : side;
-    n.ra = o ? hh : hl;
-    n.lb = o ? hh : hl;
-    n.rb = o ? side : hh;
-    n.ua = make_float2(u.x, u.y);
-    n.ub = make_float2(u.z, u.w);
-    n.da = make_float2(d.x, d.y);
-    n.db = make_float2(d.z, d.w);
-    return n;
+    Meas t{0, 0, 0, 0, 0, 0};
+    meas_black(t, cb, sb, l.x, l.y, r.x, r.y, u.x, u.y, d.x, d.y);
+    m.cx += t.cx; m.cy += t.cy; m.ix += t.ix; m.iy += t.iy; m.mx += t.mx; m.my += t.my;
 }
 
+// Per-thread geometry shared by both phases.
+struct T1Geom {
+    int L, Hh, P, kb, y0, x0;
+    int s;           // pair slot within a core half-row
+    int rt;          // row of this thread's first item; items q add q * RP rows
+    bool edge_tile;  // rows wrap around the lattice
+};
+
+template <typename T, int TX, int TY, int NT, int O, bool MEAS>
+__device__ __forceinline__ void tile1_update(const T1Geom& g, float2* __restrict__ cs, float2 (&thr)[Tile1<TX, TY, NT>::NQR],
+                                             float2 (&thb)[Tile1<TX, TY, NT>::NQB], __amdgpu_buffer_rsrc_t dst,
+                                             uint32_t sweep, uint32_t k0, uint32_t k1, const Params& p,
+                                             float the, int e, int e_row, int e_col, int e_red, int e_k,
+                                             int& acc, MeasAcc& m)
+{
+    using S = Tile1<TX, TY, NT>;
+    const float2* blk = cs + S::BLACK0;
+    const int c0 = 2 * g.s + 2;
+    const unsigned jb = (unsigned)((g.kb >> 1) + g.s);
+
+    // ---- red half-sweep: rows y0-1 .. y0+TY, columns kb-1 .. kb+TX/2
+#pragma unroll
+    for (int q = 0; q < S::NQR; ++q) {
+        const int row = q * S::RP + g.rt;
+        if (row < S::RR) {
+            const int y = g.y0 - 1 + row;
+            const int yw = g.edge_tile ? wrapi(y, g.L) : y;
+            const PairNb<O> n(blk, S::WS, row + 1, c0);
+            float4 own = *(const float4*)&cs[row * S::WS + c0];
+            const u32x4 r = philox10((uint32_t)yw * (uint32_t)g.P + jb, sweep, 0u, 0u, k0, k1);
+            float ta = thr[q].x, tb = thr[q].y;
+            const int aa = site_update<T>(ta, own.x, own.y, nsum(n.la.x, n.ra.x, n.ua.x, n.da.x),
+                                          nsum(n.la.y, n.ra.y, n.ua.y, n.da.y), r.x, r.y, p);
+            const int ab = site_update<T>(tb, own.z, own.w, nsum(n.lb.x, n.rb.x, n.ub.x, n.db.x),
+                                          nsum(n.lb.y, n.rb.y, n.ub.y, n.db.y), r.z, r.w, p);
+            *(float4*)&cs[row * S::WS + c0] = own;
+            if (row >= 1 && row <= TY) {
+                acc += aa + ab;
+                bio<T>::st2(dst, (unsigned)y * (unsigned)g.Hh + (unsigned)(g.kb + 2 * g.s), ta, tb);
+            }
+        }
+    }
+    if (e < S::NEDGE && e_red) {          // the one ring entry of red row e_row
+        const int y = g.y0 - 1 + e_row;
+        const int o = y & 1;
+        const int j = e_k >> 1;            // e_k = kb-1 (odd: words 2, 3) or kb+TX/2 (even: words 0, 1)
+        const u32x4 r = philox10((uint32_t)wrapi(y, g.L) * (uint32_t)g.P + (uint32_t)wrapi(j, g.P), sweep, 0u, 0u,
+                                 k0, k1);
+        const int b = e_row + 1;           // black row of the same y
+        const float2 l = blk[b * S::WS + e_col + o - 1], rt = blk[b * S::WS + e_col + o];
+        const float2 u = blk[(b - 1) * S::WS + e_col], d = blk[(b + 1) * S::WS + e_col];
+        float2 own = cs[e_row * S::WS + e_col];
+        const bool odd = (e_k & 1) != 0;
+        site_update<T>(the, own.x, own.y, nsum(l.x, rt.x, u.x, d.x), nsum(l.y, rt.y, u.y, d.y), odd ? r.z : r.x,
+                       odd ? r.w : r.y, p);
+        cs[e_row * S::WS + e_col] = own;
+    }
+    __syncthreads();
+
+    // ---- black half-sweep: interior rows y0 .. y0+TY-1 (black LDS rows 2 .. TY+1)
+#pragma unroll
+    for (int q = 0; q < S::NQB; ++q) {
+        const int row = q * S::RP + g.rt;
+        if (row >= 2 && row < TY + 2) {
+            const int y = g.y0 - 2 + row;  // interior: never wraps
+            const PairNb<O> n(cs, S::WS, row - 1, c0);
+            const float4 own = *(const float4*)&blk[row * S::WS + c0];
+            const u32x4 r = philox10((uint32_t)y * (uint32_t)g.P + jb, sweep, 1u, 0u, k0, k1);
+            float ta = thb[q].x, tb = thb[q].y;
+            float ca = own.x, sa = own.y, cb = own.z, sb = own.w;
+            const int aa = site_update<T>(ta, ca, sa, nsum(n.la.x, n.ra.x, n.ua.x, n.da.x),
+                                          nsum(n.la.y, n.ra.y, n.ua.y, n.da.y), r.x, r.y, p);
+            const int ab = site_update<T>(tb, cb, sb, nsum(n.lb.x, n.rb.x, n.ub.x, n.db.x),
+                                          nsum(n.lb.y, n.rb.y, n.ub.y, n.db.y), r.z, r.w, p);
+            acc += aa + ab;
+            bio<T>::st2(dst, ((unsigned)g.L + (unsigned)y) * (unsigned)g.Hh + (unsigned)(g.kb + 2 * g.s), ta, tb);
+            if constexpr (MEAS) {
+                meas_acc(m, ca, sa, n.la, n.ra, n.ua, n.da);
+                meas_acc(m, cb, sb, n.lb, n.rb, n.ub, n.db);
+            }
+        }
+    }
+}
+
+// src/dst: the two state buffers (same layout); `state_bytes` bounds the buffer
+// descriptors.  part: 8 doubles written if `meas` (Cx, Cy, Ix, Iy, Mx, My, accepts, 0).
 template <typename T, int TX, int TY, int NT>
-__device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __restrict__ dst, int L, int x0, int y0,
-                                              uint32_t sweep, uint32_t k0, uint32_t k1, const Params& p, bool meas,
-                                              double* part, char* smem, double* red)
+__device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __restrict__ dst, unsigned state_bytes,
+                                              int L, int x0, int y0, uint32_t sweep, uint32_t k0, uint32_t k1,
+                                              const Params& p, bool meas, double* part, char* smem, double* red)
 {
     using S = Tile1<TX, TY, NT>;
     float2* cs = (float2*)smem;
     const int tid = threadIdx.x;
-    const int Hh = L >> 1, P = Hh >> 1;
-    const int kb = x0 >> 1;
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, state_bytes);
+    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, state_bytes);
 
-    // ---- load: all pair items and this thread's edge entry, loads issued first
-    float2 th[S::NPI];
+    T1Geom g;
+    g.L = L;
+    g.Hh = L >> 1;
+    g.P = g.Hh >> 1;
+    g.kb = x0 >> 1;
+    g.x0 = x0;
+    g.y0 = y0;
+    {
+        const int lane = tid & 63, w = tid >> 6;
+        g.s = lane & (S::TQ - 1);
+        const int i = lane >> S::LGQ;
+        // row parity equals the wave's parity, whatever the item
+        g.rt = 2 * (i * (S::NW / 2) + (w >> 1)) + (w & 1);
+    }
+    g.edge_tile = (y0 < 2) || (y0 + TY + 2 > L);
+
+    // ---- loads: red pairs, black pairs and this thread's edge entry, all issued first
+    float2 thr[S::NQR], thb[S::NQB];
+    const unsigned col = (unsigned)(g.kb + 2 * g.s);
 #pragma unroll
-    for (int q = 0; q < S::NPI; ++q) {
-        const int idx = q * NT + tid;
-        if (idx < S::NPAIR) {
-            const bool isred = idx < S::NRED;
-            const int i2 = isred ? idx : idx - S::NRED;
-            const int row = i2 >> S::LGQ, s = i2 & (S::TQ - 1);
-            const int y = wrapi(isred ? y0 - 1 + row : y0 - 2 + row, L);
-            const int c = isred ? 0 : 1;
-            th[q] = pair_io<T>::ld(src + ((size_t)c * L + y) * Hh + kb + 2 * s);
+    for (int q = 0; q < S::NQR; ++q) {
+        const int row = q * S::RP + g.rt;
+        if (row < S::RR) {
+            const int y = g.edge_tile ? wrapi(y0 - 1 + row, L) : y0 - 1 + row;
+            thr[q] = bio<T>::ld2(rs, (unsigned)y * (unsigned)g.Hh + col);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < S::NQB; ++q) {
+        const int row = q * S::RP + g.rt;
+        if (row < S::RB) {
+            const int y = g.edge_tile ? wrapi(y0 - 2 + row, L) : y0 - 2 + row;
+            thb[q] = bio<T>::ld2(rs, ((unsigned)L + (unsigned)y) * (unsigned)g.Hh + col);
         }
     }
     const int e = NT - 1 - tid;            // red edge entries land on the last wave
@@ -149,21 +303,29 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
             yl = y0 - 2 + e_row;
             side = e2 & 1;
         }
-        e_k = side ? kb + TX / 2 : kb - 1;
+        e_k = side ? g.kb + TX / 2 : g.kb - 1;
         e_col = side ? TX / 2 + 2 : 1;
-        the = store<T>::ld(src[((size_t)(e_red ? 0 : 1) * L + wrapi(yl, L)) * Hh + wrapi(e_k, Hh)]);
+        the = bio<T>::ld1(rs, ((unsigned)(e_red ? 0 : L) + (unsigned)wrapi(yl, L)) * (unsigned)g.Hh +
+                                  (unsigned)wrapi(e_k, g.Hh));
     }
 #pragma unroll
-    for (int q = 0; q < S::NPI; ++q) {
-        const int idx = q * NT + tid;
-        if (idx < S::NPAIR) {
-            const bool isred = idx < S::NRED;
-            const int i2 = isred ? idx : idx - S::NRED;
-            const int row = i2 >> S::LGQ, s = i2 & (S::TQ - 1);
+    for (int q = 0; q < S::NQR; ++q) {
+        const int row = q * S::RP + g.rt;
+        if (row < S::RR) {
             float sa, ca, sb, cb;
-            sincos_rev(th[q].x, sa, ca);
-            sincos_rev(th[q].y, sb, cb);
-            *(float4*)&cs[(isred ? 0 : S::BLACK0) + row * S::WS + 2 * s + 2] = make_float4(ca, sa, cb, sb);
+            sincos_rev(thr[q].x, sa, ca);
+            sincos_rev(thr[q].y, sb, cb);
+            *(float4*)&cs[row * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < S::NQB; ++q) {
+        const int row = q * S::RP + g.rt;
+        if (row < S::RB) {
+            float sa, ca, sb, cb;
+            sincos_rev(thb[q].x, sa, ca);
+            sincos_rev(thb[q].y, sb, cb);
+            *(float4*)&cs[S::BLACK0 + row * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
         }
     }
     if (e < S::NEDGE) {
@@ -173,87 +335,31 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     }
     __syncthreads();
 
-    // ---- red half-sweep: rows y0-1 .. y0+TY, columns kb-1 .. kb+TX/2 (ring of one)
     int acc = 0;
-    const float2* blk = cs + S::BLACK0;
-#pragma unroll
-    for (int q = 0; q < S::NPI; ++q) {
-        const int idx = q * NT + tid;
-        if (idx < S::NRED) {
-            const int row = idx >> S::LGQ, s = idx & (S::TQ - 1);
-            const int y = y0 - 1 + row;
-            const int o = y & 1;
-            const int c0 = 2 * s + 2;
-            const PairNb n = pair_neighbours(blk, S::WS, row + 1, c0, o);
-            float4 own = *(const float4*)&cs[row * S::WS + c0];
-            const u32x4 r = philox10((uint32_t)(wrapi(y, L) * P + (kb >> 1) + s), sweep, 0u, 0u, k0, k1);
-            float ta = th[q].x, tb = th[q].y;
-            const int aa = site_update<T>(ta, own.x, own.y, nsum(n.la.x, n.ra.x, n.ua.x, n.da.x),
-                                          nsum(n.la.y, n.ra.y, n.ua.y, n.da.y), r.x, r.y, p);
-            const int ab = site_update<T>(tb, own.z, own.w, nsum(n.lb.x, n.rb.x, n.ub.x, n.db.x),
-                                          nsum(n.lb.y, n.rb.y, n.ub.y, n.db.y), r.z, r.w, p);
-            *(float4*)&cs[row * S::WS + c0] = own;
-            th[q] = make_float2(ta, tb);
-            if (row >= 1 && row <= TY) {
-                acc += aa + ab;
-                pair_io<T>::st(dst + (size_t)y * Hh + kb + 2 * s, ta, tb);
-            }
-        }
-    }
-    if (e < S::NEDGE && e_red) {
-        const int y = y0 - 1 + e_row;
-        const int o = y & 1;
-        const int j = e_k >> 1;            // e_k = kb-1 (odd: words 2, 3) or kb+TX/2 (even: words 0, 1)
-        const u32x4 r = philox10((uint32_t)(wrapi(y, L) * P + wrapi(j, P)), sweep, 0u, 0u, k0, k1);
-        const int b = e_row + 1;           // black row of the same y
-        const float2 l = blk[b * S::WS + e_col + o - 1], rt = blk[b * S::WS + e_col + o];
-        const float2 u = blk[(b - 1) * S::WS + e_col], d = blk[(b + 1) * S::WS + e_col];
-        float2 own = cs[e_row * S::WS + e_col];
-        const bool odd = (e_k & 1) != 0;
-        site_update<T>(the, own.x, own.y, nsum(l.x, rt.x, u.x, d.x), nsum(l.y, rt.y, u.y, d.y), odd ? r.z : r.x,
-                       odd ? r.w : r.y, p);
-        cs[e_row * S::WS + e_col] = own;
-    }
-    __syncthreads();
-
-    // ---- black half-sweep: interior rows y0 .. y0+TY-1 (black pair items of rows 2 .. TY+1)
-    double v[7] = {0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < S::NPI; ++q) {
-        const int idx = q * NT + tid - S::NRED - 2 * S::TQ;
-        if (idx >= 0 && idx < TY * S::TQ) {
-            const int rr = idx >> S::LGQ, s = idx & (S::TQ - 1);   // interior row rr, black LDS row rr + 2
-            const int y = y0 + rr;
-            const int o = (y + 1) & 1;
-            const int c0 = 2 * s + 2;
-            const PairNb n = pair_neighbours(cs, S::WS, rr + 1, c0, o);
-            const float4 own = *(const float4*)&blk[(rr + 2) * S::WS + c0];
-            const u32x4 r = philox10((uint32_t)(y * P + (kb >> 1) + s), sweep, 1u, 0u, k0, k1);
-            float ta = th[q].x, tb = th[q].y;
-            float ca = own.x, sa = own.y, cb = own.z, sb = own.w;
-            const int aa = site_update<T>(ta, ca, sa, nsum(n.la.x, n.ra.x, n.ua.x, n.da.x),
-                                          nsum(n.la.y, n.ra.y, n.ua.y, n.da.y), r.x, r.y, p);
-            const int ab = site_update<T>(tb, cb, sb, nsum(n.lb.x, n.rb.x, n.ub.x, n.db.x),
-                                          nsum(n.lb.y, n.rb.y, n.ub.y, n.db.y), r.z, r.w, p);
-            acc += aa + ab;
-            pair_io<T>::st(dst + ((size_t)L + y) * Hh + kb + 2 * s, ta, tb);
-            if (meas) {
-                Meas t{0, 0, 0, 0, 0, 0};
-                meas_black(t, ca, sa, n.la.x, n.la.y, n.ra.x, n.ra.y, n.ua.x, n.ua.y, n.da.x, n.da.y);
-                meas_black(t, cb, sb, n.lb.x, n.lb.y, n.rb.x, n.rb.y, n.ub.x, n.ub.y, n.db.x, n.db.y);
-                v[0] += (double)t.cx; v[1] += (double)t.cy; v[2] += (double)t.ix;
-                v[3] += (double)t.iy; v[4] += (double)t.mx; v[5] += (double)t.my;
-            }
-        }
-    }
+    MeasAcc m;
+    const bool odd_rows = ((y0 - 1 + g.rt) & 1) != 0;   // wave-uniform
     if (meas) {
-        v[6] = (double)acc;
+        if (odd_rows)
+            tile1_update<T, TX, TY, NT, 1, true>(g, cs, thr, thb, rd, sweep, k0, k1, p, the, e, e_row, e_col, e_red,
+                                                 e_k, acc, m);
+        else
+            tile1_update<T, TX, TY, NT, 0, true>(g, cs, thr, thb, rd, sweep, k0, k1, p, the, e, e_row, e_col, e_red,
+                                                 e_k, acc, m);
+        double v[7] = {(double)m.cx, (double)m.cy, (double)m.ix, (double)m.iy, (double)m.mx, (double)m.my,
+                       (double)acc};
         block_sum7<NT>(v, red);
         if (tid == 0) {
 #pragma unroll
             for (int q = 0; q < 7; ++q) part[q] = v[q];
             part[7] = 0.0;
         }
+    } else {
+        if (odd_rows)
+            tile1_update<T, TX, TY, NT, 1, false>(g, cs, thr, thb, rd, sweep, k0, k1, p, the, e, e_row, e_col,
+                                                  e_red, e_k, acc, m);
+        else
+            tile1_update<T, TX, TY, NT, 0, false>(g, cs, thr, thb, rd, sweep, k0, k1, p, the, e, e_row, e_col,
+                                                  e_red, e_k, acc, m);
     }
 }
 

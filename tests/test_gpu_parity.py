@@ -166,7 +166,8 @@ def test_debug_decisions_and_dE(orc):
 def test_schedule_invariance(L, prec):
     """Every plan (streaming, every fused tile shape, one or two sweeps per pass) gives
     the same angles bit for bit and the same accept counts; observables agree to
-    reduction-order rounding."""
+    summation-order rounding (FP32 per-thread partials of a few sites, then FP64):
+    within 1e-7 N, ten times inside the oracle tolerance."""
     res = []
     for plan in [STREAM] + fused_plans(L):
         lat = xy.Lattice(L, seed=7, beta=0.9, delta=1.0, precision=prec, plan=plan)
@@ -178,7 +179,7 @@ def test_schedule_invariance(L, prec):
         assert np.array_equal(r["n_accept"], r0["n_accept"]), plan
         assert np.array_equal(r["sweep"], r0["sweep"]), plan
         for f in ["cx", "cy", "ix", "iy", "mx", "my"]:
-            np.testing.assert_allclose(r[f], r0[f], rtol=0, atol=1e-9 * L * L)
+            np.testing.assert_allclose(r[f], r0[f], rtol=0, atol=1e-7 * L * L)
 
 
 def test_odd_and_even_sweep_counts_agree():
@@ -296,7 +297,7 @@ def test_batch_equals_single_and_graph_replays():
                 assert np.array_equal(rb["sweep"], rs["sweep"])
                 assert np.array_equal(rb["n_accept"], rs["n_accept"])
                 for f in ["cx", "cy", "ix", "iy", "mx", "my"]:
-                    np.testing.assert_allclose(rb[f], rs[f], rtol=0, atol=1e-9 * Ls[i] ** 2)
+                    np.testing.assert_allclose(rb[f], rs[f], rtol=0, atol=1e-7 * Ls[i] ** 2)
     assert b.sweep_count == 32
     b.status()
 
