@@ -28,9 +28,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                    # MI355X HBM3E
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # CUs x SIMDs x lanes x clock: 39.3 T lane-instr/s
+# VALU issue slots: one wave64 instruction at the FP32 rate (2 cycles per SIMD).
+# 256 CUs x 128 FP32 lanes x 2.4 GHz = 78.6 T slots/s (the FP32 FMA rate, half of
+# the 157.3 TFLOP/s vector peak).
+VALU_PEAK_TSLOTS = 256 * 128 * 2.4e9 / 1e12
+# Algorithmic VALU slots of one site update (half a Philox4x32-10 call, two uniforms,
+# proposal and wrap, two sin/cos, neighbour sums, dE, exp2 acceptance, selects),
+# with v_mad_u64_u32 = 2 and sin/cos/exp = 4 slots.
+ALG_SLOTS_PER_UPDATE = 90.0
 ALG_BYTES_FUSED = 8.0                    # bytes per site-update of one fused sweep: read 4 + write 4 (FP32)
 ALG_BYTES_STREAM = 12.0                  # two half-sweep passes: read both colours, write one, per half
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
+KERNEL_SOURCES = ["xy_device.hpp", "xy_tile1.hpp", "xy_fused.hip"]
+
+
+def kernel_sources_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0811_2111_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(L, plan):
+    """HBM bytes per launch of k_fused from the committed counter profile, if it was
+    taken on the current kernel sources for this lattice and tile; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    e = t.get("entries", {}).get("%d/%d,%d,%d" % (L, plan[1], plan[2], plan[3]))
+    return None if e is None else e.get("bytes_per_launch")
 
 
 def parse():
@@ -43,6 +75,12 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps of the L=4096 sample")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the main workload's sweeps (for profiler runs)")
+    ap.add_argument("--plan", type=str, default=None,
+                    help="fixed plan 'kind,tile_x,tile_y,sweeps_per_pass' instead of autotuning")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--workload", choices=["l4096", "l16384", "batch"], default="l4096",
+                    help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
     return ap.parse_args()
 
 
@@ -70,16 +108,28 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.kernel_only and args.workload != "l4096":
+        profile_leg(args, stream)
+        return
     cfg = workloads.SINGLE_4096
     L, me = cfg["L"], cfg["measure_every"]
     N = L * L
     # the plan (schedule and tile shape) is picked by the library's autotuner on a
     # scratch lattice of the same size; it does not change the trajectory
-    scratch = xy.Lattice(L, seed=cfg["seed"] + 1000, beta=cfg["beta"], delta=cfg["delta"])
-    tuned = scratch.autotune(20)
-    del scratch
+    if args.plan:
+        tuned = tuple(int(v) for v in args.plan.split(","))
+    else:
+        scratch = xy.Lattice(L, seed=cfg["seed"] + 1000, beta=cfg["beta"], delta=cfg["delta"])
+        tuned = scratch.autotune(20)
+        del scratch
     lat = xy.Lattice(L, seed=cfg["seed"], beta=cfg["beta"], delta=cfg["delta"], plan=tuned)
     plan = lat.plan
+    if args.calib_copy:
+        a = torch.ones((64 << 20,), dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     obs_w = torch.empty((max(args.warmup, 1), 8), dtype=torch.float64, device="cuda")
     obs_t = torch.empty((max(args.steps, 1), 8), dtype=torch.float64, device="cuda")
     if args.warmup:
@@ -122,15 +172,18 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {
             "kernel": "k_fused (LDS-tiled fused red+black sweep)" if plan[0] == 2 else "k_half_sweep",
-            "bound": "hbm",
-            "achieved": round(achieved_gbs, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
-            "alg_bytes_per_update": ALG_BYTES_FUSED if plan[0] == 2 else ALG_BYTES_STREAM,
+            "bound": "alu",
+            "achieved": round(ALG_SLOTS_PER_UPDATE * upd_per_launch / (per_launch_ms * 1e-3) / 1e12, 2),
+            "peak": round(VALU_PEAK_TSLOTS, 2),
+            "unit": "T VALU-slot/s",
+            "frac": round(ALG_SLOTS_PER_UPDATE * upd_per_launch / (per_launch_ms * 1e-3) / 1e12 / VALU_PEAK_TSLOTS, 4),
+            "traffic": measured_traffic(L, plan) if plan[0] == 2 else None,
+            "alg_slots_per_update": ALG_SLOTS_PER_UPDATE,
             "avg_launch_ms": round(per_launch_ms, 5),
             "kernel_gupd_s": round(gupd_kernel, 2),
+            "hbm": {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                    "alg_bytes_per_update": ALG_BYTES_FUSED if plan[0] == 2 else ALG_BYTES_STREAM},
         },
         "observables": {"E_per_site": round(e_mean, 6), "accept_rate": round(acc_rate, 4)},
     }
@@ -142,6 +195,38 @@ def main():
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sweeps)
 
     print(json.dumps(out), flush=True)
+
+
+def profile_leg(args, stream):
+    """Only the sweeps of the L = 16384 or the batched configuration (profiler runs)."""
+    import torch
+
+    from paper_0811_2111_amd import workloads, xy
+    if args.calib_copy:
+        a = torch.ones((64 << 20,), dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.workload == "l16384":
+        c4 = workloads.SINGLE_16384
+        plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
+        lat = xy.Lattice(c4["L"], seed=c4["seed"], beta=c4["beta"], delta=c4["delta"], plan=plan)
+        obs = torch.empty((max(args.steps, 1), 8), dtype=torch.float64, device="cuda")
+        lat.sweep(args.warmup, 1, out=obs[: max(args.warmup, 1)])
+        ms = timed(lambda: lat.sweep(args.steps, c4["measure_every"], out=obs[: args.steps]), stream)
+        print(json.dumps({"workload": "L16384", "sweeps": args.steps, "ms": ms,
+                          "gupd_s": float(c4["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}))
+    else:
+        sc = workloads.temperature_scan()
+        b = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+        nrec = max(args.steps // sc["measure_every"], 1)
+        bobs = torch.empty((len(sc["Ls"]), nrec, 8), dtype=torch.float64, device="cuda")
+        b.sweep(args.warmup)
+        ms = timed(lambda: b.sweep(args.steps, sc["measure_every"], out=bobs), stream)
+        sites = sum(L * L for L in sc["Ls"])
+        print(json.dumps({"workload": "batched scan", "sweeps": args.steps, "ms": ms,
+                          "gupd_s": float(sites) * args.steps / (ms * 1e-3) / 1e9}))
 
 
 def extra_legs(stream):

@@ -16,7 +16,7 @@
  *
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed mod 2^32,
  * seed >> 32), one call per two same-colour sites of a half-row: counter =
- * (y * P + (k >> 1), sweep, colour, purpose) with k the half-row index and
+ * (sweep, colour, purpose, y * P + (k >> 1)) with k the half-row index and
  * P = ceil(L/4); words (X0, X1) for even k and (X2, X3) for odd k; u = (2 (w >> 9)
  * + 1) 2^-24.  Purpose 0 drives the updates, purpose 1 (sweep 0) the hot start
  * theta = 2 pi u.  The stream depends on (seed, site, sweep) only, so every

@@ -19,8 +19,8 @@
  *     odd L (tiny test lattices only) plain sequential raster order;
  *   - the random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
  *     "Parallel random numbers: as easy as 1, 2, 3", SC'11), one call per
- *     two same-colour sites, keyed by the seed, counter (pair, sweep, colour,
- *     purpose);
+ *     two same-colour sites, keyed by the seed, counter (sweep, colour,
+ *     purpose, pair);
  *   - the observables in FP64: bond sums Cx, Cy (cosines), Ix, Iy (sines)
  *     and the magnetisation sums Mx, My.  The paper keeps global energy sums
  *     off the single-precision device for exactly this reason (section 1.2,
@@ -85,8 +85,8 @@ double orc_u01(uint32_t w)
 
 /* The two 32-bit words a site draws for (sweep, purpose).
  * Even L: colour c = (x+y)&1, half-row index k = x>>1, pairs per half-row
- * P = ceil(L/4); counter (y*P + (k>>1), sweep, c, purpose); words (X0,X1) for
- * even k, (X2,X3) for odd k.  Odd L: counter (y*L + x, sweep, 0, purpose+2),
+ * P = ceil(L/4); counter (sweep, c, purpose, y*P + (k>>1)); words (X0,X1) for
+ * even k, (X2,X3) for odd k.  Odd L: counter (sweep, 0, purpose+2, y*L + x),
  * words (X0,X1). */
 void orc_site_words(uint64_t seed, int L, int x, int y, uint32_t sweep,
                     uint32_t purpose, uint32_t w[2])
@@ -97,14 +97,14 @@ void orc_site_words(uint64_t seed, int L, int x, int y, uint32_t sweep,
         uint32_t c = (uint32_t)((x + y) & 1);
         uint32_t k = (uint32_t)(x >> 1);
         uint32_t P = (uint32_t)((L / 2 + 1) / 2);
-        ctr[0] = (uint32_t)y * P + (k >> 1);
-        ctr[1] = sweep; ctr[2] = c; ctr[3] = purpose;
+        ctr[0] = sweep; ctr[1] = c; ctr[2] = purpose;
+        ctr[3] = (uint32_t)y * P + (k >> 1);
         orc_philox4x32_10(ctr, key, r);
         if ((k & 1) == 0) { w[0] = r[0]; w[1] = r[1]; }
         else              { w[0] = r[2]; w[1] = r[3]; }
     } else {
-        ctr[0] = (uint32_t)(y * L + x);
-        ctr[1] = sweep; ctr[2] = 0; ctr[3] = purpose + 2;
+        ctr[0] = sweep; ctr[1] = 0; ctr[2] = purpose + 2;
+        ctr[3] = (uint32_t)(y * L + x);
         orc_philox4x32_10(ctr, key, r);
         w[0] = r[0]; w[1] = r[1];
     }

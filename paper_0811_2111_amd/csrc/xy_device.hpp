@@ -15,8 +15,10 @@ namespace xyd {
 // Salmon, Moraes, Dror, Shaw (SC'11): ten rounds of two 32x32->64 products of
 // words 0 and 2 with the round multipliers, high halves mixed into the other
 // words with the key, key advanced by the Weyl increments between rounds.
-// Uniform counter words and keys stay in scalar registers; on gfx950 each
-// round costs two v_mad_u64_u32 and four v_xor_b32 on the per-lane words.
+// The counter is (sweep, colour, purpose, pair): the three uniform words and
+// the key stay in scalar registers and the per-lane pair index enters through
+// the last word, which the first rounds only xor in, so the early rounds are
+// mostly scalar work.  Later rounds cost two v_mad_u64_u32 and four v_xor_b32.
 struct u32x4 {
     uint32_t x, y, z, w;
 };

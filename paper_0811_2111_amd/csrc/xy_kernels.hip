@@ -5,8 +5,8 @@
 // neighbours of entry (c, y, k) are, in the other half-lattice,
 //     left (y, k + o - 1), right (y, k + o), up (y - 1, k), down (y + 1, k),
 // with o = (c + y) & 1, all periodic.  A thread owns the two entries 2j, 2j+1 of
-// a half-row, which share one Philox call (counter word 0 = y * P + j) and their
-// middle horizontal neighbour.
+// a half-row, which share one Philox call (counter (sweep, colour, purpose,
+// y * P + j)) and their middle horizontal neighbour.
 #include <hip/hip_runtime.h>
 
 #include "xy_device.hpp"
@@ -36,7 +36,8 @@ int max_partials_for(int L)
 
 size_t work_bytes(int L, int precision)
 {
-    return align256(state_bytes(L, precision)) + 256 + (size_t)max_partials_for(L) * 8 * sizeof(double);
+    const size_t np = (size_t)max_partials_for(L);
+    return align256(state_bytes(L, precision)) + 256 + np * 8 * sizeof(double) + ((np + 255) / 256) * 8 * sizeof(double);
 }
 
 Work carve(void* work, int L, int precision)
@@ -49,6 +50,7 @@ Work carve(void* work, int L, int precision)
     p += 256;
     w.partials = (double*)p;
     w.max_partials = max_partials_for(L);
+    w.chunks = w.partials + (size_t)w.max_partials * 8;
     return w;
 }
 
@@ -69,7 +71,7 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ st, int L, uint32_
         if (kb < Hh) row[kb] = store<T>::st(0.0f);
         return;
     }
-    const u32x4 r = philox10((uint32_t)(y * P + j), 0u, (uint32_t)c, 1u, k0, k1);
+    const u32x4 r = philox10(0u, (uint32_t)c, 1u, (uint32_t)(y * P + j), k0, k1);
     // theta = 2 pi u formed in FP64, then rounded to FP32 (and on to binary16)
     const double two_pi = 6.283185307179586476925286766559;
     const double ua = (double)((((r.x >> 9) << 1) | 1u)) * 0x1p-24;
@@ -145,7 +147,7 @@ k_half_sweep(T* __restrict__ st, int L, int col, uint32_t sweep, uint32_t k0, ui
         sincos_rev(ub, sub, cub);
         sincos_rev(da, sda, cda);
         sincos_rev(db, sdb, cdb);
-        const u32x4 r = philox10((uint32_t)(y * P + j), sweep, (uint32_t)col, 0u, k0, k1);
+        const u32x4 r = philox10(sweep, (uint32_t)col, 0u, (uint32_t)(y * P + j), k0, k1);
         float tha = store<T>::ld(own[ka]);
         float sa, ca;
         sincos_rev(tha, sa, ca);
@@ -271,28 +273,60 @@ hipError_t launch_measure(const void* st, int L, int precision, double* partials
     return hipGetLastError();
 }
 
-// Fixed-order reduction of nparts partial records -> one xy_obs.
+// Fixed-order reduction of nparts partial records (8 doubles: six sums, accepts,
+// unused) -> one xy_obs.  Large counts take two levels: k_reduce_chunks sums
+// consecutive chunks of 256 records (thread t takes record t of its chunk, then a
+// fixed tree), k_finalize sums the chunk results.  Both levels are deterministic.
+__device__ __forceinline__ void block_sum7_256(double v[7], double* red /* [4][7] */)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) red[wid * 7 + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) v[q] = (red[q] + red[7 + q]) + (red[14 + q] + red[21 + q]);
+}
+
+__global__ void __launch_bounds__(256)
+k_reduce_chunks(const double* __restrict__ partials, int nparts, double* __restrict__ out)
+{
+    __shared__ double red[4 * 7];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (i < nparts) {
+        const double* q = partials + (size_t)i * 8;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) v[k] = q[k];
+    }
+    block_sum7_256(v, red);
+    if (threadIdx.x == 0) {
+        double* o = out + (size_t)blockIdx.x * 8;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) o[k] = v[k];
+        o[7] = 0.0;
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_finalize(const double* __restrict__ partials, int nparts, unsigned long long* __restrict__ counter,
            xy_obs* __restrict__ out, uint64_t sweep_after)
 {
-    __shared__ double red[4 * 6];
-    __shared__ double racc[4];
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    double a = 0.0;
+    __shared__ double red[4 * 7];
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
     for (int i = threadIdx.x; i < nparts; i += 256) {
         const double* q = partials + (size_t)i * 8;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) v[k] += q[k];
-        a += q[6];
+        for (int k = 0; k < 7; ++k) v[k] += q[k];
     }
-    a = wave_sum(a);
-    if ((threadIdx.x & 63) == 0) racc[threadIdx.x >> 6] = a;
-    block_sum6<256>(v, red);
+    block_sum7_256(v, red);
     if (threadIdx.x == 0) {
         xy_obs o;
         o.sweep = sweep_after;
-        o.n_accept = (counter ? *counter : 0ull) + (unsigned long long)(racc[0] + racc[1] + racc[2] + racc[3]);
+        o.n_accept = (counter ? *counter : 0ull) + (unsigned long long)v[6];
         o.cx = v[0]; o.cy = v[1]; o.ix = v[2]; o.iy = v[3]; o.mx = v[4]; o.my = v[5];
         *out = o;
         if (counter) *counter = 0ull;
@@ -300,9 +334,15 @@ k_finalize(const double* __restrict__ partials, int nparts, unsigned long long* 
 }
 
 hipError_t launch_finalize(const double* partials, int nparts, unsigned long long* counter, xy_obs* out,
-                           uint64_t sweep_after, hipStream_t s)
+                           uint64_t sweep_after, hipStream_t s, double* scratch)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, nparts, counter, out, sweep_after);
+    if (nparts > 2048 && scratch) {
+        const int nb = (nparts + 255) / 256;
+        hipLaunchKernelGGL(k_reduce_chunks, dim3(nb), dim3(256), 0, s, partials, nparts, scratch);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, scratch, nb, counter, out, sweep_after);
+    } else {
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, nparts, counter, out, sweep_after);
+    }
     return hipGetLastError();
 }
 

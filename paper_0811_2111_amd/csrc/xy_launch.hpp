@@ -25,6 +25,7 @@ struct Work {
     unsigned long long* counter;    // accept counter (one u64)
     double* partials;               // per-workgroup measurement partials, 8 doubles each
     int max_partials;
+    double* chunks;                 // second-level sums of 256 partials each
 };
 
 size_t state_bytes(int L, int precision);
@@ -46,7 +47,7 @@ hipError_t launch_measure(const void* st, int L, int precision, double* partials
 // Reduce partials in a fixed order, take the accept counter (and clear it) plus
 // the accepts in slot 6 of the partials, write one xy_obs record.
 hipError_t launch_finalize(const double* partials, int nparts, unsigned long long* counter,
-                           xy_obs* out, uint64_t sweep_after, hipStream_t s);
+                           xy_obs* out, uint64_t sweep_after, hipStream_t s, double* scratch);
 
 // Fused tiled sweep(s): `m` sweeps (1 or 2) per launch from a.src to a.dst.
 // meas_mask bit j set: measure after sub-sweep j into the 8-double record

@@ -78,7 +78,7 @@ __device__ __forceinline__ int tile_half(float2* __restrict__ cs, float* __restr
         const int j = (klo >> 1) + sl;                      // pair of entries 2j, 2j+1
         if (2 * j > khi) continue;
         const int yw = wrap1(y, L), jw = wrap1(j, P);
-        const u32x4 r = philox10((uint32_t)(yw * P + jw), sweep, (uint32_t)col, 0u, k0, k1);
+        const u32x4 r = philox10(sweep, (uint32_t)col, 0u, (uint32_t)(yw * P + jw), k0, k1);
         const int lr = y - (y0 - S::H);
         const bool row_in = (y >= y0) && (y < y0 + TY);
 #pragma unroll

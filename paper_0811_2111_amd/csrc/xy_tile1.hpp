@@ -148,11 +148,19 @@ struct MeasAcc {
     float cx = 0.f, cy = 0.f, ix = 0.f, iy = 0.f, mx = 0.f, my = 0.f;
 };
 
+// A black site's four bonds from the neighbour sums the update already formed:
+//   cos(tl - tb) + cos(tb - tr) = cb (cl + cr) + sb (sl + sr)
+//   sin(tl - tb) + sin(tb - tr) = cb (sl - sr) + sb (cr - cl)
+// and the same with up/down for the y bonds; plus its own spin and that of the red
+// site to its right.
 __device__ __forceinline__ void meas_acc(MeasAcc& m, float cb, float sb, float2 l, float2 r, float2 u, float2 d)
 {
-    Meas t{0, 0, 0, 0, 0, 0};
-    meas_black(t, cb, sb, l.x, l.y, r.x, r.y, u.x, u.y, d.x, d.y);
-    m.cx += t.cx; m.cy += t.cy; m.ix += t.ix; m.iy += t.iy; m.mx += t.mx; m.my += t.my;
+    m.cx += __fmaf_rn(cb, __fadd_rn(l.x, r.x), __fmul_rn(sb, __fadd_rn(l.y, r.y)));
+    m.cy += __fmaf_rn(cb, __fadd_rn(u.x, d.x), __fmul_rn(sb, __fadd_rn(u.y, d.y)));
+    m.ix += __fmaf_rn(cb, __fsub_rn(l.y, r.y), __fmul_rn(sb, __fsub_rn(r.x, l.x)));
+    m.iy += __fmaf_rn(cb, __fsub_rn(u.y, d.y), __fmul_rn(sb, __fsub_rn(d.x, u.x)));
+    m.mx += cb + r.x;
+    m.my += sb + r.y;
 }
 
 // Per-thread geometry shared by both phases.
@@ -176,15 +184,26 @@ __device__ __forceinline__ void tile1_update(const T1Geom& g, float2* __restrict
     const unsigned jb = (unsigned)((g.kb >> 1) + g.s);
 
     // ---- red half-sweep: rows y0-1 .. y0+TY, columns kb-1 .. kb+TX/2
+    // All of this thread's Philox calls first: independent chains the scheduler
+    // can interleave (each call alone is a serial chain of ten rounds).
+    u32x4 rr[S::NQR];
 #pragma unroll
     for (int q = 0; q < S::NQR; ++q) {
         const int row = q * S::RP + g.rt;
         if (row < S::RR) {
             const int y = g.y0 - 1 + row;
             const int yw = g.edge_tile ? wrapi(y, g.L) : y;
+            rr[q] = philox10(sweep, 0u, 0u, (uint32_t)yw * (uint32_t)g.P + jb, k0, k1);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < S::NQR; ++q) {
+        const int row = q * S::RP + g.rt;
+        if (row < S::RR) {
+            const int y = g.y0 - 1 + row;
             const PairNb<O> n(blk, S::WS, row + 1, c0);
             float4 own = *(const float4*)&cs[row * S::WS + c0];
-            const u32x4 r = philox10((uint32_t)yw * (uint32_t)g.P + jb, sweep, 0u, 0u, k0, k1);
+            const u32x4 r = rr[q];
             float ta = thr[q].x, tb = thr[q].y;
             const int aa = site_update<T>(ta, own.x, own.y, nsum(n.la.x, n.ra.x, n.ua.x, n.da.x),
                                           nsum(n.la.y, n.ra.y, n.ua.y, n.da.y), r.x, r.y, p);
@@ -201,7 +220,7 @@ __device__ __forceinline__ void tile1_update(const T1Geom& g, float2* __restrict
         const int y = g.y0 - 1 + e_row;
         const int o = y & 1;
         const int j = e_k >> 1;            // e_k = kb-1 (odd: words 2, 3) or kb+TX/2 (even: words 0, 1)
-        const u32x4 r = philox10((uint32_t)wrapi(y, g.L) * (uint32_t)g.P + (uint32_t)wrapi(j, g.P), sweep, 0u, 0u,
+        const u32x4 r = philox10(sweep, 0u, 0u, (uint32_t)wrapi(y, g.L) * (uint32_t)g.P + (uint32_t)wrapi(j, g.P),
                                  k0, k1);
         const int b = e_row + 1;           // black row of the same y
         const float2 l = blk[b * S::WS + e_col + o - 1], rt = blk[b * S::WS + e_col + o];
@@ -215,6 +234,13 @@ __device__ __forceinline__ void tile1_update(const T1Geom& g, float2* __restrict
     __syncthreads();
 
     // ---- black half-sweep: interior rows y0 .. y0+TY-1 (black LDS rows 2 .. TY+1)
+    u32x4 rb[S::NQB];
+#pragma unroll
+    for (int q = 0; q < S::NQB; ++q) {
+        const int row = q * S::RP + g.rt;
+        if (row >= 2 && row < TY + 2)
+            rb[q] = philox10(sweep, 1u, 0u, (uint32_t)(g.y0 - 2 + row) * (uint32_t)g.P + jb, k0, k1);
+    }
 #pragma unroll
     for (int q = 0; q < S::NQB; ++q) {
         const int row = q * S::RP + g.rt;
@@ -222,7 +248,7 @@ __device__ __forceinline__ void tile1_update(const T1Geom& g, float2* __restrict
             const int y = g.y0 - 2 + row;  // interior: never wraps
             const PairNb<O> n(cs, S::WS, row - 1, c0);
             const float4 own = *(const float4*)&blk[row * S::WS + c0];
-            const u32x4 r = philox10((uint32_t)y * (uint32_t)g.P + jb, sweep, 1u, 0u, k0, k1);
+            const u32x4 r = rb[q];
             float ta = thb[q].x, tb = thb[q].y;
             float ca = own.x, sa = own.y, cb = own.z, sb = own.w;
             const int aa = site_update<T>(ta, ca, sa, nsum(n.la.x, n.ra.x, n.ua.x, n.da.x),

@@ -431,3 +431,21 @@ def test_long_run_statistics_vs_oracle(orc):
         mu_d, err_d = per.mean(), per.std(ddof=1) / math.sqrt(n)
         mu_o, err_o = mean_err(ov)
         assert abs(mu_d - mu_o) < 3 * math.hypot(err_d, err_o), (name, mu_d, err_d, mu_o, err_o)
+
+
+def test_fp16_storage_statistics_close_to_fp32():
+    """FP16 storage (a coarser, non-uniform angle grid) shifts <e> only slightly: 16
+    replicas of L = 64 at beta = 1, FP16 vs FP32 batches, within 5 sigma + 0.01."""
+    n, L, beta = 16, 64, 1.0
+    res = {}
+    for prec in ("fp32", "fp16"):
+        b = xy.Batch([L] * n, list(range(400, 400 + n)), [beta] * n, [1.0] * n, precision=prec)
+        b.sweep(500)
+        obs = xy.records(b.sweep(3000, 5))
+        b.status()
+        e = (-(obs["cx"] + obs["cy"]) / (L * L)).mean(axis=1)
+        res[prec] = (e.mean(), e.std(ddof=1) / math.sqrt(n))
+    d = res["fp16"][0] - res["fp32"][0]
+    err = math.hypot(res["fp16"][1], res["fp32"][1])
+    print("FP16 - FP32 <e> = %.5f +- %.5f" % (d, err))
+    assert abs(d) < 5 * err + 0.01
