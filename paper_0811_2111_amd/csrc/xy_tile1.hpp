@@ -126,6 +126,7 @@ __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >
 template <int O>
 struct PairNb {
     float2 la, ra, lb, rb, ua, ub, da, db;
+    PairNb() = default;
     __device__ __forceinline__ PairNb(const float2* __restrict__ plane, int WS, int row, int c0)
     {
         const float4 h = *(const float4*)&plane[row * WS + c0];
@@ -164,43 +165,68 @@ __device__ __forceinline__ void meas_acc(MeasAcc& m, float cb, float sb, float2 
 }
 
 // Per-thread geometry shared by both phases.
+//
+// Work items are pairs of a core half-row.  A pass of the workgroup covers RP
+// rows; item q of a thread lies in row 1 + q*RP + rt of the red plane (rows
+// wrap: RR -> 0) and in row 2 + q*RP + rt of the black plane (RB, RB+1 -> 0, 1).
+// So the first TY/RP passes cover exactly the tile interior and need no bounds
+// test (their Philox chains share one basic block and interleave), and only the
+// last pass carries the halo rows.  rt has the parity of the wave, so every row a
+// wave touches in one plane has the same parity.
 struct T1Geom {
     int L, Hh, P, kb, y0, x0;
     int s;           // pair slot within a core half-row
-    int rt;          // row of this thread's first item; items q add q * RP rows
+    int rt;          // row offset of this thread within a pass
     bool edge_tile;  // rows wrap around the lattice
 };
 
-template <typename T, int TX, int TY, int NT, int O, bool MEAS>
-__device__ __forceinline__ void tile1_update(const T1Geom& g, float2* __restrict__ cs, float2 (&thr)[Tile1<TX, TY, NT>::NQR],
-                                             float2 (&thb)[Tile1<TX, TY, NT>::NQB], __amdgpu_buffer_rsrc_t dst,
-                                             uint32_t sweep, uint32_t k0, uint32_t k1, const Params& p,
-                                             float the, int e, int e_row, int e_col, int e_red, int e_k,
-                                             int& acc, MeasAcc& m)
+template <typename S> __device__ __forceinline__ bool red_valid(const T1Geom& g, int q)
+{
+    return q < S::RR / S::RP || q * S::RP + g.rt < S::RR;
+}
+template <typename S> __device__ __forceinline__ int red_row(const T1Geom& g, int q)
+{
+    const int r = 1 + q * S::RP + g.rt;
+    return (q < S::RR / S::RP - 1 || r < S::RR) ? r : r - S::RR;
+}
+template <typename S> __device__ __forceinline__ bool black_valid(const T1Geom& g, int q)
+{
+    return q < S::RB / S::RP || q * S::RP + g.rt < S::RB;
+}
+template <typename S> __device__ __forceinline__ int black_row(const T1Geom& g, int q)
+{
+    const int r = 2 + q * S::RP + g.rt;
+    return (q < S::RB / S::RP - 1 || r < S::RB) ? r : r - S::RB;
+}
+
+// Red half-sweep (rows y0-1 .. y0+TY, columns kb-1 .. kb+TX/2); O = parity of this
+// thread's red rows.
+template <typename T, int TX, int TY, int NT, int O>
+__device__ __forceinline__ void tile1_red(const T1Geom& g, float2* __restrict__ cs, float2 (&thr)[Tile1<TX, TY, NT>::NQR],
+                                          __amdgpu_buffer_rsrc_t dst, uint32_t sweep, uint32_t k0, uint32_t k1,
+                                          const Params& p, float the, int e, int e_row, int e_col, int e_red, int e_k,
+                                          int& acc)
 {
     using S = Tile1<TX, TY, NT>;
+    constexpr int FULL = TY / S::RP;           // passes entirely inside rows 1 .. TY
     const float2* blk = cs + S::BLACK0;
     const int c0 = 2 * g.s + 2;
     const unsigned jb = (unsigned)((g.kb >> 1) + g.s);
-
-    // ---- red half-sweep: rows y0-1 .. y0+TY, columns kb-1 .. kb+TX/2
-    // All of this thread's Philox calls first: independent chains the scheduler
-    // can interleave (each call alone is a serial chain of ten rounds).
+    // All of this thread's Philox calls first: independent ten-round chains the
+    // scheduler interleaves (the interior passes share one basic block).
     u32x4 rr[S::NQR];
 #pragma unroll
     for (int q = 0; q < S::NQR; ++q) {
-        const int row = q * S::RP + g.rt;
-        if (row < S::RR) {
-            const int y = g.y0 - 1 + row;
+        if (red_valid<S>(g, q)) {
+            const int y = g.y0 - 1 + red_row<S>(g, q);
             const int yw = g.edge_tile ? wrapi(y, g.L) : y;
             rr[q] = philox10(sweep, 0u, 0u, (uint32_t)yw * (uint32_t)g.P + jb, k0, k1);
         }
     }
 #pragma unroll
     for (int q = 0; q < S::NQR; ++q) {
-        const int row = q * S::RP + g.rt;
-        if (row < S::RR) {
-            const int y = g.y0 - 1 + row;
+        if (red_valid<S>(g, q)) {
+            const int row = red_row<S>(g, q);
             const PairNb<O> n(blk, S::WS, row + 1, c0);
             float4 own = *(const float4*)&cs[row * S::WS + c0];
             const u32x4 r = rr[q];
@@ -210,9 +236,9 @@ __device__ __forceinline__ void tile1_update(const T1Geom& g, float2* __restrict
             const int ab = site_update<T>(tb, own.z, own.w, nsum(n.lb.x, n.rb.x, n.ub.x, n.db.x),
                                           nsum(n.lb.y, n.rb.y, n.ub.y, n.db.y), r.z, r.w, p);
             *(float4*)&cs[row * S::WS + c0] = own;
-            if (row >= 1 && row <= TY) {
+            if (q < FULL || (row >= 1 && row <= TY)) {
                 acc += aa + ab;
-                bio<T>::st2(dst, (unsigned)y * (unsigned)g.Hh + (unsigned)(g.kb + 2 * g.s), ta, tb);
+                bio<T>::st2(dst, (unsigned)(g.y0 - 1 + row) * (unsigned)g.Hh + (unsigned)(g.kb + 2 * g.s), ta, tb);
             }
         }
     }
@@ -231,20 +257,32 @@ __device__ __forceinline__ void tile1_update(const T1Geom& g, float2* __restrict
                        odd ? r.w : r.y, p);
         cs[e_row * S::WS + e_col] = own;
     }
-    __syncthreads();
+}
 
-    // ---- black half-sweep: interior rows y0 .. y0+TY-1 (black LDS rows 2 .. TY+1)
+// Black half-sweep of the interior rows y0 .. y0+TY-1 (black LDS rows 2 .. TY+1);
+// O = parity of this thread's black rows.
+template <typename T, int TX, int TY, int NT, int O, bool MEAS>
+__device__ __forceinline__ void tile1_black(const T1Geom& g, const float2* __restrict__ cs,
+                                            float2 (&thb)[Tile1<TX, TY, NT>::NQB], __amdgpu_buffer_rsrc_t dst,
+                                            uint32_t sweep, uint32_t k0, uint32_t k1, const Params& p, int& acc,
+                                            MeasAcc& m)
+{
+    using S = Tile1<TX, TY, NT>;
+    constexpr int FULL = TY / S::RP;           // passes entirely inside rows 2 .. TY+1
+    const float2* blk = cs + S::BLACK0;
+    const int c0 = 2 * g.s + 2;
+    const unsigned jb = (unsigned)((g.kb >> 1) + g.s);
     u32x4 rb[S::NQB];
 #pragma unroll
     for (int q = 0; q < S::NQB; ++q) {
-        const int row = q * S::RP + g.rt;
-        if (row >= 2 && row < TY + 2)
+        const int row = black_row<S>(g, q);
+        if (q < FULL || (black_valid<S>(g, q) && row >= 2 && row < TY + 2))
             rb[q] = philox10(sweep, 1u, 0u, (uint32_t)(g.y0 - 2 + row) * (uint32_t)g.P + jb, k0, k1);
     }
 #pragma unroll
     for (int q = 0; q < S::NQB; ++q) {
-        const int row = q * S::RP + g.rt;
-        if (row >= 2 && row < TY + 2) {
+        const int row = black_row<S>(g, q);
+        if (q < FULL || (black_valid<S>(g, q) && row >= 2 && row < TY + 2)) {
             const int y = g.y0 - 2 + row;  // interior: never wraps
             const PairNb<O> n(cs, S::WS, row - 1, c0);
             const float4 own = *(const float4*)&blk[row * S::WS + c0];
@@ -289,8 +327,7 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
         const int lane = tid & 63, w = tid >> 6;
         g.s = lane & (S::TQ - 1);
         const int i = lane >> S::LGQ;
-        // row parity equals the wave's parity, whatever the item
-        g.rt = 2 * (i * (S::NW / 2) + (w >> 1)) + (w & 1);
+        g.rt = 2 * (i * (S::NW / 2) + (w >> 1)) + (w & 1);   // parity of the wave
     }
     g.edge_tile = (y0 < 2) || (y0 + TY + 2 > L);
 
@@ -299,17 +336,17 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     const unsigned col = (unsigned)(g.kb + 2 * g.s);
 #pragma unroll
     for (int q = 0; q < S::NQR; ++q) {
-        const int row = q * S::RP + g.rt;
-        if (row < S::RR) {
-            const int y = g.edge_tile ? wrapi(y0 - 1 + row, L) : y0 - 1 + row;
+        if (red_valid<S>(g, q)) {
+            const int y0r = y0 - 1 + red_row<S>(g, q);
+            const int y = g.edge_tile ? wrapi(y0r, L) : y0r;
             thr[q] = bio<T>::ld2(rs, (unsigned)y * (unsigned)g.Hh + col);
         }
     }
 #pragma unroll
     for (int q = 0; q < S::NQB; ++q) {
-        const int row = q * S::RP + g.rt;
-        if (row < S::RB) {
-            const int y = g.edge_tile ? wrapi(y0 - 2 + row, L) : y0 - 2 + row;
+        if (black_valid<S>(g, q)) {
+            const int y0b = y0 - 2 + black_row<S>(g, q);
+            const int y = g.edge_tile ? wrapi(y0b, L) : y0b;
             thb[q] = bio<T>::ld2(rs, ((unsigned)L + (unsigned)y) * (unsigned)g.Hh + col);
         }
     }
@@ -336,22 +373,20 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     }
 #pragma unroll
     for (int q = 0; q < S::NQR; ++q) {
-        const int row = q * S::RP + g.rt;
-        if (row < S::RR) {
+        if (red_valid<S>(g, q)) {
             float sa, ca, sb, cb;
             sincos_rev(thr[q].x, sa, ca);
             sincos_rev(thr[q].y, sb, cb);
-            *(float4*)&cs[row * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
+            *(float4*)&cs[red_row<S>(g, q) * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
         }
     }
 #pragma unroll
     for (int q = 0; q < S::NQB; ++q) {
-        const int row = q * S::RP + g.rt;
-        if (row < S::RB) {
+        if (black_valid<S>(g, q)) {
             float sa, ca, sb, cb;
             sincos_rev(thb[q].x, sa, ca);
             sincos_rev(thb[q].y, sb, cb);
-            *(float4*)&cs[S::BLACK0 + row * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
+            *(float4*)&cs[S::BLACK0 + black_row<S>(g, q) * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
         }
     }
     if (e < S::NEDGE) {
@@ -363,14 +398,19 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
 
     int acc = 0;
     MeasAcc m;
-    const bool odd_rows = ((y0 - 1 + g.rt) & 1) != 0;   // wave-uniform
+    // wave-uniform (rt has the wave's parity): made scalar so both phases branch per
+    // wave instead of running both parity variants under exec masks
+    const bool red_odd = __builtin_amdgcn_readfirstlane((y0 + g.rt) & 1) != 0;
+    if (red_odd)
+        tile1_red<T, TX, TY, NT, 1>(g, cs, thr, rd, sweep, k0, k1, p, the, e, e_row, e_col, e_red, e_k, acc);
+    else
+        tile1_red<T, TX, TY, NT, 0>(g, cs, thr, rd, sweep, k0, k1, p, the, e, e_row, e_col, e_red, e_k, acc);
+    __syncthreads();
     if (meas) {
-        if (odd_rows)
-            tile1_update<T, TX, TY, NT, 1, true>(g, cs, thr, thb, rd, sweep, k0, k1, p, the, e, e_row, e_col, e_red,
-                                                 e_k, acc, m);
+        if (red_odd)
+            tile1_black<T, TX, TY, NT, 0, true>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
         else
-            tile1_update<T, TX, TY, NT, 0, true>(g, cs, thr, thb, rd, sweep, k0, k1, p, the, e, e_row, e_col, e_red,
-                                                 e_k, acc, m);
+            tile1_black<T, TX, TY, NT, 1, true>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
         double v[7] = {(double)m.cx, (double)m.cy, (double)m.ix, (double)m.iy, (double)m.mx, (double)m.my,
                        (double)acc};
         block_sum7<NT>(v, red);
@@ -380,12 +420,10 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
             part[7] = 0.0;
         }
     } else {
-        if (odd_rows)
-            tile1_update<T, TX, TY, NT, 1, false>(g, cs, thr, thb, rd, sweep, k0, k1, p, the, e, e_row, e_col,
-                                                  e_red, e_k, acc, m);
+        if (red_odd)
+            tile1_black<T, TX, TY, NT, 0, false>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
         else
-            tile1_update<T, TX, TY, NT, 0, false>(g, cs, thr, thb, rd, sweep, k0, k1, p, the, e, e_row, e_col,
-                                                  e_red, e_k, acc, m);
+            tile1_black<T, TX, TY, NT, 1, false>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
     }
 }
 

@@ -67,7 +67,13 @@ def oracle_run(args):
     import oracle
     th = oracle.hot_start(seed, L, "f64")
     oracle.run(seed, th, beta, 1.0, discard, 0, prec="f64")
-    rec = oracle.run(seed, th, beta, 1.0, sweeps, every, sweep0=discard, prec="f64")
+    recs, done, chunk = [], 0, 1000
+    while done < sweeps:                   # chunks, so a long run reports progress
+        n = min(chunk, sweeps - done)
+        recs.append(oracle.run(seed, th, beta, 1.0, n, every, sweep0=discard + done, prec="f64"))
+        done += n
+        print("oracle L=%d beta=%s: %d/%d sweeps" % (L, beta, done, sweeps), flush=True)
+    rec = np.concatenate(recs)
     return summarize(*series(rec[:, 2], rec[:, 3], rec[:, 4], rec[:, 5], rec[:, 6], rec[:, 7], L * L, beta))
 
 
