@@ -18,28 +18,51 @@ namespace xyd {
 // The counter is (sweep, colour, purpose, pair): the three uniform words and
 // the key stay in scalar registers and the per-lane pair index enters through
 // the last word, which the first rounds only xor in, so the early rounds are
-// mostly scalar work.  Later rounds cost two v_mad_u64_u32 and four v_xor_b32.
+// mostly scalar work.  From the fifth round on every word is per-lane and a
+// round costs two v_mad_u64_u32 and two three-input xors (v_bitop3_b32 with
+// truth table 0x96 = a ^ b ^ c, which the compiler does not form by itself).
 struct u32x4 {
     uint32_t x, y, z, w;
 };
 
+template <bool VEC>
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    if constexpr (VEC) return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+    else return a ^ b ^ c;
+}
+
+template <int R>
+__device__ __forceinline__ void philox_round(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3,
+                                             uint32_t k0, uint32_t k1)
+{
+    // With a per-lane last counter word, word 1 is uniform up to round 3 and
+    // word 3 up to round 2: until then those xors have two scalar operands,
+    // which the compiler folds with one s_xor (the builtin would need them
+    // both on the vector unit).
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = xor3<(R >= 4)>((uint32_t)(p1 >> 32), c1, k0);
+    const uint32_t n1 = (uint32_t)p1;
+    const uint32_t n2 = xor3<(R >= 3)>((uint32_t)(p0 >> 32), c3, k1);
+    const uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+}
+
 __device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1)
 {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n1 = (uint32_t)p1;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        const uint32_t n3 = (uint32_t)p0;
-        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
-    }
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    philox_round<0>(c0, c1, c2, c3, k0, k1);
+    philox_round<1>(c0, c1, c2, c3, k0 + 1 * W0, k1 + 1 * W1);
+    philox_round<2>(c0, c1, c2, c3, k0 + 2 * W0, k1 + 2 * W1);
+    philox_round<3>(c0, c1, c2, c3, k0 + 3 * W0, k1 + 3 * W1);
+    philox_round<4>(c0, c1, c2, c3, k0 + 4 * W0, k1 + 4 * W1);
+    philox_round<5>(c0, c1, c2, c3, k0 + 5 * W0, k1 + 5 * W1);
+    philox_round<6>(c0, c1, c2, c3, k0 + 6 * W0, k1 + 6 * W1);
+    philox_round<7>(c0, c1, c2, c3, k0 + 7 * W0, k1 + 7 * W1);
+    philox_round<8>(c0, c1, c2, c3, k0 + 8 * W0, k1 + 8 * W1);
+    philox_round<9>(c0, c1, c2, c3, k0 + 9 * W0, k1 + 9 * W1);
     return {c0, c1, c2, c3};
 }
 
