@@ -10,30 +10,35 @@
  * checkerboard single-site Metropolis:
  *
  *   one sweep = every red site ((x+y) even), then every black site; a site
- *   proposes theta' = theta + delta (2 u1 - 1), wrapped into [0, 2 pi), and
+ *   proposes theta' = theta + delta (2 u1 - 1), taken modulo 2 pi, and
  *   accepts iff u2 < exp(-beta dE), dE = -J sum_nn [cos(theta' - theta_j) -
  *   cos(theta - theta_j)].
+ *
+ * Angle unit: the state holds phi = theta / (2 pi) in turns, the argument the
+ * hardware sine and cosine take.  delta is passed in radians and used as
+ * Delta = fl32(delta / (2 pi)) turns.
  *
  * Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed mod 2^32,
  * seed >> 32), one call per two same-colour sites of a half-row: counter =
  * (sweep, colour, purpose, y * P + (k >> 1)) with k the half-row index and
  * P = ceil(L/4); words (X0, X1) for even k and (X2, X3) for odd k; u = (2 (w >> 9)
  * + 1) 2^-24.  Purpose 0 drives the updates, purpose 1 (sweep 0) the hot start
- * theta = 2 pi u.  The stream depends on (seed, site, sweep) only, so every
+ * phi = u (theta = 2 pi u).  The stream depends on (seed, site, sweep) only, so every
  * schedule, tile shape and batch composition gives the same trajectory bit for
  * bit, and a run can be resumed from a saved state and sweep counter.
  *
- * FP32 proposal arithmetic, rounded exactly as written: step = fl(delta_f * r),
- * t = fl(theta + step), t < 0 -> fl(t + 2pi_f), t >= 2pi_f -> fl(t - 2pi_f),
- * with delta_f and 2pi_f the FP32 roundings of delta and 2 pi.  FP16 storage
- * (XY_FP16) rounds t to IEEE binary16 (nearest-even) before dE is evaluated.
+ * FP32 proposal arithmetic, rounded exactly as written: step = fl(Delta * r),
+ * t = fl(phi + step), phi' = fl(t - floor(t)), and phi' = 1 - 2^-24 where that
+ * rounds to 1 (t a tiny negative number), so FP32 angles stay in [0, 1).  FP16
+ * storage (XY_FP16) rounds phi' to IEEE binary16 (nearest-even; this may give
+ * 1.0) before dE is evaluated.
  * Energies and decisions are FP32 on the device; observables are accumulated
  * in FP64 (the paper's "global sums of the energy", section 1.2).
  *
  * State layout (device memory, owned by the caller): two half-lattices,
  * colour c = 0 (red) then c = 1 (black), each L rows of L/2 entries, row-major:
  *     elem(c, y, k) = state[(c * L + y) * (L/2) + k],  x = 2k + ((c + y) & 1),
- * stored as float (XY_FP32) or IEEE binary16 (XY_FP16), radians in [0, 2 pi).
+ * stored as float (XY_FP32) or IEEE binary16 (XY_FP16), turns in [0, 1] (FP32: [0, 1)).
  *
  * Conventions for every function:
  *   - returns XY_OK (0) or a negative error code; nothing throws or aborts;
@@ -110,9 +115,9 @@ typedef struct xy_batch xy_batch;
 int xy_state_bytes(int32_t L, int32_t precision, size_t* state, size_t* workspace);
 
 /* Create a lattice on the caller's stream (hipStream_t passed as void*, NULL =
- * the null stream) and initialise the angles: XY_HOT draws theta = 2 pi u from
- * the purpose-1 stream (formed in FP64, rounded to the storage format; FP16 via
- * FP32), XY_COLD sets theta = 0.  The sweep counter starts at 0.
+ * the null stream) and initialise the angles: XY_HOT draws phi = u from the
+ * purpose-1 stream (exact in FP32; FP16 storage rounds it once), XY_COLD sets
+ * phi = 0.  The sweep counter starts at 0.
  * beta >= 0 finite; 0 < delta <= pi. */
 int xy_init(xy_lattice** out, uint64_t seed, int32_t L, double beta, double delta,
             int32_t start, int32_t precision,

@@ -26,13 +26,19 @@
  *     off the single-precision device for exactly this reason (section 1.2,
  *     "global sums of the energy"); here they are plain FP64 loops.
  *
+ * Angle unit.  A stored angle is phi = theta / (2 pi), in turns, so
+ * theta = 2 pi phi; every cosine and sine below is taken of 2 pi times a
+ * difference of turns (exact in FP64 for FP32 or FP16 values).  The proposal
+ * width delta is given in radians, as in the model, and converted once:
+ * Delta = delta / (2 pi).
+ *
  * Storage precision.  All arithmetic is FP64.  The stored angles may be kept
  * at FP64, or rounded to the stated storage format of the device path (FP32,
  * or IEEE binary16 with FP32 arithmetic for the proposal).  In the rounded
  * modes the proposal is formed by the exact same sequence of roundings the
- * storage format implies (step = rnd(delta * r), theta' = rnd(theta + step),
- * wrap by rnd(theta' +- 2pi)), so a stored state is reproducible bit for bit;
- * energies and decisions stay FP64.
+ * storage format implies (step = rnd(Delta * r), t = rnd(phi + step), wrap by
+ * rnd(t - floor(t)) kept below 1), so a stored state is reproducible bit for
+ * bit; energies and decisions stay FP64.
  */
 #include <math.h>
 #include <stdint.h>
@@ -145,24 +151,27 @@ static double round_arith(double v, int prec)
     return (double)(float)v;
 }
 
-static double two_pi_for(int prec)
+/* Wrap t (|t| < 2) into [0, 1): t - floor(t) rounded once in the arithmetic
+ * format, and a result that rounds up to 1 (t a tiny negative number) replaced
+ * by the largest value below 1 of that format. */
+static double wrap_turn(double t, int prec)
 {
-    if (prec == ORC_PREC_F64) return 2.0 * ORC_PI;
-    return (double)(float)(2.0 * ORC_PI);
+    double r = round_arith(t - floor(t), prec);   /* the difference is exact in FP64 */
+    double below_one = (prec == ORC_PREC_F64) ? 1.0 - 0x1p-53 : 1.0 - 0x1p-24;
+    return r < 1.0 ? r : below_one;
 }
 
-/* Proposal theta' = theta + delta (2 u1 - 1), wrapped into [0, 2pi): add 2pi
- * if negative, then subtract 2pi if >= 2pi (valid for delta <= pi). */
-double orc_propose(double theta, double delta, double u1, int prec)
+/* Proposal theta' = theta + delta (2 u1 - 1) in turns:
+ * phi' = wrap(phi + Delta (2 u1 - 1)), Delta = delta / (2 pi) (delta <= pi, so
+ * |phi'| < 1.5 before the wrap). */
+double orc_propose(double phi, double delta, double u1, int prec)
 {
     double r = 2.0 * u1 - 1.0;                      /* exact */
-    double d = (prec == ORC_PREC_F64) ? delta : (double)(float)delta;
+    double d = delta / (2.0 * ORC_PI);
+    if (prec != ORC_PREC_F64) d = (double)(float)d;
     double step = round_arith(d * r, prec);
-    double t = round_arith(theta + step, prec);
-    double tp = two_pi_for(prec);
-    if (t < 0.0) t = round_arith(t + tp, prec);
-    if (t >= tp) t = round_arith(t - tp, prec);
-    return round_store(t, prec);
+    double t = round_arith(phi + step, prec);
+    return round_store(wrap_turn(t, prec), prec);
 }
 
 /* ---------------------------------------------------------------------------
@@ -174,25 +183,21 @@ double orc_hot_start_site(uint64_t seed, int L, int x, int y, int prec)
 {
     uint32_t w[2];
     orc_site_words(seed, L, x, y, 0u, 1u, w);
-    double t = 2.0 * ORC_PI * orc_u01(w[0]);
-    if (prec == ORC_PREC_F16) t = orc_round_f16((double)(float)t);
-    else if (prec == ORC_PREC_F32) t = (double)(float)t;
-    return t;
+    return round_store(orc_u01(w[0]), prec);     /* exact for FP64 and FP32 */
 }
 
-/* Hot start: theta = 2 pi u(X_a) from the purpose-1 stream of sweep 0,
- * formed in FP64 and then rounded to the storage format (FP16 storage goes
- * through FP32 first). */
-void orc_hot_start(uint64_t seed, int L, int prec, double* theta)
+/* Hot start: phi = u(X_a), i.e. theta = 2 pi u, from the purpose-1 stream of
+ * sweep 0, rounded to the storage format. */
+void orc_hot_start(uint64_t seed, int L, int prec, double* phi)
 {
     for (int y = 0; y < L; ++y)
         for (int x = 0; x < L; ++x)
-            theta[y * L + x] = orc_hot_start_site(seed, L, x, y, prec);
+            phi[y * L + x] = orc_hot_start_site(seed, L, x, y, prec);
 }
 
 /* ---------------------------------------------------------------------------
- * Observables (FP64, plain loops): bonds (x,y)-(x+1,y) and (x,y)-(x,y+1),
- * periodic, each counted once.
+ * Observables (FP64, plain loops) of the angles theta = 2 pi phi: bonds
+ * (x,y)-(x+1,y) and (x,y)-(x,y+1), periodic, each counted once.
  *   out[0] Cx = sum cos(theta(x,y) - theta(x+1,y))
  *   out[1] Cy = sum cos(theta(x,y) - theta(x,y+1))
  *   out[2] Ix = sum sin(theta(x,y) - theta(x+1,y))
@@ -200,35 +205,35 @@ void orc_hot_start(uint64_t seed, int L, int prec, double* theta)
  *   out[4] Mx = sum cos theta,  out[5] My = sum sin theta
  * E = -J (Cx + Cy).
  * ------------------------------------------------------------------------- */
-void orc_measure(int L, const double* theta, double out[6])
+void orc_measure(int L, const double* phi, double out[6])
 {
     double cx = 0, cy = 0, ix = 0, iy = 0, mx = 0, my = 0;
     for (int y = 0; y < L; ++y)
         for (int x = 0; x < L; ++x) {
-            double t = theta[y * L + x];
-            double tr = theta[y * L + (x + 1) % L];
-            double td = theta[((y + 1) % L) * L + x];
-            cx += cos(t - tr);
-            cy += cos(t - td);
-            ix += sin(t - tr);
-            iy += sin(t - td);
-            mx += cos(t);
-            my += sin(t);
+            double t = phi[y * L + x];
+            double tr = phi[y * L + (x + 1) % L];
+            double td = phi[((y + 1) % L) * L + x];
+            cx += cos(2.0 * ORC_PI * (t - tr));
+            cy += cos(2.0 * ORC_PI * (t - td));
+            ix += sin(2.0 * ORC_PI * (t - tr));
+            iy += sin(2.0 * ORC_PI * (t - td));
+            mx += cos(2.0 * ORC_PI * t);
+            my += sin(2.0 * ORC_PI * t);
         }
     out[0] = cx; out[1] = cy; out[2] = ix; out[3] = iy; out[4] = mx; out[5] = my;
 }
 
-double orc_energy(int L, const double* theta)
+double orc_energy(int L, const double* phi)
 {
     double m[6];
-    orc_measure(L, theta, m);
+    orc_measure(L, phi, m);
     return -(m[0] + m[1]);
 }
 
 /* ---------------------------------------------------------------------------
  * One Metropolis site update from explicit inputs: the site's angle t_old and
- * its four neighbours nb[] (any order).  dE = -J sum_nn [cos(theta' - theta_j)
- * - cos(theta - theta_j)]; accept iff u2 < exp(-beta dE).  Writes the angle the
+ * its four neighbours nb[] (any order), in turns.  dE = -J sum_nn
+ * [cos(theta' - theta_j) - cos(theta - theta_j)]; accept iff u2 < exp(-beta dE).  Writes the angle the
  * site holds afterwards, and optionally dE, the threshold T = -ln(u2)/beta (the
  * decision is dE < T), and the proposal.  Returns 1 if accepted.
  * ------------------------------------------------------------------------- */
@@ -243,7 +248,7 @@ int orc_site_update_explicit(uint64_t seed, int L, int x, int y, uint32_t sweep,
     double t_new = orc_propose(t_old, delta, u1, prec);
     double dE = 0.0;
     for (int j = 0; j < 4; ++j)
-        dE -= cos(t_new - nb[j]) - cos(t_old - nb[j]);
+        dE -= cos(2.0 * ORC_PI * (t_new - nb[j])) - cos(2.0 * ORC_PI * (t_old - nb[j]));
     int accept = u2 < exp(-beta * dE);
     if (dE_out) *dE_out = dE;
     if (thr_out) *thr_out = (beta > 0.0) ? -log(u2) / beta : INFINITY;
@@ -253,14 +258,14 @@ int orc_site_update_explicit(uint64_t seed, int L, int x, int y, uint32_t sweep,
 }
 
 static int site_update(uint64_t seed, int L, double beta, double delta, uint32_t sweep,
-                       int prec, double* theta, int x, int y,
+                       int prec, double* phi, int x, int y,
                        double* dE_out, double* thr_out, uint8_t* dec_out, double* prop_out)
 {
     int xl = (x + L - 1) % L, xr = (x + 1) % L;
     int yu = (y + L - 1) % L, yd = (y + 1) % L;
-    double nb[4] = { theta[y * L + xl], theta[y * L + xr], theta[yu * L + x], theta[yd * L + x] };
-    int accept = orc_site_update_explicit(seed, L, x, y, sweep, prec, beta, delta, theta[y * L + x],
-                                          nb, &theta[y * L + x], dE_out, thr_out, prop_out);
+    double nb[4] = { phi[y * L + xl], phi[y * L + xr], phi[yu * L + x], phi[yd * L + x] };
+    int accept = orc_site_update_explicit(seed, L, x, y, sweep, prec, beta, delta, phi[y * L + x],
+                                          nb, &phi[y * L + x], dE_out, thr_out, prop_out);
     if (dec_out) *dec_out = (uint8_t)accept;
     return accept;
 }
@@ -270,7 +275,7 @@ static int site_update(uint64_t seed, int L, double beta, double delta, uint32_t
  * place.  Per-site diagnostic arrays (length L*L, natural layout) may be NULL.
  * Returns the number of accepted proposals. */
 int64_t orc_sweep(uint64_t seed, int L, double beta, double delta, uint32_t sweep, int prec,
-                  double* theta, double* dE, double* thr, uint8_t* dec, double* prop)
+                  double* phi, double* dE, double* thr, uint8_t* dec, double* prop)
 {
     int64_t acc = 0;
     int ncol = (L & 1) ? 1 : 2;
@@ -279,7 +284,7 @@ int64_t orc_sweep(uint64_t seed, int L, double beta, double delta, uint32_t swee
             for (int x = 0; x < L; ++x) {
                 if (ncol == 2 && ((x + y) & 1) != c) continue;
                 int i = y * L + x;
-                acc += site_update(seed, L, beta, delta, sweep, prec, theta, x, y,
+                acc += site_update(seed, L, beta, delta, sweep, prec, phi, x, y,
                                    dE ? &dE[i] : 0, thr ? &thr[i] : 0,
                                    dec ? &dec[i] : 0, prop ? &prop[i] : 0);
             }
@@ -291,15 +296,15 @@ int64_t orc_sweep(uint64_t seed, int L, double beta, double delta, uint32_t swee
  * {absolute sweep count after the sweep, accepts in that sweep,
  *  Cx, Cy, Ix, Iy, Mx, My}.  Returns the number of records written. */
 int64_t orc_run(uint64_t seed, int L, double beta, double delta, uint32_t sweep0,
-                int64_t n_sweeps, int64_t measure_every, int prec, double* theta, double* rec)
+                int64_t n_sweeps, int64_t measure_every, int prec, double* phi, double* rec)
 {
     int64_t nrec = 0;
     for (int64_t j = 1; j <= n_sweeps; ++j) {
         uint32_t s = sweep0 + (uint32_t)(j - 1);
-        int64_t acc = orc_sweep(seed, L, beta, delta, s, prec, theta, 0, 0, 0, 0);
+        int64_t acc = orc_sweep(seed, L, beta, delta, s, prec, phi, 0, 0, 0, 0);
         if (measure_every > 0 && j % measure_every == 0) {
             double m[6];
-            orc_measure(L, theta, m);
+            orc_measure(L, phi, m);
             double* r = rec + 8 * nrec;
             r[0] = (double)(s + 1u); r[1] = (double)acc;
             for (int q = 0; q < 6; ++q) r[2 + q] = m[q];
@@ -310,11 +315,11 @@ int64_t orc_run(uint64_t seed, int L, double beta, double delta, uint32_t sweep0
 }
 
 /* ---------------------------------------------------------------------------
- * q-state clock restriction: theta = 2 pi k / q.  The proposal moves to one
+ * q-state clock restriction: theta = 2 pi k / q, i.e. phi = k / q turns.  The proposal moves to one
  * of the q-1 other states uniformly, k' = (k + 1 + floor(u1 (q-1))) mod q,
  * which is symmetric; acceptance as above.  Same sweep order and streams.
  * ------------------------------------------------------------------------- */
-static double clock_angle(int k, int q) { return 2.0 * ORC_PI * (double)k / (double)q; }
+static double clock_angle(int k, int q) { return (double)k / (double)q; }
 
 int64_t orc_clock_sweep(uint64_t seed, int L, int q, double beta, uint32_t sweep, int32_t* ks)
 {
@@ -334,8 +339,8 @@ int64_t orc_clock_sweep(uint64_t seed, int L, int q, double beta, uint32_t sweep
                 int nb[4] = { ks[y * L + xl], ks[y * L + xr], ks[yu * L + x], ks[yd * L + x] };
                 double dE = 0.0;
                 for (int j = 0; j < 4; ++j)
-                    dE -= cos(clock_angle(kn, q) - clock_angle(nb[j], q))
-                        - cos(clock_angle(k, q) - clock_angle(nb[j], q));
+                    dE -= cos(2.0 * ORC_PI * (clock_angle(kn, q) - clock_angle(nb[j], q)))
+                        - cos(2.0 * ORC_PI * (clock_angle(k, q) - clock_angle(nb[j], q)));
                 if (u2 < exp(-beta * dE)) { ks[y * L + x] = kn; ++acc; }
             }
     return acc;

@@ -161,7 +161,7 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
                 }
             }
             const int a = max(t0, d.first_tile), b = min(t1, d.first_tile + d.ntiles);
-            const Params prm{d.delta, 6.283185307179586f, d.nbl2e};
+            const Params prm{d.delta, d.nbl2e};
             for (int t = a; t < b; ++t) {
                 const int lt = t - d.first_tile;
                 const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;

@@ -86,13 +86,13 @@ __device__ __forceinline__ float sym11(uint32_t w)
 }
 
 // ------------------------------------------------------------- sin / cos / exp
-// theta is always in [0, 2 pi_f), so the hardware transcendental unit, which
-// takes its argument in revolutions, needs no range reduction.
-__device__ __forceinline__ void sincos_rev(float theta, float& s, float& c)
+// Angles are stored in turns, phi = theta / (2 pi), in [0, 1], which is the
+// argument the hardware transcendental unit takes: no scaling, no range
+// reduction.
+__device__ __forceinline__ void sincos_turn(float phi, float& s, float& c)
 {
-    const float rev = __fmul_rn(theta, 0.159154943091895335768883763372514362f);
-    s = __builtin_amdgcn_sinf(rev);
-    c = __builtin_amdgcn_cosf(rev);
+    s = __builtin_amdgcn_sinf(phi);
+    c = __builtin_amdgcn_cosf(phi);
 }
 
 // ------------------------------------------------------------------- storage
@@ -110,27 +110,27 @@ template <> struct store<__half> {
 };
 
 struct Params {
-    float delta;    // FP32 rounding of delta
-    float two_pi;   // FP32 rounding of 2 pi
+    float delta;    // FP32 rounding of delta / (2 pi): the proposal width in turns
     float nbl2e;    // -beta * log2(e), FP32
 };
 
-// One Metropolis update.  (c, s) = (cos, sin) of theta; (sx, sy) = sums of
-// the four neighbours' (cos, sin), formed by the caller as (left + right) +
-// (up + down).  w1 drives the proposal, w2 the acceptance.  Returns 1 if the
-// proposal is accepted; the new angle and its (cos, sin) come back in th, c, s.
+// One Metropolis update.  th is the angle in turns, (c, s) its (cos, sin);
+// (sx, sy) = sums of the four neighbours' (cos, sin), formed by the caller as
+// (left + right) + (up + down).  w1 drives the proposal, w2 the acceptance.
+// The proposal th + delta (2 u1 - 1) is wrapped by v_fract_f32, which returns
+// t - floor(t) rounded once and, where that rounds up to 1 (t a tiny negative
+// number), the largest float below 1.  Returns 1 if the proposal is accepted;
+// the new angle and its (cos, sin) come back in th, c, s.
 template <typename T>
 __device__ __forceinline__ int site_update(float& th, float& c, float& s, float sx, float sy,
                                            uint32_t w1, uint32_t w2, const Params& p,
                                            float* dE_out = nullptr)
 {
     const float step = __fmul_rn(p.delta, sym11(w1));
-    float t = __fadd_rn(th, step);
-    if (t < 0.0f) t = __fadd_rn(t, p.two_pi);
-    if (t >= p.two_pi) t = __fsub_rn(t, p.two_pi);
+    float t = __builtin_amdgcn_fractf(__fadd_rn(th, step));
     t = store<T>::rnd(t);
     float sn, cn;
-    sincos_rev(t, sn, cn);
+    sincos_turn(t, sn, cn);
     const float dc = __fsub_rn(cn, c);
     const float ds = __fsub_rn(sn, s);
     const float dE = -__fmaf_rn(dc, sx, __fmul_rn(ds, sy));

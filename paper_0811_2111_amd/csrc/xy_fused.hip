@@ -59,7 +59,7 @@ static hipError_t run_fused(const SweepArgs& a, unsigned meas_mask, double* part
         attr_set = true;
     }
     const int ntiles = (a.L / TX) * (a.L / TY);
-    const Params p{a.delta, a.two_pi, a.nbl2e};
+    const Params p{a.delta, a.nbl2e};
     hipLaunchKernelGGL(kern, dim3(ntiles), dim3(NT), lds, s, (const T*)a.src, (T*)a.dst,
                        a.L, a.sweep, a.key0, a.key1, p, meas_mask, partials);
     return hipGetLastError();

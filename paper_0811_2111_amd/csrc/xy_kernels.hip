@@ -72,12 +72,9 @@ __global__ void __launch_bounds__(256) k_init(T* __restrict__ st, int L, uint32_
         return;
     }
     const u32x4 r = philox10(0u, (uint32_t)c, 1u, (uint32_t)(y * P + j), k0, k1);
-    // theta = 2 pi u formed in FP64, then rounded to FP32 (and on to binary16)
-    const double two_pi = 6.283185307179586476925286766559;
-    const double ua = (double)((((r.x >> 9) << 1) | 1u)) * 0x1p-24;
-    const double ub = (double)((((r.z >> 9) << 1) | 1u)) * 0x1p-24;
-    row[ka] = store<T>::st((float)(two_pi * ua));
-    if (kb < Hh) row[kb] = store<T>::st((float)(two_pi * ub));
+    // phi = u (theta = 2 pi u), exact in FP32; binary16 storage rounds it once
+    row[ka] = store<T>::st(u01(r.x));
+    if (kb < Hh) row[kb] = store<T>::st(u01(r.z));
 }
 
 hipError_t launch_init(void* st, int L, int precision, uint32_t k0, uint32_t k1, int hot, hipStream_t s)
@@ -140,17 +137,17 @@ k_half_sweep(T* __restrict__ st, int L, int col, uint32_t sweep, uint32_t k0, ui
         const float ua = store<T>::ld(up[ka]), ub = store<T>::ld(up[kb]);
         const float da = store<T>::ld(dn[ka]), db = store<T>::ld(dn[kb]);
         float s0, c0, s1, c1, s2, c2, sua, cua, sub, cub, sda, cda, sdb, cdb;
-        sincos_rev(h0, s0, c0);
-        sincos_rev(h1, s1, c1);
-        sincos_rev(h2, s2, c2);
-        sincos_rev(ua, sua, cua);
-        sincos_rev(ub, sub, cub);
-        sincos_rev(da, sda, cda);
-        sincos_rev(db, sdb, cdb);
+        sincos_turn(h0, s0, c0);
+        sincos_turn(h1, s1, c1);
+        sincos_turn(h2, s2, c2);
+        sincos_turn(ua, sua, cua);
+        sincos_turn(ub, sub, cub);
+        sincos_turn(da, sda, cda);
+        sincos_turn(db, sdb, cdb);
         const u32x4 r = philox10(sweep, (uint32_t)col, 0u, (uint32_t)(y * P + j), k0, k1);
         float tha = store<T>::ld(own[ka]);
         float sa, ca;
-        sincos_rev(tha, sa, ca);
+        sincos_turn(tha, sa, ca);
         float dEa;
         const int acca = site_update<T>(tha, ca, sa, nsum(c0, c1, cua, cda), nsum(s0, s1, sua, sda),
                                         r.x, r.y, p, &dEa);
@@ -162,7 +159,7 @@ k_half_sweep(T* __restrict__ st, int L, int col, uint32_t sweep, uint32_t k0, ui
         if (has_b) {
             float thb = store<T>::ld(own[kb]);
             float sb, cb;
-            sincos_rev(thb, sb, cb);
+            sincos_turn(thb, sb, cb);
             float dEb;
             const int accb = site_update<T>(thb, cb, sb, nsum(c1, c2, cub, cdb), nsum(s1, s2, sub, sdb),
                                             r.z, r.w, p, &dEb);
@@ -183,7 +180,7 @@ hipError_t launch_half_sweep(const SweepArgs& a, int colour, unsigned long long*
 {
     const int P = ((a.L >> 1) + 1) >> 1;
     dim3 grid((P + 63) / 64, (a.L + 3) / 4), block(64, 4);
-    const Params p{a.delta, a.two_pi, a.nbl2e};
+    const Params p{a.delta, a.nbl2e};
     if (a.precision == XY_FP16)
         hipLaunchKernelGGL(k_half_sweep<__half>, grid, block, 0, s, (__half*)a.dst, a.L, colour, a.sweep,
                            a.key0, a.key1, p, counter, dbg_acc, dbg_dE);
@@ -238,11 +235,11 @@ __global__ void __launch_bounds__(256) k_measure(const T* __restrict__ st, int L
         for (int q = 0; q < (has_b ? 2 : 1); ++q) {
             const int k = ka + q;
             float sb, cb, sl, cl, sr, cr, su, cu, sd, cd;
-            sincos_rev(store<T>::ld(own[k]), sb, cb);
-            sincos_rev(store<T>::ld(oth[wrapk(k + o - 1, Hh)]), sl, cl);
-            sincos_rev(store<T>::ld(oth[wrapk(k + o, Hh)]), sr, cr);
-            sincos_rev(store<T>::ld(up[k]), su, cu);
-            sincos_rev(store<T>::ld(dn[k]), sd, cd);
+            sincos_turn(store<T>::ld(own[k]), sb, cb);
+            sincos_turn(store<T>::ld(oth[wrapk(k + o - 1, Hh)]), sl, cl);
+            sincos_turn(store<T>::ld(oth[wrapk(k + o, Hh)]), sr, cr);
+            sincos_turn(store<T>::ld(up[k]), su, cu);
+            sincos_turn(store<T>::ld(dn[k]), sd, cd);
             meas_black(m, cb, sb, cl, sl, cr, sr, cu, su, cd, sd);
         }
         v[0] += (double)m.cx; v[1] += (double)m.cy; v[2] += (double)m.ix;

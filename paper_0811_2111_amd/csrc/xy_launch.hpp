@@ -16,7 +16,7 @@ struct SweepArgs {
     int precision;      // XY_FP32 / XY_FP16
     uint32_t key0, key1;
     uint32_t sweep;     // absolute index of the (first) sweep
-    float delta, two_pi, nbl2e;
+    float delta, nbl2e;   // proposal width in turns (FP32), -beta log2(e)
 };
 
 // Workspace carve-up shared by the runtime and the launchers.

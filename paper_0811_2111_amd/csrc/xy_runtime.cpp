@@ -42,8 +42,7 @@ xyk::SweepArgs sweep_args(uint64_t seed, int L, int precision, double beta, doub
     a.key0 = (uint32_t)(seed & 0xffffffffu);
     a.key1 = (uint32_t)(seed >> 32);
     a.sweep = 0;
-    a.delta = (float)delta;
-    a.two_pi = (float)(2.0 * M_PI);
+    a.delta = (float)(delta / (2.0 * M_PI));   // radians -> turns, rounded once to FP32
     a.nbl2e = (float)(-beta * 1.4426950408889634073599246810018921);
     return a;
 }

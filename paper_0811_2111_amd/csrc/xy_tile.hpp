@@ -157,7 +157,7 @@ __device__ __forceinline__ void tile_program(const T* __restrict__ src, T* __res
         const int k = wrap1(kb - M + w, Hh);
         const float t = store<T>::ld(src[((size_t)c * L + y) * Hh + k]);
         float s_, c_;
-        sincos_rev(t, s_, c_);
+        sincos_turn(t, s_, c_);
         th[idx] = t;
         cs[idx] = make_float2(c_, s_);
     }

@@ -375,8 +375,8 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     for (int q = 0; q < S::NQR; ++q) {
         if (red_valid<S>(g, q)) {
             float sa, ca, sb, cb;
-            sincos_rev(thr[q].x, sa, ca);
-            sincos_rev(thr[q].y, sb, cb);
+            sincos_turn(thr[q].x, sa, ca);
+            sincos_turn(thr[q].y, sb, cb);
             *(float4*)&cs[red_row<S>(g, q) * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
         }
     }
@@ -384,14 +384,14 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     for (int q = 0; q < S::NQB; ++q) {
         if (black_valid<S>(g, q)) {
             float sa, ca, sb, cb;
-            sincos_rev(thb[q].x, sa, ca);
-            sincos_rev(thb[q].y, sb, cb);
+            sincos_turn(thb[q].x, sa, ca);
+            sincos_turn(thb[q].y, sb, cb);
             *(float4*)&cs[S::BLACK0 + black_row<S>(g, q) * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
         }
     }
     if (e < S::NEDGE) {
         float s_, c_;
-        sincos_rev(the, s_, c_);
+        sincos_turn(the, s_, c_);
         cs[(e_red ? 0 : S::BLACK0) + e_row * S::WS + e_col] = make_float2(c_, s_);
     }
     __syncthreads();

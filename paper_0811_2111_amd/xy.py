@@ -159,7 +159,10 @@ def _nbytes(t):
 
 
 class Lattice:
-    """One L x L lattice: angles and workspace in torch device tensors, sweeps in HIP."""
+    """One L x L lattice: angles and workspace in torch device tensors, sweeps in HIP.
+
+    ``state`` holds the angles in turns, phi = theta / (2 pi) in [0, 1], in the
+    half-lattice layout (2, L, L/2); ``delta`` is the proposal width in radians."""
 
     def __init__(self, L: int, seed: int = 1, beta: float = 1.0, delta: float = 1.0, start="hot",
                  precision="fp32", device="cuda", stream=None, plan=None, state=None, sweep=None):

@@ -265,8 +265,10 @@ def test_full_size_sampled_sites(orc, L, beta, delta):
         nat[yy.expand(-1, L // 2), 2 * kk + ((c + yy) & 1)] = st[c]
     right = torch.roll(nat, -1, 1)
     down = torch.roll(nat, -1, 0)
-    ref = [torch.cos(nat - right).sum(), torch.cos(nat - down).sum(), torch.sin(nat - right).sum(),
-           torch.sin(nat - down).sum(), torch.cos(nat).sum(), torch.sin(nat).sum()]
+    tp = 2 * math.pi                                       # angles are stored in turns
+    ref = [torch.cos(tp * (nat - right)).sum(), torch.cos(tp * (nat - down)).sum(),
+           torch.sin(tp * (nat - right)).sum(), torch.sin(tp * (nat - down)).sum(),
+           torch.cos(tp * nat).sum(), torch.sin(tp * nat).sum()]
     for name, r in zip(["cx", "cy", "ix", "iy", "mx", "my"], ref):
         r = float(r)
         assert abs(float(recs[1][name]) - r) <= obs_tol(r, L * L), (name, float(recs[1][name]), r)
@@ -352,9 +354,9 @@ def test_beta_zero_accepts_all_and_frozen_cold_start():
     cold = xy.Lattice(128, seed=2, beta=1e9, delta=0.5, start="cold")
     r = xy.records(cold.sweep(4, 1))
     assert np.all(r["n_accept"] < 64)
-    th = cold.state.double()
-    dev = torch.minimum(th, 2 * math.pi - th)
-    assert float(dev.max()) < 4e-4
+    th = cold.state.double()                               # turns
+    dev = torch.minimum(th, 1.0 - th)
+    assert float(dev.max()) < 4e-4 / (2 * math.pi)
     assert np.all(-(r["cx"] + r["cy"]) + 2 * 128 * 128 < 1e-4)
 
 

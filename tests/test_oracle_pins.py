@@ -97,64 +97,90 @@ def test_round_f16_matches_ieee_binary16(orc):
         assert orc.round_f16(v) == float(np.float16(v)), v
 
 
+BELOW_ONE_F32 = float(np.nextafter(np.float32(1), np.float32(0)))
+
+
+def f32_wrap(t):
+    """numpy float32 arithmetic: t - floor(t), one float32 rounding, kept below 1."""
+    t = np.float32(t)
+    v = np.float32(t - np.floor(t))
+    return np.float32(BELOW_ONE_F32) if v >= 1 else v
+
+
 @pytest.mark.parametrize("prec", ["f32", "f16"])
 def test_proposal_rounding_matches_ieee_float32_arithmetic(orc, prec):
-    """In the rounded storage modes the proposal is float32(theta + float32(delta r)),
-    wrapped with float32 +- float32(2 pi), then stored; checked against numpy float32."""
+    """In the rounded storage modes the proposal (in turns) is
+    float32(phi + float32(Delta r)) with Delta = float32(delta / 2 pi), wrapped by
+    float32(t - floor(t)) kept below 1, then stored; checked against numpy float32."""
     rng = np.random.default_rng(11)
-    tp32 = np.float32(2 * np.pi)
     for _ in range(3000):
-        th = np.float32(rng.uniform(0, 2 * np.pi))
+        ph = np.float32(rng.uniform(0, 1))
         if prec == "f16":
-            th = np.float32(np.float16(th))
+            ph = np.float32(np.float16(ph))
         delta = float(rng.choice([1.0, 1.2, np.pi, 0.3]))
         w = int(rng.integers(0, 2 ** 32))
         u1 = orc.u01(w)
         r = np.float32(2 * u1 - 1)
-        t = np.float32(th + np.float32(np.float32(delta) * r))
-        if t < 0:
-            t = np.float32(t + tp32)
-        if t >= tp32:
-            t = np.float32(t - tp32)
+        t = np.float32(ph + np.float32(np.float32(delta / (2 * np.pi)) * r))
+        t = f32_wrap(t)
         if prec == "f16":
             t = np.float32(np.float16(t))
-        assert orc.propose(float(th), delta, u1, prec) == float(t)
+        assert orc.propose(float(ph), delta, u1, prec) == float(t)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
 def test_proposal_wrap_edges(orc, prec):
-    """Wrapped proposals stay in [0, 2 pi) at the edges of the angle range."""
-    tp = 2 * np.pi if prec == "f64" else float(np.float32(2 * np.pi))
+    """Wrapped proposals stay in [0, 1) turns at the edges of the angle range
+    (binary16 storage may round a value just below 1 up to 1 itself)."""
     edge_u = [orc.u01(0), orc.u01(0xFFFFFFFF), 0.5 - 2 ** -24, 0.5 + 2 ** -24]
-    edge_t = [0.0, 1e-30, 1e-7, float(np.float32(tp - 4e-7)), float(np.nextafter(np.float32(tp), 0)), 3.0]
-    for th in edge_t:
+    edge_t = [0.0, 1e-30, 1e-7, float(np.float32(1 - 6e-8)), BELOW_ONE_F32, 0.5]
+    for ph in edge_t:
         for u in edge_u:
             for d in [np.pi, 1.0, 1e-6]:
-                v = orc.propose(th, d, u, prec)
-                assert 0.0 <= v < tp, (th, u, d, v)
+                v = orc.propose(ph, d, u, prec)
+                assert 0.0 <= v < 1.0 or (prec == "f16" and v == 1.0), (ph, u, d, v)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16"])
+def test_proposal_tiny_negative_step_wraps_below_one(orc, prec):
+    """phi = 0 moved back by less than half a float32 ulp of 1: t - floor(t) = 1 - tiny
+    rounds to 1 in float32 and is kept at the largest float32 below 1 instead
+    (binary16 storage then rounds that to 1)."""
+    u = orc.u01(0)                      # r = 2u - 1 = -1 + 2^-23
+    v = orc.propose(0.0, 1e-9, u, prec)
+    assert v == (BELOW_ONE_F32 if prec == "f32" else 1.0)
+    # a step of more than one float32 ulp of 1 rounds to an ordinary value below 1
+    v = orc.propose(0.0, 1e-5, u, prec)
+    step = np.float32(np.float32(1e-5 / (2 * np.pi)) * np.float32(2 * u - 1))
+    want = np.float32(np.float32(1) + step)
+    assert v == (float(want) if prec == "f32" else float(np.float16(want)))
 
 
 # ---------------------------------------------------------------- observables
 
 def test_measure_ground_state_and_rotation(orc):
-    """theta = const: E = -2N exactly (2N bonds), |m| = 1, helicity estimator 1."""
+    """phi = const: E = -2N exactly (2N bonds), |m| = 1, helicity estimator 1;
+    M = N (cos 2 pi phi, sin 2 pi phi)."""
     L = 8
     N = L * L
-    for c in [0.0, 1.3, 5.9]:
+    for c in [0.0, 0.21, 0.25, 0.94]:
         m = orc.measure(np.full((L, L), c))
         assert m[0] == N and m[1] == N and m[2] == 0 and m[3] == 0
-        assert math.isclose(m[4], N * math.cos(c), abs_tol=1e-12)
-        assert math.isclose(m[5], N * math.sin(c), abs_tol=1e-12)
+        assert math.isclose(m[4], N * math.cos(2 * math.pi * c), abs_tol=1e-12)
+        assert math.isclose(m[5], N * math.sin(2 * math.pi * c), abs_tol=1e-12)
         assert orc.energy(np.full((L, L), c)) == -2.0 * N
+    m = orc.measure(np.full((L, L), 0.25))      # a quarter turn: M along +y
+    assert abs(m[4]) < 1e-12 and math.isclose(m[5], N, rel_tol=1e-15)
 
 
 def test_measure_spin_wave_closed_form(orc):
-    """theta(x, y) = 2 pi n x / L: Cx = N cos(2 pi n/L), Ix = -N sin(2 pi n/L),
-    Cy = N, Iy = 0, M = 0; the transposed wave swaps the x and y sums."""
+    """theta(x, y) = 2 pi n x / L (phi = n x / L turns): Cx = N cos(2 pi n/L),
+    Ix = -N sin(2 pi n/L), Cy = N, Iy = 0, M = 0; the transposed wave swaps the x
+    and y sums."""
     L, n = 12, 1
     N = L * L
     x = np.arange(L)
-    th = np.tile(2 * np.pi * n * x / L, (L, 1))
+    th = np.tile(n * x / L, (L, 1))
     m = orc.measure(th)
     k = 2 * np.pi * n / L
     np.testing.assert_allclose(m, [N * math.cos(k), N, -N * math.sin(k), 0, 0, 0], atol=1e-9)
@@ -163,10 +189,11 @@ def test_measure_spin_wave_closed_form(orc):
 
 
 def test_measure_antiferromagnet(orc):
-    """theta = pi (x + y): every bond anti-aligned, E = +2N, M = 0."""
+    """theta = pi (x + y), half a turn on every other site: every bond
+    anti-aligned, E = +2N, M = 0."""
     L = 6
     y, x = np.mgrid[0:L, 0:L]
-    m = orc.measure(np.pi * ((x + y) % 2))
+    m = orc.measure(0.5 * ((x + y) % 2))
     np.testing.assert_allclose(m, [-L * L, -L * L, 0, 0, 0, 0], atol=1e-9)
 
 
@@ -177,7 +204,7 @@ def test_measure_single_rotated_site(orc):
     L = 8
     th = np.zeros((L, L))
     a = 0.7
-    th[3, 5] = a
+    th[3, 5] = a / (2 * math.pi)
     m = orc.measure(th)
     N = L * L
     assert math.isclose(-(m[0] + m[1]), -2 * N + 4 * (1 - math.cos(a)), abs_tol=1e-12)
@@ -187,13 +214,14 @@ def test_measure_single_rotated_site(orc):
 # --------------------------------------------------------- sweep structure
 
 def test_hot_start_rounding_modes(orc):
-    """FP32 and FP16 hot starts are the FP64 hot start rounded once (FP16 via FP32)."""
+    """The hot start phi = u lies on the 2^-24 odd grid, exact in FP32; FP16 storage
+    rounds it once."""
     L = 16
     t64 = orc.hot_start(5, L, "f64")
-    assert np.all((t64 >= 0) & (t64 < 2 * np.pi))
-    np.testing.assert_array_equal(orc.hot_start(5, L, "f32"), t64.astype(np.float32).astype(np.float64))
-    np.testing.assert_array_equal(orc.hot_start(5, L, "f16"),
-                                  t64.astype(np.float32).astype(np.float16).astype(np.float64))
+    assert np.all((t64 > 0) & (t64 < 1))
+    assert np.all(np.mod(t64 * 2 ** 24, 2) == 1)
+    np.testing.assert_array_equal(orc.hot_start(5, L, "f32"), t64)
+    np.testing.assert_array_equal(orc.hot_start(5, L, "f16"), t64.astype(np.float16).astype(np.float64))
     assert not np.array_equal(t64, orc.hot_start(6, L, "f64"))
 
 
@@ -207,7 +235,7 @@ def test_checkerboard_red_reads_only_black(orc):
         for s in range(5):
             th0 = orc.hot_start(1 + s, L)
             a = th0.copy(); orc.sweep(1, a, beta, 1.0, s)
-            b = th0.copy(); b[2, 4] = (b[2, 4] + 1.0) % (2 * np.pi)
+            b = th0.copy(); b[2, 4] = (b[2, 4] + 0.16) % 1.0
             orc.sweep(1, b, beta, 1.0, s)
             allowed = np.zeros((L, L), dtype=bool)
             for (yy, xx) in [(2, 4), (1, 4), (3, 4), (2, 3), (2, 5)]:
