@@ -167,10 +167,62 @@ __device__ __forceinline__ void meas_black(Meas& m, float cb, float sb, float cl
 }
 
 // ------------------------------------------------------------ reductions
+// v moved across lanes by a DPP permutation within each row of 16 lanes (both
+// 32-bit halves), on the vector unit instead of through the LDS crossbar.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// As dpp_f64, for the row broadcasts: rows outside ROWS receive 0.0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64_rows(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave, in a fixed order; every lane gets the result.
+// Call with all lanes active.  Within a row of 16 lanes: partner lane ^ 1, ^ 2
+// (quad permutations), then the mirror in each half-row (quad q <-> its other
+// quad) and in the row (half-row <-> half-row); a + b = b + a, so all lanes of a
+// row then hold the same row sum.  The four row sums are read as scalars and
+// added as (r0 + r1) + (r2 + r3).
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// The same sum, valid in lane 63 only (other lanes hold partial sums): after the
+// four steps within rows, row 1 adds row 0 and row 3 adds row 2 (row_bcast:15,
+// the last lane of the row below), then rows 2 and 3 add lane 31 (row_bcast:31),
+// so lane 63 ends with (r2 + r3) + (r0 + r1).  Call with all lanes active.
+__device__ __forceinline__ double wave_sum_last(double v)
+{
+    v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    v += dpp_f64_rows<0x142, 0xA>(v);   // row_bcast:15 into rows 1, 3
+    v += dpp_f64_rows<0x143, 0xC>(v);   // row_bcast:31 into rows 2, 3
     return v;
 }
 

@@ -28,7 +28,10 @@ constexpr size_t fused_lds()
     else return TileShape<TX, TY, M, NT>::lds_bytes;
 }
 
-template <typename T, int TX, int TY, int M, int NT>
+// MEAS (single-sweep tiles only): 1 = this sweep is measured, one partial record
+// per wave (tile-major); 0 = not measured.  The two-sweep tile takes the mask of
+// measured sub-sweeps at run time, one record per tile and sub-sweep.
+template <typename T, int TX, int TY, int M, int NT, int MEAS>
 __global__ void __launch_bounds__(NT)
 k_fused(const T* __restrict__ src, T* __restrict__ dst, int L, uint32_t sweep0, uint32_t k0, uint32_t k1, Params p,
         unsigned meas_mask, double* __restrict__ partials)
@@ -40,19 +43,20 @@ k_fused(const T* __restrict__ src, T* __restrict__ dst, int L, uint32_t sweep0, 
     const int ty = b / tiles_x, tx = b - ty * tiles_x;
     double* red = (double*)(smem + fused_lds<TX, TY, M, NT>());
     if constexpr (M == 1)
-        tile1_program<T, TX, TY, NT>(src, dst, (unsigned)((size_t)L * L * sizeof(T)), L, tx * TX, ty * TY, sweep0,
-                                     k0, k1, p, (meas_mask & 1u) != 0, partials + (size_t)b * 8, smem, red);
+        tile1_program<T, TX, TY, NT, MEAS>(src, dst, (unsigned)((size_t)L * L * sizeof(T)), L, tx * TX, ty * TY,
+                                           sweep0, k0, k1, p, MEAS != 0, partials + (size_t)b * (NT / 64) * 8, smem,
+                                           red);
     else
         tile_program<T, TX, TY, M, NT>(src, dst, L, tx * TX, ty * TY, sweep0, k0, k1, p, meas_mask,
                                        partials + (size_t)b * 8, (size_t)ntiles * 8, smem, red);
 }
 
-template <typename T, int TX, int TY, int M, int NT>
-static hipError_t run_fused(const SweepArgs& a, unsigned meas_mask, double* partials, hipStream_t s)
+template <typename T, int TX, int TY, int M, int NT, int MEAS>
+static hipError_t run_fused_k(const SweepArgs& a, unsigned meas_mask, double* partials, hipStream_t s)
 {
     constexpr size_t lds = fused_lds<TX, TY, M, NT>() + (size_t)(NT / 64) * 7 * sizeof(double);
     static bool attr_set = false;
-    auto kern = k_fused<T, TX, TY, M, NT>;
+    auto kern = k_fused<T, TX, TY, M, NT, MEAS>;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -63,6 +67,17 @@ static hipError_t run_fused(const SweepArgs& a, unsigned meas_mask, double* part
     hipLaunchKernelGGL(kern, dim3(ntiles), dim3(NT), lds, s, (const T*)a.src, (T*)a.dst,
                        a.L, a.sweep, a.key0, a.key1, p, meas_mask, partials);
     return hipGetLastError();
+}
+
+template <typename T, int TX, int TY, int M, int NT>
+static hipError_t run_fused(const SweepArgs& a, unsigned meas_mask, double* partials, hipStream_t s)
+{
+    if constexpr (M == 1) {
+        if (meas_mask & 1u) return run_fused_k<T, TX, TY, M, NT, 1>(a, meas_mask, partials, s);
+        return run_fused_k<T, TX, TY, M, NT, 0>(a, meas_mask, partials, s);
+    } else {
+        return run_fused_k<T, TX, TY, M, NT, -1>(a, meas_mask, partials, s);
+    }
 }
 
 // The tile shapes the autotuner chooses from.
@@ -92,6 +107,12 @@ bool fused_supported(int L, int tile_x, int tile_y, int m)
 }
 
 int fused_tiles(int L, int tile_x, int tile_y) { return (L / tile_x) * (L / tile_y); }
+
+int fused_records(int L, int tile_x, int tile_y, int m)
+{
+    // single-sweep tiles: one record per wave of the 256-thread workgroup
+    return fused_tiles(L, tile_x, tile_y) * (m == 1 ? 4 : 1);
+}
 
 hipError_t launch_fused(const SweepArgs& a, int tile_x, int tile_y, int m, unsigned meas_mask, double* partials,
                         hipStream_t s)

@@ -28,9 +28,10 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int max_partials_for(int L)
 {
-    // enough for one partial per tile of the smallest fused tile (64 x 16) for two
-    // measured sub-sweeps, and for the grid-stride measurement kernel
-    const long long t = 2LL * (long long)L * (long long)L / (64 * 16);
+    // enough for one partial per wave (4 per tile) of the smallest single-sweep
+    // tile (64 x 16), for one per tile and sub-sweep of the two-sweep tiles, and
+    // for the grid-stride measurement kernel
+    const long long t = 4LL * (long long)L * (long long)L / (64 * 16);
     return (int)(t > kMaxPartialsFloor ? t : kMaxPartialsFloor);
 }
 

@@ -55,6 +55,9 @@ hipError_t launch_finalize(const double* partials, int nparts, unsigned long lon
 hipError_t launch_fused(const SweepArgs& a, int tile_x, int tile_y, int m, unsigned meas_mask,
                         double* partials, hipStream_t s);
 int fused_tiles(int L, int tile_x, int tile_y);
+// Partial records one measured sweep of a fused launch writes (the sweep's
+// records start at partials + j * fused_records(...) * 8 for sub-sweep j).
+int fused_records(int L, int tile_x, int tile_y, int m);
 bool fused_supported(int L, int tile_x, int tile_y, int m);
 
 // Fill n u64 words with zero (kernel, not a memset node: safe inside graphs).

@@ -298,7 +298,7 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
     const int m = h->plan.sweeps_per_pass;
     int64_t passes = n_sweeps / m;
     passes -= passes & 1;
-    const int ntiles = xyk::fused_tiles(h->L, h->plan.tile_x, h->plan.tile_y);
+    const int nrec = xyk::fused_records(h->L, h->plan.tile_x, h->plan.tile_y, m);
     int64_t j = 0;  // sweeps done in this call
     for (int64_t q = 0; q < passes; ++q) {
         xyk::SweepArgs a = args_of(h);
@@ -311,7 +311,7 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
         if (e != hipSuccess) return hip_fail(e, "fused sweep launch");
         for (int js = 0; js < m; ++js) {
             if (!(mask & (1u << js))) continue;
-            e = xyk::launch_finalize(h->w.partials + (size_t)js * ntiles * 8, ntiles, nullptr,
+            e = xyk::launch_finalize(h->w.partials + (size_t)js * nrec * 8, nrec, nullptr,
                                      rec_of(j + js + 1), h->sweep + js + 1, h->stream, h->w.chunks);
             if (e != hipSuccess) return hip_fail(e, "finalize launch");
         }

@@ -154,14 +154,16 @@ struct MeasAcc {
 //   sin(tl - tb) + sin(tb - tr) = cb (sl - sr) + sb (cr - cl)
 // and the same with up/down for the y bonds; plus its own spin and that of the red
 // site to its right.
+// Each bond term goes into the FP32 accumulator as two fused multiply-adds; the
+// sums l + r and u + d are the ones the update's neighbour sums already formed.
 __device__ __forceinline__ void meas_acc(MeasAcc& m, float cb, float sb, float2 l, float2 r, float2 u, float2 d)
 {
-    m.cx += __fmaf_rn(cb, __fadd_rn(l.x, r.x), __fmul_rn(sb, __fadd_rn(l.y, r.y)));
-    m.cy += __fmaf_rn(cb, __fadd_rn(u.x, d.x), __fmul_rn(sb, __fadd_rn(u.y, d.y)));
-    m.ix += __fmaf_rn(cb, __fsub_rn(l.y, r.y), __fmul_rn(sb, __fsub_rn(r.x, l.x)));
-    m.iy += __fmaf_rn(cb, __fsub_rn(u.y, d.y), __fmul_rn(sb, __fsub_rn(d.x, u.x)));
-    m.mx += cb + r.x;
-    m.my += sb + r.y;
+    m.cx = __fmaf_rn(sb, __fadd_rn(l.y, r.y), __fmaf_rn(cb, __fadd_rn(l.x, r.x), m.cx));
+    m.cy = __fmaf_rn(sb, __fadd_rn(u.y, d.y), __fmaf_rn(cb, __fadd_rn(u.x, d.x), m.cy));
+    m.ix = __fmaf_rn(sb, __fsub_rn(r.x, l.x), __fmaf_rn(cb, __fsub_rn(l.y, r.y), m.ix));
+    m.iy = __fmaf_rn(sb, __fsub_rn(d.x, u.x), __fmaf_rn(cb, __fsub_rn(u.y, d.y), m.iy));
+    m.mx = __fadd_rn(__fadd_rn(m.mx, cb), r.x);
+    m.my = __fadd_rn(__fadd_rn(m.my, sb), r.y);
 }
 
 // Per-thread geometry shared by both phases.
@@ -304,8 +306,14 @@ __device__ __forceinline__ void tile1_black(const T1Geom& g, const float2* __res
 }
 
 // src/dst: the two state buffers (same layout); `state_bytes` bounds the buffer
-// descriptors.  part: 8 doubles written if `meas` (Cx, Cy, Ix, Iy, Mx, My, accepts, 0).
-template <typename T, int TX, int TY, int NT>
+// descriptors.  MEAS selects the measurement at compile time:
+//   MEAS = 0 : never measure;
+//   MEAS = 1 : always measure, one partial record per wave at part[wave * 8 ..]
+//              (no barrier and no cross-wave step: the records are summed later in
+//              a fixed order);
+//   MEAS = -1: measure if `meas`, one partial record per tile at part[0 .. 8].
+// A record is (Cx, Cy, Ix, Iy, Mx, My, accepts, 0).
+template <typename T, int TX, int TY, int NT, int MEAS = -1>
 __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __restrict__ dst, unsigned state_bytes,
                                               int L, int x0, int y0, uint32_t sweep, uint32_t k0, uint32_t k1,
                                               const Params& p, bool meas, double* part, char* smem, double* red)
@@ -406,18 +414,29 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     else
         tile1_red<T, TX, TY, NT, 0>(g, cs, thr, rd, sweep, k0, k1, p, the, e, e_row, e_col, e_red, e_k, acc);
     __syncthreads();
-    if (meas) {
+    if (MEAS == 1 || (MEAS == -1 && meas)) {
         if (red_odd)
             tile1_black<T, TX, TY, NT, 0, true>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
         else
             tile1_black<T, TX, TY, NT, 1, true>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
         double v[7] = {(double)m.cx, (double)m.cy, (double)m.ix, (double)m.iy, (double)m.mx, (double)m.my,
                        (double)acc};
-        block_sum7<NT>(v, red);
-        if (tid == 0) {
+        if constexpr (MEAS == 1) {
 #pragma unroll
-            for (int q = 0; q < 7; ++q) part[q] = v[q];
-            part[7] = 0.0;
+            for (int q = 0; q < 7; ++q) v[q] = wave_sum_last(v[q]);
+            if ((tid & 63) == 63) {
+                double* w = part + (size_t)(tid >> 6) * 8;
+#pragma unroll
+                for (int q = 0; q < 7; ++q) w[q] = v[q];
+                w[7] = 0.0;
+            }
+        } else {
+            block_sum7<NT>(v, red);
+            if (tid == 0) {
+#pragma unroll
+                for (int q = 0; q < 7; ++q) part[q] = v[q];
+                part[7] = 0.0;
+            }
         }
     } else {
         if (red_odd)

@@ -60,6 +60,11 @@ class XYError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libxyhip.so is not built (%s); run python -m paper_0811_2111_amd.build" % LIB_PATH)
+    # torch first: its bundled HIP runtime carries the soname libamdhip64.so.7, so
+    # the library's dependency then resolves to that same runtime.  Loaded the
+    # other way round, torch would bring a second HIP runtime into the process,
+    # and the library's one would see no device.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, sz, i32, i64, u64, dbl = (ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64,
                                   ctypes.c_uint64, ctypes.c_double)
