@@ -32,10 +32,18 @@ HBM_PEAK_GBS = 8000.0                    # MI355X HBM3E
 # 256 CUs x 128 FP32 lanes x 2.4 GHz = 78.6 T slots/s (the FP32 FMA rate, half of
 # the 157.3 TFLOP/s vector peak).
 VALU_PEAK_TSLOTS = 256 * 128 * 2.4e9 / 1e12
-# Algorithmic VALU slots of one site update (half a Philox4x32-10 call, two uniforms,
-# proposal and wrap, two sin/cos, neighbour sums, dE, exp2 acceptance, selects),
-# with v_mad_u64_u32 = 2 and sin/cos/exp = 4 slots.
-ALG_SLOTS_PER_UPDATE = 90.0
+# Algorithmic VALU slots of one site update of a sweep that reads the angles once
+# (v_mad_u64_u32 = 2 slots, sin/cos/exp = 4, every other instruction 1):
+#   half a Philox4x32-10 call: 16 multiplies + 18 xors per call      25
+#   two uniforms (2 alignbit, fma + add, sub)                         5
+#   proposal: multiply, add, fract                                    3
+#   sin and cos of the proposal                                       8
+#   sin and cos of the site's loaded angle (the (cos, sin) cache)     8
+#   two neighbour sums of four terms                                  6
+#   dE (2 sub, mul, fma)                                              4
+#   acceptance (mul, exp2, compare)                                   6
+#   three selects                                                     3
+ALG_SLOTS_PER_UPDATE = 68.0
 ALG_BYTES_FUSED = 8.0                    # bytes per site-update of one fused sweep: read 4 + write 4 (FP32)
 ALG_BYTES_STREAM = 12.0                  # two half-sweep passes: read both colours, write one, per half
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
