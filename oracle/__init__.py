@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "xy_oracle.c")
+_SRC_HMC = os.path.join(_HERE, "xy_hmc_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PREC_F64, PREC_F32, PREC_F16 = 0, 1, 2
@@ -29,9 +30,11 @@ _PREC = {"f64": PREC_F64, "f32": PREC_F32, "f16": PREC_F16}
 
 def build(force: bool = False) -> str:
     """Compile ``xy_oracle.c`` into ``liboracle.so`` with gcc (single-threaded)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_HMC))
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp,
+                               _SRC, _SRC_HMC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -83,6 +86,24 @@ def lib():
         L.orc_site_update_explicit.restype = ctypes.c_int
         L.orc_hot_start_site.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.orc_hot_start_site.restype = ctypes.c_double
+        L.orc_hmc_momentum.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32]
+        L.orc_hmc_momentum.restype = ctypes.c_double
+        L.orc_hmc_momenta.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_uint32, dp]
+        L.orc_hmc_momenta.restype = None
+        L.orc_hmc_accept_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32]
+        L.orc_hmc_accept_uniform.restype = ctypes.c_double
+        L.orc_hmc_force.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        L.orc_hmc_force.restype = None
+        L.orc_hmc_hamiltonian.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        L.orc_hmc_hamiltonian.restype = ctypes.c_double
+        L.orc_hmc_leapfrog.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
+        L.orc_hmc_leapfrog.restype = ctypes.c_int
+        L.orc_hmc_trajectory.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_uint32, dp, dp, dp]
+        L.orc_hmc_trajectory.restype = ctypes.c_int
+        L.orc_hmc_run.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                  ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64, dp, dp]
+        L.orc_hmc_run.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -203,3 +224,64 @@ def site_update(seed: int, L: int, x: int, y: int, sweep_index: int, beta: float
                                          float(theta), _dp(nb), _dp(out[0:]), _dp(out[1:]), _dp(out[2:]),
                                          _dp(out[3:]))
     return float(out[0]), bool(acc), float(out[1]), float(out[2]), float(out[3])
+
+
+# ------------------------------------------------------------------ HMC
+# Hybrid Monte Carlo trajectories (xy_hmc_oracle.c): angles in turns, momenta
+# in the natural layout, everything FP64.
+
+def hmc_momenta(seed: int, L: int, traj: int) -> np.ndarray:
+    p = np.zeros((L, L), dtype=np.float64)
+    lib().orc_hmc_momenta(seed, L, traj, _dp(p))
+    return p
+
+
+def hmc_momentum(seed: int, L: int, x: int, y: int, traj: int) -> float:
+    return lib().orc_hmc_momentum(seed, L, x, y, traj)
+
+
+def hmc_accept_uniform(seed: int, traj: int) -> float:
+    return lib().orc_hmc_accept_uniform(seed, traj)
+
+
+def hmc_force(phi: np.ndarray, beta: float) -> np.ndarray:
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    F = np.zeros_like(ph)
+    lib().orc_hmc_force(ph.shape[0], beta, _dp(ph), _dp(F))
+    return F
+
+
+def hmc_hamiltonian(phi: np.ndarray, p: np.ndarray, beta: float) -> float:
+    ph = np.ascontiguousarray(phi, dtype=np.float64)
+    pp = np.ascontiguousarray(p, dtype=np.float64)
+    return lib().orc_hmc_hamiltonian(ph.shape[0], beta, _dp(ph), _dp(pp))
+
+
+def hmc_leapfrog(phi: np.ndarray, p: np.ndarray, beta: float, eps: float, n: int) -> None:
+    """n leap-frog steps in place (both arrays float64, C-contiguous)."""
+    assert phi.dtype == np.float64 and p.dtype == np.float64 and phi.flags.c_contiguous and p.flags.c_contiguous
+    if lib().orc_hmc_leapfrog(phi.shape[0], beta, eps, n, _dp(phi), _dp(p)) != 0:
+        raise MemoryError("orc_hmc_leapfrog")
+
+
+def hmc_trajectory(seed: int, phi: np.ndarray, beta: float, eps: float, n: int, traj: int):
+    """One trajectory in place; returns (accepted, dH, H_old)."""
+    assert phi.dtype == np.float64 and phi.flags.c_contiguous
+    out = np.zeros(2)
+    acc = lib().orc_hmc_trajectory(seed, phi.shape[0], beta, eps, n, traj, _dp(phi), _dp(out[0:]), _dp(out[1:]))
+    if acc < 0:
+        raise MemoryError("orc_hmc_trajectory")
+    return bool(acc), float(out[0]), float(out[1])
+
+
+def hmc_run(seed: int, phi: np.ndarray, beta: float, eps: float, n: int, n_traj: int,
+            measure_every: int = 1, traj0: int = 0) -> np.ndarray:
+    """n_traj trajectories in place; records (n_rec, 9):
+    [trajectory count after, accepted, dH, Cx, Cy, Ix, Iy, Mx, My]."""
+    assert phi.dtype == np.float64 and phi.flags.c_contiguous
+    nrec = n_traj // measure_every if measure_every > 0 else 0
+    rec = np.zeros((max(nrec, 1), 9), dtype=np.float64)
+    got = lib().orc_hmc_run(seed, phi.shape[0], beta, eps, n, traj0, n_traj, measure_every, _dp(phi), _dp(rec))
+    if got < 0:
+        raise MemoryError("orc_hmc_run")
+    return rec[:got]
