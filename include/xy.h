@@ -149,6 +149,47 @@ int xy_set_plan(xy_lattice* h, const xy_plan* plan);
 int xy_get_plan(const xy_lattice* h, xy_plan* plan);
 int xy_free(xy_lattice* h);
 
+/* ------------------------------------------------------ hybrid Monte Carlo
+ * The paper's own update (section 1.2): Gaussian momenta converted from flat
+ * random numbers, leap-frog integration of the equations of motion, and a
+ * Metropolis step on global sums of the energy kept in double precision.
+ *
+ *   H = sum_i p_i^2 / 2 + beta E,  E = -sum_<ij> cos(theta_i - theta_j);
+ *   force F_i = -beta sum_{j nn i} sin(theta_i - theta_j);
+ *   trajectory: p_i = sqrt(-2 ln u1) cos(2 pi u2) with (u1, u2) the site's two
+ *   uniforms of Philox purpose 2 (counter word 0 = the trajectory index, same
+ *   site pairing as the Metropolis update); n_md leap-frog steps of size eps
+ *   (p += eps/2 F, theta += eps p, p += eps/2 F; adjacent half kicks merged);
+ *   dH = H_new - H_old from FP64 sums of FP32 per-site terms; accept iff
+ *   u < exp(-dH), u = u(X0) of Philox counter (traj, 0, 3, 0); a rejected
+ *   trajectory leaves the angles as they were.
+ *
+ * Trajectories and Metropolis sweeps share the handle's counter: trajectory t
+ * uses counter word 0 = t and advances the counter by one.  FP32 lattices only.
+ *
+ * One record per trajectory, 72 bytes: */
+typedef struct xy_hmc_obs {
+    uint64_t traj;       /* counter after the trajectory */
+    uint64_t accepted;   /* 1 if accepted */
+    double dH;           /* H_new - H_old */
+    double cx, cy, ix, iy, mx, my;   /* sums as in xy_obs, of the state after the Metropolis step */
+} xy_hmc_obs;
+
+/* Bytes of device workspace xy_hmc needs for an L x L lattice (momenta, saved
+ * angles, partial sums, accept flag): 8 L^2 + 256 + 2 * 4096 * 64. */
+int xy_hmc_work_bytes(int32_t L, size_t* bytes);
+
+/* Run n_traj trajectories of n_md leap-frog steps of size eps (> 0, finite) on
+ * the lattice's angles, on its stream; the lattice workspace's ping-pong buffer
+ * holds the second copy of the angles during a trajectory.  hmc_work: device
+ * memory of at least xy_hmc_work_bytes (caller-owned, contents overwritten).
+ * obs_dev: NULL, or device memory for n_traj records (record j after trajectory
+ * j of the call).  XY_EINVAL for an FP16 lattice, n_traj < 0, n_md < 1 or a bad
+ * eps; XY_ESIZE if hmc_len is too small; XY_ERANGE if the counter would pass
+ * 2^32 - 1. */
+int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
+           xy_hmc_obs* obs_dev);
+
 /* Test support: run ONE sweep with the streaming schedule and write, per site in
  * the state layout (red half then black half), accept_dev[i] = 1/0 and dE_dev[i] =
  * the FP32 energy change of the proposal.  Either output may be NULL. */

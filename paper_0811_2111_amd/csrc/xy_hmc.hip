@@ -1,0 +1,294 @@
+// xy_hmc.hip -- hybrid Monte Carlo trajectories (section 1.2): Gaussian momenta,
+// leap-frog integration of the equations of motion, Metropolis step on FP64
+// global sums of H = sum p^2/2 + beta E, all on the device.
+//
+// Angles are in turns (phi = theta / 2 pi), momenta in radians per unit time,
+// both FP32 in the half-lattice layout of the state.  With
+//     F_i = -beta sum_{j nn i} sin(theta_i - theta_j)
+//         = -beta (s_i sum_j c_j - c_i sum_j s_j),   (c, s) = (cos, sin) theta,
+// one trajectory of n leap-frog steps of size eps is
+//     begin : p = Box-Muller(Philox), saved = phi, H_old partials;
+//     step 1: p += eps/2 F(phi), phi += eps/(2 pi) p     (kick, then drift)
+//     step k: p += eps   F(phi), phi += eps/(2 pi) p     (k = 2 .. n; two half
+//             kicks of neighbouring steps merged)
+//     end   : p += eps/2 F(phi), H_new partials;
+//     decide: dH = H_new - H_old (FP64), accept iff u < exp(-dH);
+//     restore phi = saved if rejected.
+// A step is a Jacobi update (every site from the same old angles), so the
+// angles ping-pong between the state and a second buffer; momenta are local and
+// are updated in place.
+#include <hip/hip_runtime.h>
+
+#include "xy_device.hpp"
+#include "xy_launch.hpp"
+
+using namespace xyd;
+
+namespace xyk {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr float kMinus2Ln2 = -1.38629436111989061883f;   // -2 ln 2
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// Box-Muller, cosine branch: sqrt(-2 ln u1) cos(2 pi u2); the hardware log is
+// base 2 and the hardware cosine takes turns, so 2 pi u2 turns is u2.
+__device__ __forceinline__ float box_muller(uint32_t w1, uint32_t w2)
+{
+    const float r2 = kMinus2Ln2 * __builtin_amdgcn_logf(u01(w1));
+    return __builtin_sqrtf(r2) * __builtin_amdgcn_cosf(u01(w2));
+}
+
+// (cos, sin) of entry (c, y, k) and of its four neighbours in the other plane.
+struct Nb {
+    float c, s;                    // the site
+    float cl, sl, cr, sr, cu, su, cd, sd;
+};
+
+__device__ __forceinline__ Nb load_nb(const float* __restrict__ st, int L, int Hh, int c, int y, int k, float& th)
+{
+    const int o = (c + y) & 1;
+    const float* oth = st + (size_t)(1 - c) * L * Hh;
+    th = st[((size_t)c * L + y) * Hh + k];
+    const float tl = oth[(size_t)y * Hh + wrapi(k + o - 1, Hh)];
+    const float tr = oth[(size_t)y * Hh + wrapi(k + o, Hh)];
+    const float tu = oth[(size_t)wrapi(y - 1, L) * Hh + k];
+    const float td = oth[(size_t)wrapi(y + 1, L) * Hh + k];
+    Nb n;
+    sincos_turn(th, n.s, n.c);
+    sincos_turn(tl, n.sl, n.cl);
+    sincos_turn(tr, n.sr, n.cr);
+    sincos_turn(tu, n.su, n.cu);
+    sincos_turn(td, n.sd, n.cd);
+    return n;
+}
+
+// s_i sum c_j - c_i sum s_j = sum_j sin(theta_i - theta_j); F = -beta times this.
+__device__ __forceinline__ float sin_sum(const Nb& n)
+{
+    const float sc = nsum(n.cl, n.cr, n.cu, n.cd);
+    const float ss = nsum(n.sl, n.sr, n.su, n.sd);
+    return __fmaf_rn(n.s, sc, -__fmul_rn(n.c, ss));
+}
+
+// One partial record per wave: (Cx, Cy, Ix, Iy, Mx, My, K, 0).  Black sites add
+// their four bonds, their own spin and that of the red site to their right (as
+// the Metropolis measurement does); every site adds p^2 / 2.
+__device__ __forceinline__ void write_record(double v[7], double* __restrict__ rec)
+{
+#pragma unroll
+    for (int q = 0; q < 7; ++q) v[q] = wave_sum_last(v[q]);
+    if ((threadIdx.x & 63) == 63) {
+        const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        double* r = rec + (b * (kThreads / 64) + (threadIdx.x >> 6)) * 8;
+#pragma unroll
+        for (int q = 0; q < 7; ++q) r[q] = v[q];
+        r[7] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void accumulate(double v[7], const Nb& n, int c, float kin)
+{
+    if (c == 1) {
+        Meas m{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        meas_black(m, n.c, n.s, n.cl, n.sl, n.cr, n.sr, n.cu, n.su, n.cd, n.sd);
+        v[0] += (double)m.cx; v[1] += (double)m.cy; v[2] += (double)m.ix;
+        v[3] += (double)m.iy; v[4] += (double)m.mx; v[5] += (double)m.my;
+    }
+    v[6] += (double)kin;
+}
+
+// Momenta, saved angles and the partial records of H_old.  Grid (ceil(Hh/256),
+// rows, 2): rows of a colour are taken with stride gridDim.y.
+__global__ void __launch_bounds__(kThreads)
+k_hmc_begin(const float* __restrict__ st, float* __restrict__ p, float* __restrict__ saved, int L, uint32_t traj,
+            uint32_t k0, uint32_t k1, double* __restrict__ rec)
+{
+    const int Hh = L >> 1, P = (Hh + 1) >> 1;
+    const int k = blockIdx.x * kThreads + threadIdx.x;
+    const int c = blockIdx.z;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (k < Hh) {
+        for (int y = blockIdx.y; y < L; y += gridDim.y) {
+            float th;
+            const Nb n = load_nb(st, L, Hh, c, y, k, th);
+            const size_t i = ((size_t)c * L + y) * Hh + k;
+            saved[i] = th;
+            const u32x4 r = philox10(traj, (uint32_t)c, 2u, (uint32_t)y * (uint32_t)P + (uint32_t)(k >> 1), k0, k1);
+            const float pm = (k & 1) ? box_muller(r.z, r.w) : box_muller(r.x, r.y);
+            p[i] = pm;
+            accumulate(v, n, c, __fmul_rn(0.5f, __fmul_rn(pm, pm)));
+        }
+    }
+    write_record(v, rec);                 // every lane reaches the wave sums
+}
+
+// One leap-frog step: kick with `kick` = eps (eps/2 on the first step), then
+// drift by eps/(2 pi) p turns.  Grid (ceil(Hh/256), L, 2).
+__global__ void __launch_bounds__(kThreads)
+k_hmc_step(const float* __restrict__ src, float* __restrict__ dst, float* __restrict__ p, int L, float nbeta_kick,
+           float drift)
+{
+    const int Hh = L >> 1;
+    const int k = blockIdx.x * kThreads + threadIdx.x;
+    if (k >= Hh) return;
+    const int y = blockIdx.y, c = blockIdx.z;
+    float th;
+    const Nb n = load_nb(src, L, Hh, c, y, k, th);
+    const size_t i = ((size_t)c * L + y) * Hh + k;
+    const float pn = __fmaf_rn(nbeta_kick, sin_sum(n), p[i]);
+    p[i] = pn;
+    dst[i] = __builtin_amdgcn_fractf(__fmaf_rn(drift, pn, th));
+}
+
+// Final half kick and the partial records of H_new; `copy` != NULL receives the
+// angles (the final ones may sit in the second buffer).  Grid as k_hmc_begin.
+__global__ void __launch_bounds__(kThreads)
+k_hmc_end(const float* __restrict__ st, float* __restrict__ copy, const float* __restrict__ p, int L,
+          float nbeta_kick, double* __restrict__ rec)
+{
+    const int Hh = L >> 1;
+    const int k = blockIdx.x * kThreads + threadIdx.x;
+    const int c = blockIdx.z;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (k < Hh) {
+        for (int y = blockIdx.y; y < L; y += gridDim.y) {
+            float th;
+            const Nb n = load_nb(st, L, Hh, c, y, k, th);
+            const size_t i = ((size_t)c * L + y) * Hh + k;
+            if (copy) copy[i] = th;
+            const float pn = __fmaf_rn(nbeta_kick, sin_sum(n), p[i]);
+            accumulate(v, n, c, __fmul_rn(0.5f, __fmul_rn(pn, pn)));
+        }
+    }
+    write_record(v, rec);
+}
+
+// Sum of one set of records in a fixed order (thread t: records t, t + 256, ...,
+// then the wave sums and the four waves in order); thread 0 gets the totals.
+__device__ void sum_records(const double* __restrict__ rec, int nrec, double out[7], double* red)
+{
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int r = threadIdx.x; r < nrec; r += kThreads)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) v[q] += rec[(size_t)r * 8 + q];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) red[(threadIdx.x >> 6) * 7 + q] = v[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) out[q] = (red[q] + red[7 + q]) + (red[14 + q] + red[21 + q]);
+    __syncthreads();
+}
+
+// Metropolis step of the trajectory: one workgroup.
+__global__ void __launch_bounds__(kThreads)
+k_hmc_decide(const double* __restrict__ rec_old, const double* __restrict__ rec_new, int nrec, double beta,
+             uint32_t traj, uint32_t k0, uint32_t k1, unsigned* __restrict__ flag, xy_hmc_obs* __restrict__ obs)
+{
+    __shared__ double red[4 * 7];
+    double o[7], n[7];
+    sum_records(rec_old, nrec, o, red);
+    sum_records(rec_new, nrec, n, red);
+    if (threadIdx.x == 0) {
+        const double h_old = o[6] - beta * (o[0] + o[1]);
+        const double h_new = n[6] - beta * (n[0] + n[1]);
+        const double dH = h_new - h_old;
+        const u32x4 r = philox10(traj, 0u, 3u, 0u, k0, k1);
+        const double u = (double)u01(r.x);           // exact in FP32
+        const unsigned acc = u < exp(-dH) ? 1u : 0u;
+        *flag = acc;
+        if (obs) {
+            const double* s = acc ? n : o;
+            obs->traj = (uint64_t)traj + 1u;
+            obs->accepted = acc;
+            obs->dH = dH;
+            obs->cx = s[0]; obs->cy = s[1]; obs->ix = s[2]; obs->iy = s[3]; obs->mx = s[4]; obs->my = s[5];
+        }
+    }
+}
+
+// Rejected trajectory: the saved angles back into the state.
+__global__ void __launch_bounds__(kThreads)
+k_hmc_restore(const unsigned* __restrict__ flag, const float* __restrict__ saved, float* __restrict__ st, size_t n)
+{
+    if (*flag) return;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads)
+        st[i] = saved[i];
+}
+
+}  // namespace
+
+// Rows per colour that the record-writing kernels give each block column: keeps
+// the records of one set at most kHmcMaxRecords.
+static int hmc_row_blocks(int L)
+{
+    const int gx = ((L >> 1) + kThreads - 1) / kThreads;
+    int gy = kHmcMaxRecords / (gx * 2 * (kThreads / 64));
+    if (gy > L) gy = L;
+    return gy < 1 ? 1 : gy;
+}
+
+int hmc_records(int L)
+{
+    const int gx = ((L >> 1) + kThreads - 1) / kThreads;
+    return gx * hmc_row_blocks(L) * 2 * (kThreads / 64);
+}
+
+size_t hmc_work_bytes(int L)
+{
+    const size_t n = (size_t)L * (size_t)L;
+    return 256 + 2 * n * sizeof(float) + 2 * (size_t)kHmcMaxRecords * 8 * sizeof(double);
+}
+
+HmcWork hmc_carve(void* work, int L)
+{
+    HmcWork w;
+    char* b = (char*)work;
+    w.flag = (unsigned*)b;
+    b += 256;
+    const size_t n = (size_t)L * (size_t)L;
+    w.p = (float*)b;
+    b += n * sizeof(float);
+    w.saved = (float*)b;
+    b += n * sizeof(float);
+    w.rec_old = (double*)b;
+    b += (size_t)kHmcMaxRecords * 8 * sizeof(double);
+    w.rec_new = (double*)b;
+    return w;
+}
+
+hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w, int L, double beta, double eps,
+                                 int n_md, uint32_t traj, uint32_t k0, uint32_t k1, xy_hmc_obs* obs, hipStream_t s)
+{
+    const int Hh = L >> 1;
+    const int gx = (Hh + kThreads - 1) / kThreads;
+    const dim3 grec(gx, hmc_row_blocks(L), 2), gstep(gx, L, 2), block(kThreads);
+    const int nrec = hmc_records(L);
+    const float drift = (float)(eps / (2.0 * 3.14159265358979323846));
+    hipLaunchKernelGGL(k_hmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, w.rec_old);
+    float* src = state;
+    float* dst = pingpong;
+    for (int q = 0; q < n_md; ++q) {
+        const float kick = (float)(-beta * (q == 0 ? 0.5 * eps : eps));
+        hipLaunchKernelGGL(k_hmc_step, gstep, block, 0, s, src, dst, w.p, L, kick, drift);
+        float* t = src;
+        src = dst;
+        dst = t;
+    }
+    hipLaunchKernelGGL(k_hmc_end, grec, block, 0, s, src, src == state ? nullptr : state, w.p, L,
+                       (float)(-beta * 0.5 * eps), w.rec_new);
+    hipLaunchKernelGGL(k_hmc_decide, dim3(1), block, 0, s, w.rec_old, w.rec_new, nrec, beta, traj, k0, k1, w.flag,
+                       obs);
+    const size_t n = (size_t)L * (size_t)L;
+    const unsigned nb = (unsigned)((n + kThreads * 8 - 1) / (kThreads * 8));
+    hipLaunchKernelGGL(k_hmc_restore, dim3(nb < 4096 ? nb : 4096), block, 0, s, w.flag, w.saved, state, n);
+    return hipGetLastError();
+}
+
+}  // namespace xyk

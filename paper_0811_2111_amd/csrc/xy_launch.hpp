@@ -58,6 +58,23 @@ int fused_tiles(int L, int tile_x, int tile_y);
 // Partial records one measured sweep of a fused launch writes (the sweep's
 // records start at partials + j * fused_records(...) * 8 for sub-sweep j).
 int fused_records(int L, int tile_x, int tile_y, int m);
+
+// ---- hybrid Monte Carlo (xy_hmc.hip)
+constexpr int kHmcMaxRecords = 4096;    // partial records of one H sum (old or new)
+struct HmcWork {
+    unsigned* flag;     // accept flag of the last trajectory
+    float* p;           // momenta, state layout
+    float* saved;       // angles at the start of the trajectory
+    double* rec_old;    // partial records of H_old (8 doubles each)
+    double* rec_new;    // partial records of H_new
+};
+size_t hmc_work_bytes(int L);
+HmcWork hmc_carve(void* work, int L);
+int hmc_records(int L);
+// One trajectory from the FP32 angles in `state` (result back in `state`),
+// `pingpong` a second state-sized buffer; record to obs if not NULL.
+hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w, int L, double beta, double eps,
+                                 int n_md, uint32_t traj, uint32_t k0, uint32_t k1, xy_hmc_obs* obs, hipStream_t s);
 bool fused_supported(int L, int tile_x, int tile_y, int m);
 
 // Fill n u64 words with zero (kernel, not a memset node: safe inside graphs).

@@ -336,6 +336,33 @@ int xy_measure(xy_lattice* h, xy_obs* obs_dev)
     return XY_OK;
 }
 
+int xy_hmc_work_bytes(int32_t L, size_t* bytes)
+{
+    if (!valid_L(L)) return XY_EINVAL;
+    if (bytes) *bytes = xyk::hmc_work_bytes(L);
+    return XY_OK;
+}
+
+int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
+           xy_hmc_obs* obs_dev)
+{
+    if (!live(h)) return XY_ESTATE;
+    if (h->precision != XY_FP32 || n_traj < 0 || n_md < 1 || !std::isfinite(eps) || !(eps > 0.0)) return XY_EINVAL;
+    if (!hmc_work) return XY_ESTATE;
+    if (hmc_len < xyk::hmc_work_bytes(h->L)) return XY_ESIZE;
+    if (h->sweep + (uint64_t)n_traj >= 0xffffffffull) return XY_ERANGE;
+    const xyk::HmcWork w = xyk::hmc_carve(hmc_work, h->L);
+    const uint32_t k0 = (uint32_t)(h->seed & 0xffffffffu), k1 = (uint32_t)(h->seed >> 32);
+    for (int64_t j = 0; j < n_traj; ++j) {
+        hipError_t e = xyk::launch_hmc_trajectory((float*)h->state, (float*)h->w.pingpong, w, h->L, h->beta, eps,
+                                                  n_md, (uint32_t)h->sweep, k0, k1, obs_dev ? obs_dev + j : nullptr,
+                                                  h->stream);
+        if (e != hipSuccess) return hip_fail(e, "hmc trajectory launch");
+        h->sweep += 1;
+    }
+    return XY_OK;
+}
+
 int xy_set_params(xy_lattice* h, double beta, double delta)
 {
     if (!live(h)) return XY_ESTATE;

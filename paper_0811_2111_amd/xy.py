@@ -46,6 +46,8 @@ class xy_plan(ctypes.Structure):
 
 OBS_DTYPE = np.dtype([("sweep", "<u8"), ("n_accept", "<u8"), ("cx", "<f8"), ("cy", "<f8"),
                       ("ix", "<f8"), ("iy", "<f8"), ("mx", "<f8"), ("my", "<f8")])
+HMC_DTYPE = np.dtype([("traj", "<u8"), ("accepted", "<u8"), ("dH", "<f8"), ("cx", "<f8"), ("cy", "<f8"),
+                      ("ix", "<f8"), ("iy", "<f8"), ("mx", "<f8"), ("my", "<f8")])
 
 
 class XYError(RuntimeError):
@@ -94,6 +96,8 @@ def _load():
         "xy_batch_autotune": [vp, i32, P(i32), P(i32)],
         "xy_batch_status": [vp],
         "xy_batch_free": [vp],
+        "xy_hmc_work_bytes": [i32, P(sz)],
+        "xy_hmc": [vp, i64, i32, dbl, vp, sz, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -146,6 +150,18 @@ def records(obs) -> np.ndarray:
     import torch
     host = obs.detach().to("cpu").contiguous()
     return host.numpy().view(np.uint8).view(OBS_DTYPE).reshape(host.shape[:-1])
+
+
+def hmc_records(obs) -> np.ndarray:
+    """Copy a device tensor of xy_hmc_obs records (n, 9) to a host structured array."""
+    host = obs.detach().to("cpu").contiguous()
+    return host.numpy().view(np.uint8).view(HMC_DTYPE).reshape(host.shape[:-1])
+
+
+def xy_hmc_work_bytes(L: int) -> int:
+    b = ctypes.c_size_t()
+    check(_lib.xy_hmc_work_bytes(L, ctypes.byref(b)), "xy_hmc_work_bytes")
+    return b.value
 
 
 def _stream_handle(stream):
@@ -212,6 +228,19 @@ class Lattice:
         rc = _lib.xy_sweep(self.h, int(n), int(measure_every), _ptr(out) if nrec else None)
         check(rc, "xy_sweep")
         return out
+
+    def hmc(self, n_traj: int, n_md: int, eps: float, out=None):
+        """n_traj HMC trajectories of n_md leap-frog steps of size eps; returns a
+        device tensor (n_traj, 9) of xy_hmc_obs records (see hmc_records)."""
+        import torch
+        if getattr(self, "hmc_work", None) is None:
+            self.hmc_work = torch.empty((xy_hmc_work_bytes(self.L),), dtype=torch.uint8, device=self.state.device)
+        if out is None:
+            out = torch.empty((max(int(n_traj), 1), 9), dtype=torch.float64, device=self.state.device)
+        rc = _lib.xy_hmc(self.h, int(n_traj), int(n_md), float(eps), _ptr(self.hmc_work), _nbytes(self.hmc_work),
+                         _ptr(out) if n_traj > 0 else None)
+        check(rc, "xy_hmc")
+        return out[: int(n_traj)]
 
     def measure(self, out=None):
         import torch

@@ -1,0 +1,167 @@
+"""HMC on the device (xy_hmc through the C ABI) against the FP64 HMC oracle.
+
+The oracle integrates in FP64 from the same FP32 hot start and the same Philox
+words; the device integrates in FP32.  So the two trajectories stay within a few
+FP32 rounding errors of each other: the final angles agree to 1e-5 turns and dH
+to 1e-4 (L = 32; the FP32 per-site terms of the two H sums dominate), and the
+accept decisions agree unless exp(-dH) lies within 1e-4 of the uniform.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import natural, obs_tol
+from mcstats import mean_err
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_0811_2111_amd import xy
+else:  # collected on CPU-only machines; skipped by the marker filter
+    xy = None
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "exact_small_lattices.json")
+DECISION_EXEMPT = 1e-4
+
+
+def turn_dist(a, b):
+    d = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+    return np.abs(d - np.round(d))
+
+
+def momenta_of(lat):
+    """Momenta left in the HMC workspace (state layout) -> natural layout."""
+    L = lat.L
+    p = lat.hmc_work[256:256 + 4 * L * L].view(torch.float32).reshape(2, L, L // 2)
+    return natural(p)
+
+
+def test_momenta_match_oracle(orc):
+    """A trajectory with eps = 1e-20 changes neither angles nor momenta in FP32, so
+    the workspace keeps the initial momenta: Box-Muller of the same Philox words."""
+    for L in (32, 130):
+        lat = xy.Lattice(L, seed=11, beta=1.0)
+        before = lat.state.clone()
+        rec = xy.hmc_records(lat.hmc(1, 3, 1e-20))
+        torch.cuda.synchronize()
+        assert torch.equal(lat.state, before)
+        assert int(rec["accepted"][0]) == 1 and float(rec["dH"][0]) == 0.0
+        p_ref = orc.hmc_momenta(11, L, 0)
+        p_dev = momenta_of(lat)
+        assert np.max(np.abs(p_dev - p_ref) / np.maximum(1.0, np.abs(p_ref))) < 3e-6
+
+
+def test_one_trajectory_matches_oracle(orc):
+    L, seed, beta, eps, n = 32, 3, 1.0, 0.1, 10
+    lat = xy.Lattice(L, seed=seed, beta=beta)
+    phi = orc.hot_start(seed, L, "f32")
+    np.testing.assert_array_equal(natural(lat.state), phi)
+    rec = xy.hmc_records(lat.hmc(1, n, eps))
+    acc, dH, _ = orc.hmc_trajectory(seed, phi, beta, eps, n, 0)
+    assert abs(float(rec["dH"][0]) - dH) < 1e-4, (float(rec["dH"][0]), dH)
+    u = orc.hmc_accept_uniform(seed, 0)
+    if abs(math.exp(-dH) - u) > DECISION_EXEMPT:
+        assert bool(rec["accepted"][0]) == acc
+        if acc:
+            assert np.max(turn_dist(natural(lat.state), phi)) < 1e-5
+    m = orc.measure(natural(lat.state))
+    for name, ref in zip(["cx", "cy", "ix", "iy", "mx", "my"], m):
+        assert abs(float(rec[name][0]) - ref) <= obs_tol(ref, L * L), name
+    assert int(rec["traj"][0]) == 1 and lat.sweep_count == 1
+
+
+def test_trajectory_chain_follows_oracle(orc):
+    """Five trajectories in one call: every record (dH, decision, observables)
+    against the oracle run, until a decision falls inside the exemption band."""
+    L, seed, beta, eps, n, T = 32, 5, 1.1, 0.15, 8, 5
+    lat = xy.Lattice(L, seed=seed, beta=beta)
+    phi = orc.hot_start(seed, L, "f32")
+    rec = xy.hmc_records(lat.hmc(T, n, eps))
+    ref = orc.hmc_run(seed, phi, beta, eps, n, T, 1)
+    for t in range(T):
+        assert int(rec["traj"][t]) == t + 1
+        assert abs(float(rec["dH"][t]) - ref[t, 2]) < 1e-4, (t, float(rec["dH"][t]), ref[t, 2])
+        u = orc.hmc_accept_uniform(seed, t)
+        if abs(math.exp(-ref[t, 2]) - u) < DECISION_EXEMPT:
+            return                                   # the chains may part here
+        assert int(rec["accepted"][t]) == int(ref[t, 1])
+        for q, name in enumerate(["cx", "cy", "ix", "iy", "mx", "my"]):
+            assert abs(float(rec[name][t]) - ref[t, 3 + q]) <= 1e-5 * L * L, (t, name)
+    assert np.max(turn_dist(natural(lat.state), phi)) < 1e-4
+
+
+def test_rejected_trajectory_restores_state():
+    lat = xy.Lattice(64, seed=8, beta=1.0)
+    before = lat.state.clone()
+    rec = xy.hmc_records(lat.hmc(1, 10, 3.0))
+    assert int(rec["accepted"][0]) == 0 and float(rec["dH"][0]) > 50
+    assert torch.equal(lat.state, before)
+    m = xy.records(lat.measure())
+    for name in ["cx", "cy", "ix", "iy", "mx", "my"]:
+        assert abs(float(rec[name][0]) - float(m[name][0])) <= 1e-9 * 64 * 64
+
+
+def test_trajectory_at_L1024_matches_oracle(orc):
+    """A full L = 1024 trajectory from the hot start against the oracle's (an eps
+    small enough for the hot start to be accepted): dH, the decision with the
+    oracle's uniform, and every final angle."""
+    L, seed, beta, eps, n = 1024, 12, 1.0, 0.002, 5
+    lat = xy.Lattice(L, seed=seed, beta=beta)
+    phi = orc.hot_start(seed, L, "f32")
+    rec = xy.hmc_records(lat.hmc(1, n, eps))
+    acc, dH, _ = orc.hmc_trajectory(seed, phi, beta, eps, n, 0)
+    d = float(rec["dH"][0])
+    assert abs(d - dH) < 2e-3, (d, dH)
+    u = orc.hmc_accept_uniform(seed, 0)
+    if abs(math.exp(-dH) - u) > DECISION_EXEMPT:
+        assert bool(rec["accepted"][0]) == acc
+    assert int(rec["accepted"][0]) == int(u < math.exp(-d))
+    if acc and rec["accepted"][0]:
+        assert np.max(turn_dist(natural(lat.state), phi)) < 1e-5
+
+
+def test_hmc_4x4_against_transfer_matrix():
+    with open(GOLD) as f:
+        ref = json.load(f)["xy_4x4_continuous_E"]["1.0"]["q14"]
+    lat = xy.Lattice(4, seed=13, beta=1.0)
+    rec = xy.hmc_records(lat.hmc(20000, 5, 0.3))
+    e = -(rec["cx"] + rec["cy"]) / 16
+    mu, err = mean_err(e, discard=200)
+    assert abs(mu - ref) < 3 * err, (mu, ref, err)
+    dH = rec["dH"][200:]
+    c_mu, c_err = mean_err(np.exp(-dH))
+    assert abs(c_mu - 1) < 3 * c_err + 1e-3
+
+
+def test_metropolis_and_hmc_share_the_counter():
+    lat = xy.Lattice(64, seed=2, beta=1.0)
+    lat.sweep(3)
+    rec = xy.hmc_records(lat.hmc(2, 4, 0.1))
+    assert list(rec["traj"]) == [4, 5] and lat.sweep_count == 5
+    lat.sweep(2)
+    assert lat.sweep_count == 7
+
+
+def test_hmc_error_codes():
+    L_ = xy.lib()
+    lat = xy.Lattice(32, seed=1)
+    lat.hmc(1, 1, 0.1)
+    w = lat.hmc_work
+    args = (xy._ptr(w), w.numel())
+    assert L_.xy_hmc(lat.h, 1, 0, 0.1, *args, None) == xy.XY_EINVAL
+    assert L_.xy_hmc(lat.h, 1, 1, 0.0, *args, None) == xy.XY_EINVAL
+    assert L_.xy_hmc(lat.h, 1, 1, float("nan"), *args, None) == xy.XY_EINVAL
+    assert L_.xy_hmc(lat.h, -1, 1, 0.1, *args, None) == xy.XY_EINVAL
+    assert L_.xy_hmc(lat.h, 1, 1, 0.1, xy._ptr(w), w.numel() - 1, None) == xy.XY_ESIZE
+    assert L_.xy_hmc(lat.h, 1, 1, 0.1, None, 0, None) == xy.XY_ESTATE
+    assert L_.xy_hmc(None, 1, 1, 0.1, *args, None) == xy.XY_ESTATE
+    lat.set_sweep(0xFFFFFFFF - 2)
+    assert L_.xy_hmc(lat.h, 5, 1, 0.1, *args, None) == xy.XY_ERANGE
+    half = xy.Lattice(32, seed=1, precision="fp16")
+    assert L_.xy_hmc(half.h, 1, 1, 0.1, *args, None) == xy.XY_EINVAL

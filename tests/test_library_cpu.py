@@ -141,3 +141,16 @@ def test_init_without_gpu_reports_hip_error():
     assert rc == xy.XY_EHIP
     assert not h.value
     assert L_.xy_last_hip_error()
+
+
+@pytest.mark.parametrize("L", [4, 32, 130, 4096])
+def test_hmc_work_bytes(L):
+    b = xy.xy_hmc_work_bytes(L)
+    assert b == 256 + 8 * L * L + 2 * 4096 * 64     # flag, momenta + saved angles, two record sets
+
+
+def test_hmc_validation_without_gpu():
+    L_ = xy.lib()
+    s = ctypes.c_size_t()
+    assert L_.xy_hmc_work_bytes(5, ctypes.byref(s)) == xy.XY_EINVAL
+    assert L_.xy_hmc(None, 1, 1, 0.1, None, 0, None) == xy.XY_ESTATE
