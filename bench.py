@@ -46,6 +46,7 @@ VALU_PEAK_TSLOTS = 256 * 128 * 2.4e9 / 1e12
 ALG_SLOTS_PER_UPDATE = 68.0
 ALG_BYTES_FUSED = 8.0                    # bytes per site-update of one fused sweep: read 4 + write 4 (FP32)
 ALG_BYTES_STREAM = 12.0                  # two half-sweep passes: read both colours, write one, per half
+ALG_BYTES_HMC_STEP = 16.0                # one leap-frog step: read and write the angle and the momentum
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
 KERNEL_SOURCES = ["xy_device.hpp", "xy_tile1.hpp", "xy_fused.hip"]
 
@@ -87,7 +88,7 @@ def parse():
                     help="fixed plan 'kind,tile_x,tile_y,sweeps_per_pass' instead of autotuning")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["l4096", "l16384", "batch"], default="l4096",
+    ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc"], default="l4096",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
     return ap.parse_args()
 
@@ -225,6 +226,13 @@ def profile_leg(args, stream):
         ms = timed(lambda: lat.sweep(args.steps, c4["measure_every"], out=obs[: args.steps]), stream)
         print(json.dumps({"workload": "L16384", "sweeps": args.steps, "ms": ms,
                           "gupd_s": float(c4["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}))
+    elif args.workload == "hmc":
+        hc = workloads.HMC_16384
+        lat = xy.Lattice(hc["L"], seed=hc["seed"], beta=hc["beta"])
+        lat.sweep(args.warmup)
+        ms = timed(lambda: lat.hmc(args.steps, hc["n_md"], hc["eps"]), stream)
+        print(json.dumps({"workload": "HMC L16384", "trajectories": args.steps, "ms": ms,
+                          "g_site_steps_s": float(hc["L"]) ** 2 * hc["n_md"] * args.steps / (ms * 1e-3) / 1e9}))
     else:
         sc = workloads.temperature_scan()
         b = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
@@ -304,6 +312,24 @@ def extra_legs(stream):
         res[prec] = round(float(pc["L"]) ** 2 * 200 / (ms_x * 1e-3) / 1e9, 2)
         del lt
     ex["L8192_storage_gupd_s"] = res
+
+    # hybrid Monte Carlo trajectories (the paper's update)
+    for name, hc in (("hmc_L4096", workloads.HMC_4096), ("hmc_L16384", workloads.HMC_16384)):
+        lt = xy.Lattice(hc["L"], seed=hc["seed"], beta=hc["beta"])
+        lt.sweep(hc["therm"])
+        lt.hmc(2, hc["n_md"], hc["eps"])
+        out = torch.empty((hc["traj"], 9), dtype=torch.float64, device="cuda")
+        ms_h = timed(lambda: lt.hmc(hc["traj"], hc["n_md"], hc["eps"], out=out), stream)
+        r = xy.hmc_records(out)
+        steps = float(hc["L"]) ** 2 * hc["n_md"] * hc["traj"]
+        g_s = steps / (ms_h * 1e-3) / 1e9
+        ex[name] = {"g_site_steps_s": round(g_s, 2), "trajectories": hc["traj"], "n_md": hc["n_md"],
+                    "eps": hc["eps"], "ms": round(ms_h, 2), "accept_rate": round(float(r["accepted"].mean()), 3),
+                    "mean_dH": round(float(r["dH"].mean()), 4),
+                    "hbm_GBps_16B": round(g_s * ALG_BYTES_HMC_STEP, 1),
+                    "frac_hbm_16B": round(g_s * ALG_BYTES_HMC_STEP / HBM_PEAK_GBS, 4)}
+        del lt, out
+        torch.cuda.empty_cache()
     return ex
 
 

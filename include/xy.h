@@ -176,7 +176,7 @@ typedef struct xy_hmc_obs {
 } xy_hmc_obs;
 
 /* Bytes of device workspace xy_hmc needs for an L x L lattice (momenta, saved
- * angles, partial sums, accept flag): 8 L^2 + 256 + 2 * 4096 * 64. */
+ * angles, partial sums, accept flag): 8 L^2 + 256 + 2 * (65536 + 256) * 64. */
 int xy_hmc_work_bytes(int32_t L, size_t* bytes);
 
 /* Run n_traj trajectories of n_md leap-frog steps of size eps (> 0, finite) on

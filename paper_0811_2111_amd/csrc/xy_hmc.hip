@@ -81,7 +81,7 @@ __device__ __forceinline__ void write_record(double v[7], double* __restrict__ r
 #pragma unroll
     for (int q = 0; q < 7; ++q) v[q] = wave_sum_last(v[q]);
     if ((threadIdx.x & 63) == 63) {
-        const size_t b = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
         double* r = rec + (b * (kThreads / 64) + (threadIdx.x >> 6)) * 8;
 #pragma unroll
         for (int q = 0; q < 7; ++q) r[q] = v[q];
@@ -100,15 +100,18 @@ __device__ __forceinline__ void accumulate(double v[7], const Nb& n, int c, floa
     v[6] += (double)kin;
 }
 
-// Momenta, saved angles and the partial records of H_old.  Grid (ceil(Hh/256),
-// rows, 2): rows of a colour are taken with stride gridDim.y.
+// Block x index = 2 * (column block) + colour: the two colours of the same rows
+// run side by side, so the other plane's rows a block reads are L2 hits.
+
+// Momenta, saved angles and the partial records of H_old.  Grid
+// (2 ceil(Hh/256), rows): rows are taken with stride gridDim.y.
 __global__ void __launch_bounds__(kThreads)
 k_hmc_begin(const float* __restrict__ st, float* __restrict__ p, float* __restrict__ saved, int L, uint32_t traj,
             uint32_t k0, uint32_t k1, double* __restrict__ rec)
 {
     const int Hh = L >> 1, P = (Hh + 1) >> 1;
-    const int k = blockIdx.x * kThreads + threadIdx.x;
-    const int c = blockIdx.z;
+    const int k = (blockIdx.x >> 1) * kThreads + threadIdx.x;
+    const int c = blockIdx.x & 1;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (k < Hh) {
         for (int y = blockIdx.y; y < L; y += gridDim.y) {
@@ -126,15 +129,15 @@ k_hmc_begin(const float* __restrict__ st, float* __restrict__ p, float* __restri
 }
 
 // One leap-frog step: kick with `kick` = eps (eps/2 on the first step), then
-// drift by eps/(2 pi) p turns.  Grid (ceil(Hh/256), L, 2).
+// drift by eps/(2 pi) p turns.  Grid (2 ceil(Hh/256), L).
 __global__ void __launch_bounds__(kThreads)
 k_hmc_step(const float* __restrict__ src, float* __restrict__ dst, float* __restrict__ p, int L, float nbeta_kick,
            float drift)
 {
     const int Hh = L >> 1;
-    const int k = blockIdx.x * kThreads + threadIdx.x;
+    const int k = (blockIdx.x >> 1) * kThreads + threadIdx.x;
     if (k >= Hh) return;
-    const int y = blockIdx.y, c = blockIdx.z;
+    const int y = blockIdx.y, c = blockIdx.x & 1;
     float th;
     const Nb n = load_nb(src, L, Hh, c, y, k, th);
     const size_t i = ((size_t)c * L + y) * Hh + k;
@@ -143,6 +146,83 @@ k_hmc_step(const float* __restrict__ src, float* __restrict__ dst, float* __rest
     dst[i] = __builtin_amdgcn_fractf(__fmaf_rn(drift, pn, th));
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
+// this remap gives each XCD one contiguous band of rows (both colours), so the
+// neighbour rows a block reads from the other plane are hits in that XCD's L2.
+__device__ __forceinline__ unsigned xcd_band(unsigned b, unsigned nb)
+{
+    if ((nb & 7u) != 0u) return b;
+    return (b & 7u) * (nb >> 3) + (b >> 3);
+}
+
+// One leap-frog step for L % 4 == 0: a thread takes the two entries 2j, 2j+1 of
+// a half-row in R consecutive rows (8-byte loads and stores).  Its horizontal
+// neighbours in the other plane are that plane's pair 2j, 2j+1 of the same row
+// and one more entry (2j-1 if o = 0, 2j+2 if o = 1); its vertical neighbours are
+// the other plane's pairs of the rows above and below, so the R rows share R + 2
+// rows of the other plane.  1-D grid of 2 ceil(J/256) (L/R) workgroups, J = L/4,
+// remapped by xcd_band.
+template <int R>
+__global__ void __launch_bounds__(kThreads)
+k_hmc_step2(const float* __restrict__ src, float* __restrict__ dst, float* __restrict__ p, int L, float nbeta_kick,
+            float drift)
+{
+    const int Hh = L >> 1, J = Hh >> 1;
+    const int cols = 2 * ((J + kThreads - 1) / kThreads);
+    const unsigned t = xcd_band(blockIdx.x, gridDim.x);
+    const int y0 = (int)(t / (unsigned)cols) * R, col = (int)(t % (unsigned)cols);
+    const int c = col & 1;
+    const int j = (col >> 1) * kThreads + threadIdx.x;
+    if (j >= J) return;
+    const float* oth = src + (size_t)(1 - c) * L * Hh;
+    float2 h[R + 2];                       // other plane, rows y0-1 .. y0+R
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) h[r] = ((const float2*)(oth + (size_t)wrapi(y0 - 1 + r, L) * Hh))[j];
+    float2 th[R], pv[R];
+    float e[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = y0 + r;
+        const int o = (c + y) & 1;
+        th[r] = ((const float2*)(src + ((size_t)c * L + y) * Hh))[j];
+        pv[r] = ((const float2*)(p + ((size_t)c * L + y) * Hh))[j];
+        e[r] = oth[(size_t)y * Hh + (o ? wrapi(2 * j + 2, Hh) : wrapi(2 * j - 1, Hh))];
+    }
+    float hc0[R + 2], hs0[R + 2], hc1[R + 2], hs1[R + 2];
+#pragma unroll
+    for (int r = 0; r < R + 2; ++r) {
+        sincos_turn(h[r].x, hs0[r], hc0[r]);
+        sincos_turn(h[r].y, hs1[r], hc1[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int y = y0 + r;
+        const int o = (c + y) & 1;
+        float sa, ca, sb, cb, se, ce;
+        sincos_turn(th[r].x, sa, ca);
+        sincos_turn(th[r].y, sb, cb);
+        sincos_turn(e[r], se, ce);
+        Nb na, nb;
+        na.c = ca; na.s = sa;
+        nb.c = cb; nb.s = sb;
+        // entry 2j: left = (o ? h0 : e), right = (o ? h1 : h0); 2j+1: left = (o ? h1 : h0), right = (o ? e : h1)
+        na.cl = o ? hc0[r + 1] : ce;         na.sl = o ? hs0[r + 1] : se;
+        na.cr = o ? hc1[r + 1] : hc0[r + 1]; na.sr = o ? hs1[r + 1] : hs0[r + 1];
+        nb.cl = o ? hc1[r + 1] : hc0[r + 1]; nb.sl = o ? hs1[r + 1] : hs0[r + 1];
+        nb.cr = o ? ce : hc1[r + 1];         nb.sr = o ? se : hs1[r + 1];
+        na.cu = hc0[r]; na.su = hs0[r]; nb.cu = hc1[r]; nb.su = hs1[r];
+        na.cd = hc0[r + 2]; na.sd = hs0[r + 2]; nb.cd = hc1[r + 2]; nb.sd = hs1[r + 2];
+        const float pa = __fmaf_rn(nbeta_kick, sin_sum(na), pv[r].x);
+        const float pb = __fmaf_rn(nbeta_kick, sin_sum(nb), pv[r].y);
+        ((float2*)(p + ((size_t)c * L + y) * Hh))[j] = make_float2(pa, pb);
+        ((float2*)(dst + ((size_t)c * L + y) * Hh))[j] =
+            make_float2(__builtin_amdgcn_fractf(__fmaf_rn(drift, pa, th[r].x)),
+                        __builtin_amdgcn_fractf(__fmaf_rn(drift, pb, th[r].y)));
+    }
+}
+
+constexpr int kStepRows = 4;               // rows per thread of k_hmc_step2
+
 // Final half kick and the partial records of H_new; `copy` != NULL receives the
 // angles (the final ones may sit in the second buffer).  Grid as k_hmc_begin.
 __global__ void __launch_bounds__(kThreads)
@@ -150,8 +230,8 @@ k_hmc_end(const float* __restrict__ st, float* __restrict__ copy, const float* _
           float nbeta_kick, double* __restrict__ rec)
 {
     const int Hh = L >> 1;
-    const int k = blockIdx.x * kThreads + threadIdx.x;
-    const int c = blockIdx.z;
+    const int k = (blockIdx.x >> 1) * kThreads + threadIdx.x;
+    const int c = blockIdx.x & 1;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (k < Hh) {
         for (int y = blockIdx.y; y < L; y += gridDim.y) {
@@ -186,7 +266,8 @@ __device__ void sum_records(const double* __restrict__ rec, int nrec, double out
     __syncthreads();
 }
 
-// Metropolis step of the trajectory: one workgroup.
+// Metropolis step of the trajectory: one workgroup, on the chunk sums of the two
+// record sets.
 __global__ void __launch_bounds__(kThreads)
 k_hmc_decide(const double* __restrict__ rec_old, const double* __restrict__ rec_new, int nrec, double beta,
              uint32_t traj, uint32_t k0, uint32_t k1, unsigned* __restrict__ flag, xy_hmc_obs* __restrict__ obs)
@@ -224,26 +305,23 @@ k_hmc_restore(const unsigned* __restrict__ flag, const float* __restrict__ saved
 
 }  // namespace
 
-// Rows per colour that the record-writing kernels give each block column: keeps
-// the records of one set at most kHmcMaxRecords.
+// Block columns (both colours) and row blocks of the record-writing kernels: as
+// many rows as keep one record set at most kHmcMaxRecords.
+static int hmc_cols(int L) { return 2 * (((L >> 1) + kThreads - 1) / kThreads); }
+
 static int hmc_row_blocks(int L)
 {
-    const int gx = ((L >> 1) + kThreads - 1) / kThreads;
-    int gy = kHmcMaxRecords / (gx * 2 * (kThreads / 64));
+    int gy = kHmcMaxRecords / (hmc_cols(L) * (kThreads / 64));
     if (gy > L) gy = L;
     return gy < 1 ? 1 : gy;
 }
 
-int hmc_records(int L)
-{
-    const int gx = ((L >> 1) + kThreads - 1) / kThreads;
-    return gx * hmc_row_blocks(L) * 2 * (kThreads / 64);
-}
+int hmc_records(int L) { return hmc_cols(L) * hmc_row_blocks(L) * (kThreads / 64); }
 
 size_t hmc_work_bytes(int L)
 {
     const size_t n = (size_t)L * (size_t)L;
-    return 256 + 2 * n * sizeof(float) + 2 * (size_t)kHmcMaxRecords * 8 * sizeof(double);
+    return 256 + 2 * n * sizeof(float) + 2 * (size_t)(kHmcMaxRecords + kHmcMaxChunks) * 8 * sizeof(double);
 }
 
 HmcWork hmc_carve(void* work, int L)
@@ -260,31 +338,42 @@ HmcWork hmc_carve(void* work, int L)
     w.rec_old = (double*)b;
     b += (size_t)kHmcMaxRecords * 8 * sizeof(double);
     w.rec_new = (double*)b;
+    b += (size_t)kHmcMaxRecords * 8 * sizeof(double);
+    w.chunk_old = (double*)b;
+    b += (size_t)kHmcMaxChunks * 8 * sizeof(double);
+    w.chunk_new = (double*)b;
     return w;
 }
 
 hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w, int L, double beta, double eps,
                                  int n_md, uint32_t traj, uint32_t k0, uint32_t k1, xy_hmc_obs* obs, hipStream_t s)
 {
-    const int Hh = L >> 1;
-    const int gx = (Hh + kThreads - 1) / kThreads;
-    const dim3 grec(gx, hmc_row_blocks(L), 2), gstep(gx, L, 2), block(kThreads);
+    const dim3 grec(hmc_cols(L), hmc_row_blocks(L)), gstep(hmc_cols(L), L), block(kThreads);
     const int nrec = hmc_records(L);
+    const int nchunk = (nrec + 255) / 256;
     const float drift = (float)(eps / (2.0 * 3.14159265358979323846));
     hipLaunchKernelGGL(k_hmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, w.rec_old);
     float* src = state;
     float* dst = pingpong;
+    const bool pairs = (L % (4 * kStepRows)) == 0;
+    const unsigned nstep2 = (unsigned)(2 * ((L / 4 + kThreads - 1) / kThreads)) * (unsigned)(L / kStepRows);
     for (int q = 0; q < n_md; ++q) {
         const float kick = (float)(-beta * (q == 0 ? 0.5 * eps : eps));
-        hipLaunchKernelGGL(k_hmc_step, gstep, block, 0, s, src, dst, w.p, L, kick, drift);
+        if (pairs)
+            hipLaunchKernelGGL(k_hmc_step2<kStepRows>, dim3(nstep2), block, 0, s, src, dst, w.p, L, kick, drift);
+        else
+            hipLaunchKernelGGL(k_hmc_step, gstep, block, 0, s, src, dst, w.p, L, kick, drift);
         float* t = src;
         src = dst;
         dst = t;
     }
     hipLaunchKernelGGL(k_hmc_end, grec, block, 0, s, src, src == state ? nullptr : state, w.p, L,
                        (float)(-beta * 0.5 * eps), w.rec_new);
-    hipLaunchKernelGGL(k_hmc_decide, dim3(1), block, 0, s, w.rec_old, w.rec_new, nrec, beta, traj, k0, k1, w.flag,
-                       obs);
+    hipError_t e = launch_reduce_chunks(w.rec_old, nrec, w.chunk_old, s);
+    if (e == hipSuccess) e = launch_reduce_chunks(w.rec_new, nrec, w.chunk_new, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hmc_decide, dim3(1), block, 0, s, w.chunk_old, w.chunk_new, nchunk, beta, traj, k0, k1,
+                       w.flag, obs);
     const size_t n = (size_t)L * (size_t)L;
     const unsigned nb = (unsigned)((n + kThreads * 8 - 1) / (kThreads * 8));
     hipLaunchKernelGGL(k_hmc_restore, dim3(nb < 4096 ? nb : 4096), block, 0, s, w.flag, w.saved, state, n);

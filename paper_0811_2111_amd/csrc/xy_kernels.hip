@@ -331,6 +331,13 @@ k_finalize(const double* __restrict__ partials, int nparts, unsigned long long* 
     }
 }
 
+hipError_t launch_reduce_chunks(const double* partials, int nparts, double* out, hipStream_t s)
+{
+    const int nb = (nparts + 255) / 256;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nb), dim3(256), 0, s, partials, nparts, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const double* partials, int nparts, unsigned long long* counter, xy_obs* out,
                            uint64_t sweep_after, hipStream_t s, double* scratch)
 {

@@ -46,6 +46,9 @@ hipError_t launch_measure(const void* st, int L, int precision, double* partials
 
 // Reduce partials in a fixed order, take the accept counter (and clear it) plus
 // the accepts in slot 6 of the partials, write one xy_obs record.
+// Sums of 256 consecutive records (slots 0..6) into out[chunk * 8 ..], fixed order.
+hipError_t launch_reduce_chunks(const double* partials, int nparts, double* out, hipStream_t s);
+
 hipError_t launch_finalize(const double* partials, int nparts, unsigned long long* counter,
                            xy_obs* out, uint64_t sweep_after, hipStream_t s, double* scratch);
 
@@ -60,13 +63,16 @@ int fused_tiles(int L, int tile_x, int tile_y);
 int fused_records(int L, int tile_x, int tile_y, int m);
 
 // ---- hybrid Monte Carlo (xy_hmc.hip)
-constexpr int kHmcMaxRecords = 4096;    // partial records of one H sum (old or new)
+constexpr int kHmcMaxRecords = 65536;   // partial records of one H sum (old or new)
+constexpr int kHmcMaxChunks = kHmcMaxRecords / 256;
 struct HmcWork {
     unsigned* flag;     // accept flag of the last trajectory
     float* p;           // momenta, state layout
     float* saved;       // angles at the start of the trajectory
     double* rec_old;    // partial records of H_old (8 doubles each)
     double* rec_new;    // partial records of H_new
+    double* chunk_old;  // sums of 256 records each
+    double* chunk_new;
 };
 size_t hmc_work_bytes(int L);
 HmcWork hmc_carve(void* work, int L);

@@ -25,6 +25,13 @@ PRECISION = dict(L=8192, betas=(0.9, 1.0, 1.1), delta=1.0, seed=1, sweeps=20000,
                  bias_L=256)
 
 
+# hybrid Monte Carlo (the paper's update): n_md leap-frog steps of size eps per
+# trajectory, after `therm` Metropolis sweeps from the hot start; eps falls with
+# the lattice size (the mean energy violation grows like L^2 eps^4)
+HMC_4096 = dict(L=4096, beta=1.0, eps=0.02, n_md=20, seed=1, therm=500, traj=50)
+HMC_16384 = dict(L=16384, beta=1.0, eps=0.01, n_md=20, seed=1, therm=200, traj=20)
+
+
 def temperature_scan(n: int = 96, sizes=(64, 128, 256, 512, 1024), beta_lo: float = 0.80,
                      beta_hi: float = 1.30, seed: int = 1):
     """The batched temperature scan: n lattices with L drawn uniformly from `sizes`
