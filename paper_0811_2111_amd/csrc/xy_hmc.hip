@@ -76,13 +76,12 @@ __device__ __forceinline__ float sin_sum(const Nb& n)
 // One partial record per wave: (Cx, Cy, Ix, Iy, Mx, My, K, 0).  Black sites add
 // their four bonds, their own spin and that of the red site to their right (as
 // the Metropolis measurement does); every site adds p^2 / 2.
-__device__ __forceinline__ void write_record(double v[7], double* __restrict__ rec)
+__device__ __forceinline__ void write_record(double v[7], double* __restrict__ rec, unsigned b)
 {
 #pragma unroll
     for (int q = 0; q < 7; ++q) v[q] = wave_sum_last(v[q]);
     if ((threadIdx.x & 63) == 63) {
-        const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-        double* r = rec + (b * (kThreads / 64) + (threadIdx.x >> 6)) * 8;
+        double* r = rec + ((size_t)b * (kThreads / 64) + (threadIdx.x >> 6)) * 8;
 #pragma unroll
         for (int q = 0; q < 7; ++q) r[q] = v[q];
         r[7] = 0.0;
@@ -100,21 +99,35 @@ __device__ __forceinline__ void accumulate(double v[7], const Nb& n, int c, floa
     v[6] += (double)kin;
 }
 
-// Block x index = 2 * (column block) + colour: the two colours of the same rows
-// run side by side, so the other plane's rows a block reads are L2 hits.
+// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
+// this remap gives each XCD one contiguous band of rows (both colours), so the
+// neighbour rows a block reads from the other plane are hits in that XCD's L2.
+__device__ __forceinline__ unsigned xcd_band(unsigned b, unsigned nb)
+{
+    if ((nb & 7u) != 0u) return b;
+    return (b & 7u) * (nb >> 3) + (b >> 3);
+}
 
-// Momenta, saved angles and the partial records of H_old.  Grid
-// (2 ceil(Hh/256), rows): rows are taken with stride gridDim.y.
+// Record-writing passes: 1-D grid of cols x rb workgroups, cols = 2 ceil(Hh/256)
+// (column block, colour interleaved), rb row blocks; after the XCD remap t,
+// column t % cols takes the run of R = ceil(L / rb) consecutive rows starting at
+// (t / cols) R, so the rows above and the row itself that a thread needs from
+// the other plane were loaded in its previous iteration.  Record index: t.
+
+// Momenta, saved angles and the partial records of H_old.
 __global__ void __launch_bounds__(kThreads)
 k_hmc_begin(const float* __restrict__ st, float* __restrict__ p, float* __restrict__ saved, int L, uint32_t traj,
-            uint32_t k0, uint32_t k1, double* __restrict__ rec)
+            uint32_t k0, uint32_t k1, int cols, int rb, double* __restrict__ rec)
 {
     const int Hh = L >> 1, P = (Hh + 1) >> 1;
-    const int k = (blockIdx.x >> 1) * kThreads + threadIdx.x;
-    const int c = blockIdx.x & 1;
+    const unsigned t = xcd_band(blockIdx.x, gridDim.x);
+    const int col = (int)(t % (unsigned)cols);
+    const int k = (col >> 1) * kThreads + threadIdx.x;
+    const int c = col & 1;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int R = (L + rb - 1) / rb, y0 = (int)(t / (unsigned)cols) * R, y1 = y0 + R < L ? y0 + R : L;
     if (k < Hh) {
-        for (int y = blockIdx.y; y < L; y += gridDim.y) {
+        for (int y = y0; y < y1; ++y) {
             float th;
             const Nb n = load_nb(st, L, Hh, c, y, k, th);
             const size_t i = ((size_t)c * L + y) * Hh + k;
@@ -125,7 +138,7 @@ k_hmc_begin(const float* __restrict__ st, float* __restrict__ p, float* __restri
             accumulate(v, n, c, __fmul_rn(0.5f, __fmul_rn(pm, pm)));
         }
     }
-    write_record(v, rec);                 // every lane reaches the wave sums
+    write_record(v, rec, t);              // every lane reaches the wave sums
 }
 
 // One leap-frog step: kick with `kick` = eps (eps/2 on the first step), then
@@ -144,15 +157,6 @@ k_hmc_step(const float* __restrict__ src, float* __restrict__ dst, float* __rest
     const float pn = __fmaf_rn(nbeta_kick, sin_sum(n), p[i]);
     p[i] = pn;
     dst[i] = __builtin_amdgcn_fractf(__fmaf_rn(drift, pn, th));
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8);
-// this remap gives each XCD one contiguous band of rows (both colours), so the
-// neighbour rows a block reads from the other plane are hits in that XCD's L2.
-__device__ __forceinline__ unsigned xcd_band(unsigned b, unsigned nb)
-{
-    if ((nb & 7u) != 0u) return b;
-    return (b & 7u) * (nb >> 3) + (b >> 3);
 }
 
 // One leap-frog step for L % 4 == 0: a thread takes the two entries 2j, 2j+1 of
@@ -227,14 +231,17 @@ constexpr int kStepRows = 4;               // rows per thread of k_hmc_step2
 // angles (the final ones may sit in the second buffer).  Grid as k_hmc_begin.
 __global__ void __launch_bounds__(kThreads)
 k_hmc_end(const float* __restrict__ st, float* __restrict__ copy, const float* __restrict__ p, int L,
-          float nbeta_kick, double* __restrict__ rec)
+          float nbeta_kick, int cols, int rb, double* __restrict__ rec)
 {
     const int Hh = L >> 1;
-    const int k = (blockIdx.x >> 1) * kThreads + threadIdx.x;
-    const int c = blockIdx.x & 1;
+    const unsigned t = xcd_band(blockIdx.x, gridDim.x);
+    const int col = (int)(t % (unsigned)cols);
+    const int k = (col >> 1) * kThreads + threadIdx.x;
+    const int c = col & 1;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int R = (L + rb - 1) / rb, y0 = (int)(t / (unsigned)cols) * R, y1 = y0 + R < L ? y0 + R : L;
     if (k < Hh) {
-        for (int y = blockIdx.y; y < L; y += gridDim.y) {
+        for (int y = y0; y < y1; ++y) {
             float th;
             const Nb n = load_nb(st, L, Hh, c, y, k, th);
             const size_t i = ((size_t)c * L + y) * Hh + k;
@@ -243,7 +250,7 @@ k_hmc_end(const float* __restrict__ st, float* __restrict__ copy, const float* _
             accumulate(v, n, c, __fmul_rn(0.5f, __fmul_rn(pn, pn)));
         }
     }
-    write_record(v, rec);
+    write_record(v, rec, t);
 }
 
 // Sum of one set of records in a fixed order (thread t: records t, t + 256, ...,
@@ -348,11 +355,12 @@ HmcWork hmc_carve(void* work, int L)
 hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w, int L, double beta, double eps,
                                  int n_md, uint32_t traj, uint32_t k0, uint32_t k1, xy_hmc_obs* obs, hipStream_t s)
 {
-    const dim3 grec(hmc_cols(L), hmc_row_blocks(L)), gstep(hmc_cols(L), L), block(kThreads);
+    const int cols = hmc_cols(L), rb = hmc_row_blocks(L);
+    const dim3 grec((unsigned)(cols * rb)), gstep(cols, L), block(kThreads);
     const int nrec = hmc_records(L);
     const int nchunk = (nrec + 255) / 256;
     const float drift = (float)(eps / (2.0 * 3.14159265358979323846));
-    hipLaunchKernelGGL(k_hmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, w.rec_old);
+    hipLaunchKernelGGL(k_hmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, cols, rb, w.rec_old);
     float* src = state;
     float* dst = pingpong;
     const bool pairs = (L % (4 * kStepRows)) == 0;
@@ -368,7 +376,7 @@ hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w
         dst = t;
     }
     hipLaunchKernelGGL(k_hmc_end, grec, block, 0, s, src, src == state ? nullptr : state, w.p, L,
-                       (float)(-beta * 0.5 * eps), w.rec_new);
+                       (float)(-beta * 0.5 * eps), cols, rb, w.rec_new);
     hipError_t e = launch_reduce_chunks(w.rec_old, nrec, w.chunk_old, s);
     if (e == hipSuccess) e = launch_reduce_chunks(w.rec_new, nrec, w.chunk_new, s);
     if (e != hipSuccess) return e;
