@@ -198,7 +198,7 @@ def main():
     }
 
     if not args.kernel_only and not args.no_extra:
-        out["extra"] = extra_legs(stream)
+        out["extra"] = extra_legs(stream, lat)
 
     if not args.kernel_only and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sweeps)
@@ -245,7 +245,7 @@ def profile_leg(args, stream):
                           "gupd_s": float(sites) * args.steps / (ms * 1e-3) / 1e9}))
 
 
-def extra_legs(stream):
+def extra_legs(stream, main_lat=None):
     import torch
 
     from paper_0811_2111_amd import workloads, xy
@@ -312,6 +312,30 @@ def extra_legs(stream):
         res[prec] = round(float(pc["L"]) ** 2 * 200 / (ms_x * 1e-3) / 1e9, 2)
         del lt
     ex["L8192_storage_gupd_s"] = res
+
+    # four replicas of L = 4096 in one float4 state vs the same four as single lattices
+    qc = workloads.QUAD_4096
+    qd = xy.Quad(qc["L"], qc["seeds"], qc["betas"], [qc["delta"]] * 4)
+    qd.sweep(10, 10)
+    qobs = torch.empty((qc["sweeps"] // qc["measure_every"], 4, 8), dtype=torch.float64, device="cuda")
+    ms_q = timed(lambda: qd.sweep(qc["sweeps"], qc["measure_every"], out=qobs), stream)
+    tile_q = qd.tile
+    del qd, qobs
+    singles = [xy.Lattice(qc["L"], seed=s_, beta=b_, delta=qc["delta"], plan=tuple(main_lat.plan) if main_lat is not None else None)
+               for s_, b_ in zip(qc["seeds"], qc["betas"])]
+    for lt in singles:
+        lt.sweep(10, 10)
+
+    def four_singles():
+        for lt in singles:
+            lt.sweep(qc["sweeps"], qc["measure_every"])
+    ms_s = timed(four_singles, stream)
+    del singles
+    torch.cuda.empty_cache()
+    upd = 4.0 * qc["L"] ** 2 * qc["sweeps"]
+    ex["quad_L4096"] = {"gupd_s": round(upd / (ms_q * 1e-3) / 1e9, 2), "tile": list(tile_q),
+                        "four_single_lattices_gupd_s": round(upd / (ms_s * 1e-3) / 1e9, 2),
+                        "sweeps": qc["sweeps"], "betas": qc["betas"]}
 
     # hybrid Monte Carlo trajectories (the paper's update)
     for name, hc in (("hmc_L4096", workloads.HMC_4096), ("hmc_L16384", workloads.HMC_16384)):

@@ -149,6 +149,40 @@ int xy_set_plan(xy_lattice* h, const xy_plan* plan);
 int xy_get_plan(const xy_lattice* h, xy_plan* plan);
 int xy_free(xy_lattice* h);
 
+/* ------------------------------------------------ four-replica lattices
+ * Four replicas of one L x L lattice (own seed, beta and delta each, e.g. four
+ * temperatures) in one state array, the four-channel texel of section 3.2:
+ * entry (c, y, k) of the layout above is four floats, component r holding
+ * replica r's angle (turns), 16 bytes per entry.  Replica r draws exactly the
+ * random numbers a single lattice with seed_r draws, so its trajectory is bit
+ * for bit that of xy_init/xy_sweep with (seed_r, L, beta_r, delta_r) in FP32;
+ * a sweep updates all four with one pass over the state.  FP32 only;
+ * L % 32 == 0, 32 <= L and 16 L^2 < 2^32. */
+typedef struct xy_quad xy_quad;
+
+/* *state = 16 L^2 bytes; *workspace = the second state buffer plus partial sums
+ * (16 L^2 + 2 L^2 + small). */
+int xy_quad_state_bytes(int32_t L, size_t* state, size_t* workspace);
+
+/* seeds, beta, delta: host arrays of 4.  start: XY_HOT (replica r: the hot start
+ * of seed_r) or XY_COLD.  Counter starts at 0. */
+int xy_quad_init(xy_quad** out, const uint64_t* seeds, int32_t L, const double* beta, const double* delta,
+                 int32_t start, void* state_dev, size_t state_len, void* work_dev, size_t work_len,
+                 void* hip_stream);
+
+/* As xy_sweep; records go to obs_dev[(j / measure_every - 1) * 4 + r] for
+ * replica r (4 xy_obs per measured sweep). */
+int xy_quad_sweep(xy_quad* q, int64_t n_sweeps, int32_t measure_every, xy_obs* obs_dev);
+int xy_quad_set_params(xy_quad* q, const double* beta, const double* delta);
+int xy_quad_get_sweep(const xy_quad* q, uint64_t* sweep);
+int xy_quad_set_sweep(xy_quad* q, uint64_t sweep);
+/* Tile shape of the fused sweep: (32, 16), (64, 8), (64, 16), (128, 4), (128, 8),
+ * dividing L (default (128, 8), or (32, 16) if 128 does not divide L).  The
+ * trajectory does not depend on it. */
+int xy_quad_set_tile(xy_quad* q, int32_t tile_x, int32_t tile_y);
+int xy_quad_get_tile(const xy_quad* q, int32_t* tile_x, int32_t* tile_y);
+int xy_quad_free(xy_quad* q);
+
 /* ------------------------------------------------------ hybrid Monte Carlo
  * The paper's own update (section 1.2): Gaussian momenta converted from flat
  * random numbers, leap-frog integration of the equations of motion, and a

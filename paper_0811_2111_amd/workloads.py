@@ -25,6 +25,10 @@ PRECISION = dict(L=8192, betas=(0.9, 1.0, 1.1), delta=1.0, seed=1, sweeps=20000,
                  bias_L=256)
 
 
+# four replicas of one L = 4096 lattice at four temperatures in one float4 state
+# (the four-channel texel of section 3.2), records every 10 sweeps
+QUAD_4096 = dict(L=4096, seeds=[1, 2, 3, 4], betas=[0.9, 1.0, 1.12, 1.3], delta=1.0, sweeps=1000, measure_every=10)
+
 # hybrid Monte Carlo (the paper's update): n_md leap-frog steps of size eps per
 # trajectory, after `therm` Metropolis sweeps from the hot start; eps falls with
 # the lattice size (the mean energy violation grows like L^2 eps^4)

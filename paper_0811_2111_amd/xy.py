@@ -97,6 +97,15 @@ def _load():
         "xy_batch_status": [vp],
         "xy_batch_free": [vp],
         "xy_hmc_work_bytes": [i32, P(sz)],
+        "xy_quad_state_bytes": [i32, P(sz), P(sz)],
+        "xy_quad_init": [P(vp), P(u64), i32, P(dbl), P(dbl), i32, vp, sz, vp, sz, vp],
+        "xy_quad_sweep": [vp, i64, i32, vp],
+        "xy_quad_set_params": [vp, P(dbl), P(dbl)],
+        "xy_quad_get_sweep": [vp, P(u64)],
+        "xy_quad_set_sweep": [vp, u64],
+        "xy_quad_set_tile": [vp, i32, i32],
+        "xy_quad_get_tile": [vp, P(i32), P(i32)],
+        "xy_quad_free": [vp],
         "xy_hmc": [vp, i64, i32, dbl, vp, sz, vp],
     }
     for name, args in sig.items():
@@ -352,3 +361,67 @@ class Batch:
         check(_lib.xy_batch_autotune(self.h, int(sweeps_per_trial), ctypes.byref(tx), ctypes.byref(ty)),
               "xy_batch_autotune")
         return tx.value, ty.value
+
+
+class Quad:
+    """Four replicas of one L x L lattice in one float4 state (component r = replica r)."""
+
+    def __init__(self, L: int, seeds, betas, deltas=(1.0, 1.0, 1.0, 1.0), start="hot", device="cuda", stream=None):
+        import torch
+        assert len(seeds) == 4 and len(betas) == 4 and len(deltas) == 4
+        self.L = int(L)
+        self.seeds, self.betas, self.deltas = [int(v) for v in seeds], [float(v) for v in betas], \
+            [float(v) for v in deltas]
+        s, w = ctypes.c_size_t(), ctypes.c_size_t()
+        check(_lib.xy_quad_state_bytes(self.L, ctypes.byref(s), ctypes.byref(w)), "xy_quad_state_bytes")
+        self.state = torch.empty((2, self.L, self.L // 2, 4), dtype=torch.float32, device=device)
+        self.work = torch.empty((w.value,), dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        rc = _lib.xy_quad_init(ctypes.byref(h), (ctypes.c_uint64 * 4)(*self.seeds), self.L,
+                               (ctypes.c_double * 4)(*self.betas), (ctypes.c_double * 4)(*self.deltas), _START[start],
+                               _ptr(self.state), _nbytes(self.state), _ptr(self.work), _nbytes(self.work),
+                               _stream_handle(stream))
+        check(rc, "xy_quad_init")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            _lib.xy_quad_free(h)
+            self.h = None
+
+    def replica_state(self, r: int):
+        """(2, L, L/2) view of replica r's angles (strided)."""
+        return self.state[..., r]
+
+    def sweep(self, n: int, measure_every: int = 0, out=None):
+        """n sweeps; returns a device tensor (records, 4, 8) of xy_obs, or None."""
+        import torch
+        nrec = n // measure_every if measure_every > 0 else 0
+        if nrec and out is None:
+            out = torch.empty((nrec, 4, 8), dtype=torch.float64, device=self.state.device)
+        check(_lib.xy_quad_sweep(self.h, int(n), int(measure_every), _ptr(out) if nrec else None), "xy_quad_sweep")
+        return out
+
+    def set_params(self, betas, deltas):
+        check(_lib.xy_quad_set_params(self.h, (ctypes.c_double * 4)(*betas), (ctypes.c_double * 4)(*deltas)),
+              "xy_quad_set_params")
+        self.betas, self.deltas = [float(v) for v in betas], [float(v) for v in deltas]
+
+    @property
+    def sweep_count(self) -> int:
+        v = ctypes.c_uint64()
+        check(_lib.xy_quad_get_sweep(self.h, ctypes.byref(v)), "xy_quad_get_sweep")
+        return v.value
+
+    def set_sweep(self, s: int):
+        check(_lib.xy_quad_set_sweep(self.h, int(s)), "xy_quad_set_sweep")
+
+    def set_tile(self, tx: int, ty: int):
+        check(_lib.xy_quad_set_tile(self.h, int(tx), int(ty)), "xy_quad_set_tile")
+
+    @property
+    def tile(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.xy_quad_get_tile(self.h, ctypes.byref(a), ctypes.byref(b)), "xy_quad_get_tile")
+        return a.value, b.value
