@@ -22,6 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "xy_oracle.c")
 _SRC_HMC = os.path.join(_HERE, "xy_hmc_oracle.c")
+_SRC_PT = os.path.join(_HERE, "xy_pt_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 PREC_F64, PREC_F32, PREC_F16 = 0, 1, 2
@@ -30,11 +31,11 @@ _PREC = {"f64": PREC_F64, "f32": PREC_F32, "f16": PREC_F16}
 
 def build(force: bool = False) -> str:
     """Compile ``xy_oracle.c`` into ``liboracle.so`` with gcc (single-threaded)."""
-    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_HMC))
+    newest = max(os.path.getmtime(_SRC), os.path.getmtime(_SRC_HMC), os.path.getmtime(_SRC_PT))
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp,
-                               _SRC, _SRC_HMC, "-lm"])
+                               _SRC, _SRC_HMC, _SRC_PT, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -104,6 +105,13 @@ def lib():
         L.orc_hmc_run.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                   ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64, dp, dp]
         L.orc_hmc_run.restype = ctypes.c_int64
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.orc_pt_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32]
+        L.orc_pt_uniform.restype = ctypes.c_double
+        L.orc_pt_run.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.c_int, ctypes.c_int, dp, dp, i32p,
+                                 ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64,
+                                 ctypes.c_int, ctypes.c_int, dp, dp, i32p]
+        L.orc_pt_run.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -285,3 +293,32 @@ def hmc_run(seed: int, phi: np.ndarray, beta: float, eps: float, n: int, n_traj:
     if got < 0:
         raise MemoryError("orc_hmc_run")
     return rec[:got]
+
+
+# ------------------------------------------------------- parallel tempering
+# One ladder of M lattices of the same L (xy_pt_oracle.c).
+
+def pt_uniform(pt_seed: int, rnd: int, ladder: int, rung: int) -> float:
+    return lib().orc_pt_uniform(pt_seed, rnd, ladder, rung)
+
+
+def pt_run(seeds, phi: np.ndarray, betas, deltas, member: np.ndarray, pt_seed: int, n_rounds: int, K: int,
+           ladder: int = 0, round0: int = 0, sweep0: int = 0, prec="f32"):
+    """n_rounds tempering rounds in place.  phi: (M, L, L) float64 (C-contiguous);
+    member: int32 (M,) lattice on each rung, updated.  Returns (rec, rung):
+    rec (n_rounds, M, 9) = [round, sweep count after, accepts, Cx, Cy, Ix, Iy, Mx, My]
+    of each lattice, rung (n_rounds, M) = its rung during the round."""
+    M, L = phi.shape[0], phi.shape[1]
+    assert phi.dtype == np.float64 and phi.flags.c_contiguous
+    assert member.dtype == np.int32 and member.flags.c_contiguous and member.shape == (M,)
+    sd = (ctypes.c_uint64 * M)(*[int(v) for v in seeds])
+    b = np.ascontiguousarray(betas, dtype=np.float64)
+    d = np.ascontiguousarray(deltas, dtype=np.float64)
+    rec = np.zeros((n_rounds, M, 9), dtype=np.float64)
+    rung = np.zeros((n_rounds, M), dtype=np.int32)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    rc = lib().orc_pt_run(sd, M, L, _dp(b), _dp(d), member.ctypes.data_as(i32), pt_seed, ladder, round0, sweep0,
+                          n_rounds, K, _prec(prec), _dp(phi), _dp(rec), rung.ctypes.data_as(i32))
+    if rc != 0:
+        raise MemoryError("orc_pt_run")
+    return rec, rung
