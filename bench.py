@@ -302,6 +302,22 @@ def extra_legs(stream, main_lat=None):
     del lats
     torch.cuda.empty_cache()
 
+    # parallel tempering over the same scan: ladders of equal L, rounds of 10 sweeps
+    tb = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+    tb.set_tile(*tile)
+    rounds, K = sc["sweeps"] // sc["measure_every"], sc["measure_every"]
+    tb.tempering(2, K, 1)
+    trec = torch.empty((rounds, n, 8), dtype=torch.float64, device="cuda")
+    trung = torch.empty((rounds, n), dtype=torch.int32, device="cuda")
+    ms_t = timed(lambda: tb.tempering(rounds, K, 1, out=trec, rungs=trung), stream)
+    moved = float((trung[1:] != trung[:-1]).float().mean())
+    ex["tempering_scan_96"] = {"gupd_s": round(float(sites) * rounds * K / (ms_t * 1e-3) / 1e9, 2),
+                               "rounds": rounds, "sweeps_per_round": K, "ms": round(ms_t, 2),
+                               "rung_change_rate": round(moved, 4),
+                               "vs_batched_sweeps": round(float(sites) * rounds * K / (ms_t * 1e-3) / 1e9 / g_b, 3)}
+    del tb, trec, trung
+    torch.cuda.empty_cache()
+
     # FP16 vs FP32 storage at L = 8192
     pc = workloads.PRECISION
     res = {}

@@ -149,6 +149,28 @@ int xy_set_plan(xy_lattice* h, const xy_plan* plan);
 int xy_get_plan(const xy_lattice* h, xy_plan* plan);
 int xy_free(xy_lattice* h);
 
+/* Parallel tempering over a batch.  Lattices of equal L form a ladder (ladders in
+ * order of L), its rungs ordered by the beta each lattice holds when the call
+ * starts (ties by index); rung t keeps that (beta_t, delta_t).  Each of n_rounds
+ * rounds runs sweeps_per_round sweeps of every lattice (the last one measured),
+ * then the lattices a, b on rungs t, t+1 of every ladder, for t = p, p + 2, ...
+ * (p = round index mod 2), exchange rungs iff u < exp((beta_t - beta_t+1)
+ * (E_a - E_b)), E = -(cx + cy) of the round's record and u = u(X0) of Philox
+ * counter (round, ladder, 4, t), key = (pt_seed mod 2^32, pt_seed >> 32).
+ * Configurations stay in place; temperatures move.  Round indices continue
+ * across calls on a batch.  obs_dev: NULL or device memory for n_rounds * n
+ * records, [round][lattice]; rung_dev: NULL or n_rounds * n int32, the rung each
+ * lattice held during the round.  Returns after the work has finished (the
+ * lattices' new (beta, delta) are read back; see xy_batch_get_params).
+ * XY_EINVAL: n_rounds < 0 or sweeps_per_round < 1; XY_ERANGE: the sweep or round
+ * counter would pass 2^32 - 1. */
+int xy_batch_tempering(xy_batch* b, int64_t n_rounds, int32_t sweeps_per_round, uint64_t pt_seed,
+                       xy_obs* obs_dev, int32_t* rung_dev);
+
+/* The (beta, delta) each lattice of the batch currently runs at (host arrays of
+ * n; either may be NULL). */
+int xy_batch_get_params(const xy_batch* b, double* beta, double* delta);
+
 /* ------------------------------------------------ four-replica lattices
  * Four replicas of one L x L lattice (own seed, beta and delta each, e.g. four
  * temperatures) in one state array, the four-channel texel of section 3.2:

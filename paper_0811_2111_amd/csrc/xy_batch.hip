@@ -206,6 +206,48 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
 
 __global__ void k_batch_advance(Ctrl* ctrl, uint32_t n) { ctrl->sweep0 += n; }
 
+// ---------------------------------------------------------- parallel tempering
+// Lattices of equal L form a ladder (ladders ordered by L); rung t of ladder g
+// has the temperature (beta, delta) of rung_param[start_g + t]; member[start_g +
+// t] is the lattice on it.  After a round (its last sweep measured into
+// round_obs[i]), the lattices a, b on rungs t, t+1 (t = parity, parity + 2, ...)
+// exchange rungs iff u < exp((beta_t - beta_t+1)(E_a - E_b)), E = -(Cx + Cy),
+// u = u(X0) of Philox counter (round, g, 4, t) keyed by the tempering seed; an
+// exchange rewrites the two lattices' descriptors (delta, -beta log2 e).
+struct Rung {
+    double beta;
+    float delta, nbl2e;      // as in LatDesc
+};
+
+__global__ void __launch_bounds__(256)
+k_batch_exchange(LatDesc* __restrict__ lat, int* __restrict__ member, const int2* __restrict__ ladders, int nlad,
+                 const Rung* __restrict__ rung, const xy_obs* __restrict__ round_obs, uint32_t round, uint32_t k0,
+                 uint32_t k1, xy_obs* __restrict__ obs_out, int32_t* __restrict__ rung_out)
+{
+    for (int g = threadIdx.x; g < nlad; g += 256) {
+        const int start = ladders[g].x, len = ladders[g].y;
+        for (int t = 0; t < len; ++t) {
+            const int i = member[start + t];
+            if (obs_out) obs_out[i] = round_obs[i];
+            if (rung_out) rung_out[i] = t;
+        }
+        for (int t = (int)(round & 1u); t + 1 < len; t += 2) {
+            const int a = member[start + t], b = member[start + t + 1];
+            const double ea = -(round_obs[a].cx + round_obs[a].cy), eb = -(round_obs[b].cx + round_obs[b].cy);
+            const Rung ra = rung[start + t], rb = rung[start + t + 1];
+            const u32x4 w = philox10(round, (uint32_t)g, 4u, (uint32_t)t, k0, k1);
+            if ((double)u01(w.x) < exp((ra.beta - rb.beta) * (ea - eb))) {
+                member[start + t] = b;
+                member[start + t + 1] = a;
+                lat[a].delta = rb.delta;
+                lat[a].nbl2e = rb.nbl2e;
+                lat[b].delta = ra.delta;
+                lat[b].nbl2e = ra.nbl2e;
+            }
+        }
+    }
+}
+
 __global__ void k_zero_u32(unsigned* p, int n)
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
@@ -248,9 +290,20 @@ static std::vector<Shape> candidates(int n, const int32_t* L)
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, part_off, total;
+    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, part_off, pt_off, total;
     long long max_tiles;
 };
+
+// Tempering area: per lattice one round record, one ladder member slot, one rung
+// and one ladder-table entry.
+struct PtArea {
+    xy_obs* round_obs;
+    int* member;
+    Rung* rung;
+    int2* ladders;
+};
+
+static size_t pt_bytes(int n) { return (size_t)n * (sizeof(xy_obs) + sizeof(int) + sizeof(Rung) + sizeof(int2)) + 4 * 256; }
 
 static Layout layout(int n, const int32_t* L, int precision)
 {
@@ -268,7 +321,8 @@ static Layout layout(int n, const int32_t* L, int precision)
     lo.bar_off = lo.ctrl_off + 256;
     lo.desc_off = align256(lo.bar_off + (size_t)n * sizeof(unsigned));
     lo.part_off = align256(lo.desc_off + (size_t)n * sizeof(LatDesc));
-    lo.total = lo.part_off + (size_t)2 * lo.max_tiles * 8 * sizeof(double);
+    lo.pt_off = align256(lo.part_off + (size_t)2 * lo.max_tiles * 8 * sizeof(double));
+    lo.total = lo.pt_off + pt_bytes(n);
     return lo;
 }
 
@@ -303,6 +357,7 @@ static const uint32_t kBatchMagic = 0x58594254u;  // "XYBT"
 
 struct xy_batch {
     uint32_t magic;
+    uint32_t pt_round;     // index of the next tempering round (exchange random numbers)
     int n;
     std::vector<int32_t> L;
     std::vector<uint64_t> seed;
@@ -468,6 +523,7 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->stream = (hipStream_t)hip_stream;
     b->cap = nullptr;
     b->sweep = 0;
+    b->pt_round = 0;
     b->lo = layout(n, L, precision);
     b->graph = nullptr;
     b->exec = nullptr;
@@ -610,6 +666,88 @@ int xy_batch_get_tile(const xy_batch* b, int32_t* tile_x, int32_t* tile_y)
     if (!blive(b)) return XY_ESTATE;
     if (tile_x) *tile_x = b->shape.tx;
     if (tile_y) *tile_y = b->shape.ty;
+    return XY_OK;
+}
+
+int xy_batch_tempering(xy_batch* b, int64_t n_rounds, int32_t sweeps_per_round, uint64_t pt_seed, xy_obs* obs_dev,
+                       int32_t* rung_dev)
+{
+    if (!blive(b)) return XY_ESTATE;
+    if (n_rounds < 0 || sweeps_per_round < 1) return XY_EINVAL;
+    if (b->sweep + (uint64_t)n_rounds * (uint64_t)sweeps_per_round >= 0xffffffffull ||
+        (uint64_t)b->pt_round + (uint64_t)n_rounds >= 0xffffffffull)
+        return XY_ERANGE;
+    if (n_rounds == 0) return XY_OK;
+    const int n = b->n;
+    // ladders: lattices of equal L in order of L, each ordered by (beta, index)
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (b->L[x] != b->L[y]) return b->L[x] < b->L[y];
+        return b->beta[x] < b->beta[y];
+    });
+    std::vector<int> member(n);
+    std::vector<Rung> rung(n);
+    std::vector<int2> ladders;
+    for (int k = 0; k < n; ++k) {
+        const int i = order[k];
+        if (k == 0 || b->L[i] != b->L[order[k - 1]]) ladders.push_back(make_int2(k, 0));
+        ladders.back().y += 1;
+        member[k] = i;
+        const xyk::SweepArgs a = xyr::sweep_args(b->seed[i], b->L[i], b->precision, b->beta[i], b->delta[i]);
+        rung[k].beta = b->beta[i];
+        rung[k].delta = a.delta;
+        rung[k].nbl2e = a.nbl2e;
+    }
+    std::vector<double> rbeta(n), rdelta(n);
+    for (int k = 0; k < n; ++k) {
+        rbeta[k] = b->beta[order[k]];
+        rdelta[k] = b->delta[order[k]];
+    }
+    char* pt = b->work + b->lo.pt_off;
+    PtArea area;
+    area.round_obs = (xy_obs*)pt;
+    area.member = (int*)(pt + align256((size_t)n * sizeof(xy_obs)));
+    area.rung = (Rung*)((char*)area.member + align256((size_t)n * sizeof(int)));
+    area.ladders = (int2*)((char*)area.rung + align256((size_t)n * sizeof(Rung)));
+    hipError_t e;
+    if ((e = hipMemcpyAsync(area.member, member.data(), sizeof(int) * n, hipMemcpyHostToDevice, b->stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(area.rung, rung.data(), sizeof(Rung) * n, hipMemcpyHostToDevice, b->stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(area.ladders, ladders.data(), sizeof(int2) * ladders.size(), hipMemcpyHostToDevice,
+                            b->stream)) != hipSuccess)
+        return xyr::hip_fail(e, "xy_batch_tempering: upload");
+    const uint32_t k0 = (uint32_t)(pt_seed & 0xffffffffu), k1 = (uint32_t)(pt_seed >> 32);
+    LatDesc* desc = (LatDesc*)(b->work + b->lo.desc_off);
+    for (int64_t r = 0; r < n_rounds; ++r) {
+        int rc = xy_batch_sweep(b, sweeps_per_round, sweeps_per_round, area.round_obs);
+        if (rc != XY_OK) return rc;
+        hipLaunchKernelGGL(k_batch_exchange, dim3(1), dim3(256), 0, b->stream, desc, area.member, area.ladders,
+                           (int)ladders.size(), area.rung, area.round_obs, b->pt_round + (uint32_t)r, k0, k1,
+                           obs_dev ? obs_dev + (size_t)r * n : nullptr, rung_dev ? rung_dev + (size_t)r * n : nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return xyr::hip_fail(e, "xy_batch_tempering: exchange launch");
+    }
+    b->pt_round += (uint32_t)n_rounds;
+    // the host copies of beta and delta follow the lattices to their new rungs
+    if ((e = hipMemcpyAsync(member.data(), area.member, sizeof(int) * n, hipMemcpyDeviceToHost, b->stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(b->stream)) != hipSuccess)
+        return xyr::hip_fail(e, "xy_batch_tempering: read back");
+    for (int k = 0; k < n; ++k) {
+        b->beta[member[k]] = rbeta[k];
+        b->delta[member[k]] = rdelta[k];
+    }
+    return XY_OK;
+}
+
+int xy_batch_get_params(const xy_batch* b, double* beta, double* delta)
+{
+    if (!blive(b)) return XY_ESTATE;
+    for (int i = 0; i < b->n; ++i) {
+        if (beta) beta[i] = b->beta[i];
+        if (delta) delta[i] = b->delta[i];
+    }
     return XY_OK;
 }
 

@@ -97,6 +97,8 @@ def _load():
         "xy_batch_status": [vp],
         "xy_batch_free": [vp],
         "xy_hmc_work_bytes": [i32, P(sz)],
+        "xy_batch_tempering": [vp, i64, i32, u64, vp, vp],
+        "xy_batch_get_params": [vp, P(dbl), P(dbl)],
         "xy_quad_state_bytes": [i32, P(sz), P(sz)],
         "xy_quad_init": [P(vp), P(u64), i32, P(dbl), P(dbl), i32, vp, sz, vp, sz, vp],
         "xy_quad_sweep": [vp, i64, i32, vp],
@@ -323,6 +325,25 @@ class Batch:
         if h is not None and h.value:
             _lib.xy_batch_free(h)
             self.h = None
+
+    def tempering(self, n_rounds: int, sweeps_per_round: int, pt_seed: int, out=None, rungs=None):
+        """n_rounds parallel-tempering rounds; returns device tensors (records
+        (n_rounds, n, 8) of xy_obs, rungs (n_rounds, n) int32)."""
+        import torch
+        n = len(self.Ls)
+        if out is None:
+            out = torch.empty((max(int(n_rounds), 1), n, 8), dtype=torch.float64, device=self.state.device)
+        if rungs is None:
+            rungs = torch.empty((max(int(n_rounds), 1), n), dtype=torch.int32, device=self.state.device)
+        check(_lib.xy_batch_tempering(self.h, int(n_rounds), int(sweeps_per_round), int(pt_seed), _ptr(out),
+                                      _ptr(rungs)), "xy_batch_tempering")
+        return out[: int(n_rounds)], rungs[: int(n_rounds)]
+
+    def params(self):
+        n = len(self.Ls)
+        b, d = (ctypes.c_double * n)(), (ctypes.c_double * n)()
+        check(_lib.xy_batch_get_params(self.h, b, d), "xy_batch_get_params")
+        return list(b), list(d)
 
     def lattice_state(self, i: int):
         L = self.Ls[i]
