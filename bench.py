@@ -48,6 +48,9 @@ ALG_BYTES_FUSED = 8.0                    # bytes per site-update of one fused sw
 ALG_BYTES_STREAM = 12.0                  # two half-sweep passes: read both colours, write one, per half
 ALG_BYTES_HMC_STEP = 16.0                # one leap-frog step: read and write the angle and the momentum
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
+PLAN_NAMES = {1: "stream", 2: "fused", 3: "strip"}
+KERNEL_NAMES = {1: "k_half_sweep", 2: "k_fused (LDS-tiled fused red+black sweep)",
+                3: "k_strip (strip segment, rows streamed through LDS rings)"}
 KERNEL_SOURCES = ["xy_device.hpp", "xy_tile1.hpp", "xy_fused.hip"]
 
 
@@ -69,6 +72,8 @@ def measured_traffic(L, plan):
     except (OSError, ValueError):
         return None
     if t.get("kernel_sources_sha256") != kernel_sources_hash():
+        return None
+    if plan[0] != 2:                         # the counters were taken on the fused tile kernel
         return None
     e = t.get("entries", {}).get("%d/%d,%d,%d" % (L, plan[1], plan[2], plan[3]))
     return None if e is None else e.get("bytes_per_launch")
@@ -150,14 +155,16 @@ def main():
     e_mean = float(-(rec["cx"] + rec["cy"]).mean() / N)
     acc_rate = float(rec["n_accept"].mean() / N)
 
-    # dominant kernel: average duration of one fused launch (no measurement), events on the stream
+    # dominant kernel: average duration of one fused or strip launch (no measurement),
+    # events on the stream; the streaming plan launches two half-sweeps per sweep
     nrep = 40
+    tiled = plan[0] in (xy.XY_PLAN_FUSED, xy.XY_PLAN_STRIP)
     ms_k = timed(lambda: lat.sweep(nrep * plan[3] * 2), stream)
-    launches = nrep * 2 if plan[0] == 2 else nrep * 2 * plan[3] * 2
+    launches = nrep * 2 if tiled else nrep * 2 * plan[3] * 2
     per_launch_ms = ms_k / launches
-    sweeps_per_launch = plan[3] if plan[0] == 2 else 0.5
+    sweeps_per_launch = plan[3] if tiled else 0.5
     upd_per_launch = N * sweeps_per_launch
-    alg_bytes = (ALG_BYTES_FUSED if plan[0] == 2 else ALG_BYTES_STREAM / 2) * upd_per_launch
+    alg_bytes = (ALG_BYTES_FUSED if tiled else ALG_BYTES_STREAM / 2) * upd_per_launch
     achieved_gbs = alg_bytes / (per_launch_ms * 1e-3) / 1e9
     gupd_kernel = upd_per_launch / (per_launch_ms * 1e-3) / 1e9
     out = {
@@ -176,23 +183,23 @@ def main():
         "config": {"workload": "XY checkerboard Metropolis, L=4096 single lattice, beta=1.12, delta=1.0, "
                                "10 sweeps + FP64 E/M/helicity record per step",
                    "L": L, "beta": cfg["beta"], "delta": cfg["delta"], "sweeps_per_step": me,
-                   "plan": {"kind": "fused" if plan[0] == 2 else "stream", "tile_x": plan[1], "tile_y": plan[2],
+                   "plan": {"kind": PLAN_NAMES[plan[0]], "tile_x": plan[1], "tile_y": plan[2],
                             "sweeps_per_pass": plan[3]},
                    "parallelism": "single GPU"},
         "roofline": {
-            "kernel": "k_fused (LDS-tiled fused red+black sweep)" if plan[0] == 2 else "k_half_sweep",
+            "kernel": KERNEL_NAMES[plan[0]],
             "bound": "alu",
             "achieved": round(ALG_SLOTS_PER_UPDATE * upd_per_launch / (per_launch_ms * 1e-3) / 1e12, 2),
             "peak": round(VALU_PEAK_TSLOTS, 2),
             "unit": "T VALU-slot/s",
             "frac": round(ALG_SLOTS_PER_UPDATE * upd_per_launch / (per_launch_ms * 1e-3) / 1e12 / VALU_PEAK_TSLOTS, 4),
-            "traffic": measured_traffic(L, plan) if plan[0] == 2 else None,
+            "traffic": measured_traffic(L, plan),
             "alg_slots_per_update": ALG_SLOTS_PER_UPDATE,
             "avg_launch_ms": round(per_launch_ms, 5),
             "kernel_gupd_s": round(gupd_kernel, 2),
             "hbm": {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                    "alg_bytes_per_update": ALG_BYTES_FUSED if plan[0] == 2 else ALG_BYTES_STREAM},
+                    "alg_bytes_per_update": ALG_BYTES_FUSED if tiled else ALG_BYTES_STREAM},
         },
         "observables": {"E_per_site": round(e_mean, 6), "accept_rate": round(acc_rate, 4)},
     }

@@ -97,8 +97,16 @@ typedef struct xy_obs {
  *                   halo's red sites with their owners' random numbers) and writes
  *                   the tile to the other buffer of a ping-pong pair.  Needs
  *                   L % 4 == 0, tile_x % 4 == 0, tile_x | L, tile_y | L.
+ *   XY_PLAN_STRIP : one launch per sweep; a workgroup walks down a segment of
+ *                   tile_x columns (128 or 256) and tile_y rows, a few rows of each
+ *                   colour at a time, with (cos, sin) of the rows in flight in LDS
+ *                   rings and the next rows' loads issued ahead; the halo is one
+ *                   red row above and below the segment plus one red entry per row
+ *                   beside it, recomputed.  Needs tile_x | L, tile_y | L, (tile_x,
+ *                   tile_y) one of (128, 32|64|128), (256, 32|64|128|256),
+ *                   sweeps_per_pass = 1.
  *   XY_PLAN_AUTO  : the tuned plan for (L, precision) if one is cached, else a default. */
-enum { XY_PLAN_AUTO = 0, XY_PLAN_STREAM = 1, XY_PLAN_FUSED = 2 };
+enum { XY_PLAN_AUTO = 0, XY_PLAN_STREAM = 1, XY_PLAN_FUSED = 2, XY_PLAN_STRIP = 3 };
 typedef struct xy_plan {
     int32_t kind;
     int32_t tile_x;

@@ -62,6 +62,13 @@ int fused_tiles(int L, int tile_x, int tile_y);
 // records start at partials + j * fused_records(...) * 8 for sub-sweep j).
 int fused_records(int L, int tile_x, int tile_y, int m);
 
+// Strip sweep (xy_strip.hip): one sweep from a.src to a.dst by segments of
+// tile_x columns x tile_y rows; measured: one record per wave (4 per segment) at
+// partials[(segment * 4 + wave) * 8].
+bool strip_supported(int L, int tile_x, int tile_y);
+hipError_t launch_strip(const SweepArgs& a, int tile_x, int tile_y, bool meas, double* partials, hipStream_t s);
+int strip_records(int L, int tile_x, int tile_y);
+
 // ---- hybrid Monte Carlo (xy_hmc.hip)
 constexpr int kHmcMaxRecords = 65536;   // partial records of one H sum (old or new)
 constexpr int kHmcMaxChunks = kHmcMaxRecords / 256;

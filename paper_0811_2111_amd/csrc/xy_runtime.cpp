@@ -66,6 +66,7 @@ bool plan_ok(int32_t L, const xy_plan& p)
 {
     if (p.kind == XY_PLAN_STREAM) return true;
     if (p.kind == XY_PLAN_FUSED) return xyk::fused_supported(L, p.tile_x, p.tile_y, p.sweeps_per_pass);
+    if (p.kind == XY_PLAN_STRIP) return p.sweeps_per_pass == 1 && xyk::strip_supported(L, p.tile_x, p.tile_y);
     return false;
 }
 
@@ -295,10 +296,12 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
     // Fused schedule: an even number of ping-pong passes (state -> pingpong ->
     // state ...), so the angles end in the caller's buffer; the remaining sweeps
     // run in place with the streaming schedule (same trajectory).
-    const int m = h->plan.sweeps_per_pass;
+    const bool strip = h->plan.kind == XY_PLAN_STRIP;
+    const int m = strip ? 1 : h->plan.sweeps_per_pass;
     int64_t passes = n_sweeps / m;
     passes -= passes & 1;
-    const int nrec = xyk::fused_records(h->L, h->plan.tile_x, h->plan.tile_y, m);
+    const int nrec = strip ? xyk::strip_records(h->L, h->plan.tile_x, h->plan.tile_y)
+                           : xyk::fused_records(h->L, h->plan.tile_x, h->plan.tile_y, m);
     int64_t j = 0;  // sweeps done in this call
     for (int64_t q = 0; q < passes; ++q) {
         xyk::SweepArgs a = args_of(h);
@@ -307,7 +310,9 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
         unsigned mask = 0;
         for (int js = 0; js < m; ++js)
             if (measured(j + js + 1)) mask |= 1u << js;
-        hipError_t e = xyk::launch_fused(a, h->plan.tile_x, h->plan.tile_y, m, mask, h->w.partials, h->stream);
+        hipError_t e = strip ? xyk::launch_strip(a, h->plan.tile_x, h->plan.tile_y, mask != 0, h->w.partials,
+                                                 h->stream)
+                             : xyk::launch_fused(a, h->plan.tile_x, h->plan.tile_y, m, mask, h->w.partials, h->stream);
         if (e != hipSuccess) return hip_fail(e, "fused sweep launch");
         for (int js = 0; js < m; ++js) {
             if (!(mask & (1u << js))) continue;
@@ -438,6 +443,11 @@ int xy_autotune(xy_lattice* h, int32_t sweeps_per_trial, const char* cache_path,
                                     {256, 16, 1}, {256, 32, 1}, {64, 32, 2}, {128, 32, 2}};
     for (auto& s : shapes) {
         xy_plan p{XY_PLAN_FUSED, s[0], s[1], s[2]};
+        if (plan_ok(h->L, p)) cands.push_back(p);
+    }
+    static const int strips[][2] = {{128, 32}, {128, 64}, {128, 128}, {256, 32}, {256, 64}, {256, 128}, {256, 256}};
+    for (auto& s : strips) {
+        xy_plan p{XY_PLAN_STRIP, s[0], s[1], 1};
         if (plan_ok(h->L, p)) cands.push_back(p);
     }
     hipEvent_t e0, e1;

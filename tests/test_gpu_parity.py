@@ -30,8 +30,15 @@ FUSED_SHAPES = [(64, 16, 1), (64, 32, 1), (128, 16, 1), (128, 32, 1), (128, 64, 
 OPREC = {"fp32": "f32", "fp16": "f16"}
 
 
+STRIP_SHAPES = [(128, 32), (128, 64), (128, 128), (256, 32), (256, 64), (256, 128), (256, 256)]
+
+
 def fused_plans(L):
     return [(2, tx, ty, m) for (tx, ty, m) in FUSED_SHAPES if L % tx == 0 and L % ty == 0]
+
+
+def strip_plans(L):
+    return [(3, tx, sh, 1) for (tx, sh) in STRIP_SHAPES if L % tx == 0 and L % sh == 0]
 
 
 def dilate(mask, r):
@@ -122,7 +129,8 @@ def test_c1_trajectory_fp32(orc):
 
 
 @pytest.mark.parametrize("L,plan", [(64, (2, 64, 16, 1)), (64, (2, 64, 32, 2)), (128, (2, 128, 32, 1)),
-                                    (256, (2, 256, 32, 1))])
+                                    (256, (2, 256, 32, 1)), (128, (3, 128, 32, 1)), (256, (3, 256, 64, 1)),
+                                    (256, (3, 256, 256, 1))])
 def test_fused_trajectory_fp32(orc, L, plan):
     lat = xy.Lattice(L, seed=2, beta=1.12, delta=1.0, plan=plan)
     per = 2 * plan[3]
@@ -130,9 +138,9 @@ def test_fused_trajectory_fp32(orc, L, plan):
     print("first divergence:", div)
 
 
-@pytest.mark.parametrize("plan", [STREAM, (2, 64, 32, 1)])
-def test_fp16_trajectory(orc, plan):
-    lat = xy.Lattice(64, seed=4, beta=1.0, delta=1.0, precision="fp16", plan=plan)
+@pytest.mark.parametrize("L,plan", [(64, STREAM), (64, (2, 64, 32, 1)), (128, (3, 128, 64, 1))])
+def test_fp16_trajectory(orc, L, plan):
+    lat = xy.Lattice(L, seed=4, beta=1.0, delta=1.0, precision="fp16", plan=plan)
     follow(orc, lat, 4, 1.0, 1.0, n_calls=15, per_call=2, prec="fp16")
 
 
@@ -162,14 +170,15 @@ def test_debug_decisions_and_dE(orc):
 # ------------------------------------------------------- schedule invariance
 
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
-@pytest.mark.parametrize("L", [64, 128, 256])
+@pytest.mark.parametrize("L", [64, 128, 256, 512])
 def test_schedule_invariance(L, prec):
-    """Every plan (streaming, every fused tile shape, one or two sweeps per pass) gives
+    """Every plan (streaming, every fused tile shape, one or two sweeps per pass, every
+    strip shape) gives
     the same angles bit for bit and the same accept counts; observables agree to
     summation-order rounding (FP32 per-thread partials of a few sites, then FP64):
     within 1e-7 N, ten times inside the oracle tolerance."""
     res = []
-    for plan in [STREAM] + fused_plans(L):
+    for plan in [STREAM] + fused_plans(L) + strip_plans(L):
         lat = xy.Lattice(L, seed=7, beta=0.9, delta=1.0, precision=prec, plan=plan)
         obs = lat.sweep(7, 1)
         res.append((plan, lat.state.clone(), xy.records(obs)))
