@@ -272,10 +272,18 @@ int xy_tuned_plan(const char* cache_path, int32_t L, int32_t precision, xy_plan*
 
 /* ----------------------------------------------------------------- batches
  * n lattices of sizes L[i] >= 4, L[i] % 4 == 0 (possibly different), with their own seed,
- * beta and delta, advanced together by one persistent kernel per call, captured
- * once into a HIP graph and replayed.  Lattice i's angles start at element
- * offset sum_{j<i} L[j]^2 of state_dev, in the single-lattice layout.  A lattice
- * follows exactly the trajectory it would follow alone with the same seed. */
+ * beta and delta, advanced together; the launches of one call are captured once
+ * into a HIP graph and replayed.  Lattice i's angles start at element offset
+ * sum_{j<i} L[j]^2 of state_dev, in the single-lattice layout.  A lattice
+ * follows exactly the trajectory it would follow alone with the same seed.
+ * Two schedules (xy_batch_set_schedule), the same trajectory:
+ *   XY_BATCH_PERSISTENT: one persistent kernel per call; every workgroup owns a
+ *     contiguous range of the tiles of all lattices and waits, before each pass
+ *     over a lattice, for the previous pass of that lattice (per-lattice
+ *     counters in device memory);
+ *   XY_BATCH_PASSES (default): one launch per sweep over all tiles of all
+ *     lattices, one workgroup per tile; the kernel boundary orders the sweeps. */
+enum { XY_BATCH_PERSISTENT = 0, XY_BATCH_PASSES = 1 };
 int xy_batch_state_bytes(int32_t n, const int32_t* L, int32_t precision,
                          size_t* state, size_t* workspace);
 int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_t* L,
@@ -292,8 +300,11 @@ int xy_batch_get_sweep(const xy_batch* b, uint64_t* sweep);
  * allows; else the largest of 16x16, 8x8, 4x4 that divides every L). */
 int xy_batch_set_tile(xy_batch* b, int32_t tile_x, int32_t tile_y);
 int xy_batch_get_tile(const xy_batch* b, int32_t* tile_x, int32_t* tile_y);
-/* Time every candidate tile shape for `sweeps_per_trial` sweeps (after one
- * untimed trial that also captures the graph) and keep the fastest.  The trials
+int xy_batch_set_schedule(xy_batch* b, int32_t schedule);   /* XY_EINVAL if not one of the two */
+int xy_batch_get_schedule(const xy_batch* b, int32_t* schedule);
+/* Time every candidate tile shape under both schedules for `sweeps_per_trial`
+ * sweeps (after one untimed trial that also captures the graph) and keep the
+ * fastest (shape and schedule).  The trials
  * advance the batch: run it on a scratch batch of the same sizes. */
 int xy_batch_autotune(xy_batch* b, int32_t sweeps_per_trial, int32_t* tile_x, int32_t* tile_y);
 /* Wait for the batch's stream and report whether any launch so far hit a barrier

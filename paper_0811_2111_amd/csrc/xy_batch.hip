@@ -14,6 +14,15 @@
 // tiles of that lattice has finished pass p-1 (an epoch counter per lattice),
 // which orders both the new reads after the old writes and the new writes after
 // the old halo reads.  Lattices never wait for each other.
+//
+// The second schedule (XY_BATCH_PASSES) launches one kernel per pass over the
+// whole work list instead, one workgroup per tile, and lets the kernel boundary
+// order the passes.  A workgroup-level barrier needs an agent-scope release and
+// acquire per workgroup and pass, i.e. write-backs and invalidations of the
+// XCD's L2 cache, whereas a kernel boundary does that once per pass; when many
+// workgroups share a lattice the boundary is the cheaper barrier.  Records of a
+// measured pass are one partial per tile, summed per lattice in a fixed order by
+// a second small kernel.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -206,6 +215,46 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
 
 __global__ void k_batch_advance(Ctrl* ctrl, uint32_t n) { ctrl->sweep0 += n; }
 
+// One pass of the per-pass schedule: workgroup b sweeps tile t (XCD-aware order:
+// each XCD takes a contiguous run of the work list, so neighbouring tiles share
+// its L2).  MEAS = -1: measured, one record per tile at part[t * 8]; 0: not.
+template <typename T, int TX, int TY, int MEAS>
+__global__ void __launch_bounds__(256)
+k_batch_pass(const T* __restrict__ src, T* __restrict__ dst, const LatDesc* __restrict__ lat, int nlat,
+             int total_tiles, const Ctrl* __restrict__ ctrl, int p, double* __restrict__ part)
+{
+    extern __shared__ __align__(16) char smem[];
+    using S = Tile1<TX, TY, 256>;
+    double* red = (double*)(smem + S::lds_bytes);
+    const int b = (int)blockIdx.x;
+    const int t = (total_tiles & 7) ? b : (b & 7) * (total_tiles >> 3) + (b >> 3);
+    const int i = lattice_of(lat, nlat, t);
+    const LatDesc d = lat[i];
+    const int lt = t - d.first_tile;
+    const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
+    const Params prm{d.delta, d.nbl2e};
+    tile1_program<T, TX, TY, 256, MEAS>(src + d.off, dst + d.off, (unsigned)((size_t)d.L * d.L * sizeof(T)), d.L,
+                                        tx * TX, ty * TY, ctrl->sweep0 + (uint32_t)p, d.key0, d.key1, prm, MEAS != 0,
+                                        part + (size_t)t * 8, smem, red);
+}
+
+// Records of measured pass p (one workgroup per lattice, fixed order): record r of
+// lattice i at obs[i * nrec + r], sweep count sweep0 + p + 1.
+__global__ void __launch_bounds__(256)
+k_batch_reduce(const LatDesc* __restrict__ lat, const Ctrl* __restrict__ ctrl, int p, const double* __restrict__ part,
+               xy_obs* __restrict__ obs, int nrec, int r)
+{
+    __shared__ double red[4 * 7];
+    const int i = (int)blockIdx.x;
+    reduce_lattice<256>(lat[i], part, obs + (size_t)i * nrec + r, (uint64_t)ctrl->sweep0 + (uint64_t)p + 1u, red);
+}
+
+// dst <- src, n16 16-byte words
+__global__ void __launch_bounds__(256) k_batch_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, size_t n16)
+{
+    for (size_t k = (size_t)blockIdx.x * 256 + threadIdx.x; k < n16; k += (size_t)gridDim.x * 256) dst[k] = src[k];
+}
+
 // ---------------------------------------------------------- parallel tempering
 // Lattices of equal L form a ladder (ladders ordered by L); rung t of ladder g
 // has the temperature (beta, delta) of rung_param[start_g + t]; member[start_g +
@@ -332,6 +381,32 @@ static void* kernel_ptr()
     return (void*)k_batch<T, TX, TY, kNT>;
 }
 
+template <typename T, int TX, int TY, int MEAS>
+static void* pass_kernel_ptr()
+{
+    return (void*)k_batch_pass<T, TX, TY, MEAS>;
+}
+
+// The per-pass kernel for shape s (measured or not) and its LDS bytes.
+static void* pass_kernel(int precision, Shape s, bool meas, size_t* lds)
+{
+#define XYB_CASE(TXV, TYV)                                                                          \
+    if (s.tx == TXV && s.ty == TYV) {                                                               \
+        *lds = Tile1<TXV, TYV, kNT>::lds_bytes + Tile1<TXV, TYV, kNT>::red_bytes;                   \
+        if (precision == XY_FP16)                                                                   \
+            return meas ? pass_kernel_ptr<__half, TXV, TYV, -1>() : pass_kernel_ptr<__half, TXV, TYV, 0>(); \
+        return meas ? pass_kernel_ptr<float, TXV, TYV, -1>() : pass_kernel_ptr<float, TXV, TYV, 0>();       \
+    }
+    XYB_CASE(64, 32)
+    XYB_CASE(64, 16)
+    XYB_CASE(32, 16)
+    XYB_CASE(16, 16)
+    XYB_CASE(8, 8)
+    XYB_CASE(4, 4)
+#undef XYB_CASE
+    return nullptr;
+}
+
 static void* batch_kernel(int precision, Shape s, size_t* lds)
 {
 #define XYB_CASE(TXV, TYV)                                                                         \
@@ -371,6 +446,7 @@ struct xy_batch {
     uint64_t sweep;
     Layout lo;
     Shape shape;
+    int sched;             // XY_BATCH_PERSISTENT or XY_BATCH_PASSES
     int grid;
     int total_tiles;
     std::vector<LatDesc> desc;
@@ -380,6 +456,7 @@ struct xy_batch {
     int32_t g_me;
     xy_obs* g_obs;
     int g_grid;
+    int g_sched;
 };
 
 static bool blive(const xy_batch* b) { return b && b->magic == kBatchMagic; }
@@ -401,6 +478,13 @@ static int plan_batch(xy_batch* b, Shape s)
     if (!k) return XY_EINVAL;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return xyr::hip_fail(e, "hipFuncSetAttribute");
+    for (int m = 0; m < 2; ++m) {
+        size_t pl = 0;
+        void* pk = pass_kernel(b->precision, s, m == 1, &pl);
+        if (!pk) return XY_EINVAL;
+        if ((e = hipFuncSetAttribute(pk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl)) != hipSuccess)
+            return xyr::hip_fail(e, "hipFuncSetAttribute");
+    }
     int dev = 0, cus = 0, per_cu = 0;
     if ((e = hipGetDevice(&dev)) != hipSuccess) return xyr::hip_fail(e, "hipGetDevice");
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
@@ -478,6 +562,42 @@ static hipError_t enqueue_batch(xy_batch* b, hipStream_t s, int npass, int32_t m
     return hipGetLastError();
 }
 
+// Per-pass schedule: one launch per pass over all tiles, a record kernel after each
+// measured pass, a copy back for an odd pass count, then the sweep counter.
+static hipError_t enqueue_passes(xy_batch* b, hipStream_t s, int npass, int32_t me, xy_obs* obs)
+{
+    Ctrl* ctrl = (Ctrl*)(b->work + b->lo.ctrl_off);
+    const LatDesc* desc = (const LatDesc*)(b->work + b->lo.desc_off);
+    double* part = (double*)(b->work + b->lo.part_off);
+    const int nrec = me > 0 ? npass / me : 0;
+    void* pp = b->work + b->lo.pp_off;
+    int nlat = b->n, tt = b->total_tiles;
+    hipError_t e = hipSuccess;
+    for (int p = 0; p < npass; ++p) {
+        const bool meas = me > 0 && ((p + 1) % me) == 0;
+        size_t lds = 0;
+        void* k = pass_kernel(b->precision, b->shape, meas, &lds);
+        void* src = (p & 1) ? pp : (void*)b->state;
+        void* dst = (p & 1) ? (void*)b->state : pp;
+        int pv = p;
+        void* args[] = {&src, &dst, &desc, &nlat, &tt, &ctrl, &pv, &part};
+        if ((e = hipLaunchKernel(k, dim3(tt), dim3(kNT), args, lds, s)) != hipSuccess) return e;
+        if (meas) {
+            hipLaunchKernelGGL(k_batch_reduce, dim3(nlat), dim3(kNT), 0, s, desc, (const Ctrl*)ctrl, p,
+                               (const double*)part, obs, nrec, (p + 1) / me - 1);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    if (npass & 1) {
+        const size_t n16 = b->lo.state_bytes / 16;
+        const int grid = (int)std::min<size_t>((n16 + kNT - 1) / kNT, 4096);
+        hipLaunchKernelGGL(k_batch_copy, dim3(grid), dim3(kNT), 0, s, (uint4*)b->state, (const uint4*)pp, n16);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(1), 0, s, ctrl, (uint32_t)npass);
+    return hipGetLastError();
+}
+
 extern "C" {
 
 int xy_batch_state_bytes(int32_t n, const int32_t* L, int32_t precision, size_t* state, size_t* workspace)
@@ -531,6 +651,8 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->g_me = -1;
     b->g_obs = nullptr;
     b->g_grid = 0;
+    b->g_sched = -1;
+    b->sched = XY_BATCH_PASSES;
     auto fail = [&](int code) {
         drop_graph(b);
         if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -580,11 +702,13 @@ int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs*
     const int32_t me = (obs_dev && measure_every > 0) ? measure_every : 0;
     xy_obs* obs = me ? obs_dev : nullptr;
     hipError_t e;
-    if (!b->exec || b->g_n != n_sweeps || b->g_me != me || b->g_obs != obs || b->g_grid != b->grid) {
+    if (!b->exec || b->g_n != n_sweeps || b->g_me != me || b->g_obs != obs || b->g_grid != b->grid ||
+        b->g_sched != b->sched) {
         drop_graph(b);
         if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return xyr::hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = enqueue_batch(b, b->cap, (int)n_sweeps, me, obs);
+        hipError_t le = b->sched == XY_BATCH_PASSES ? enqueue_passes(b, b->cap, (int)n_sweeps, me, obs)
+                                                    : enqueue_batch(b, b->cap, (int)n_sweeps, me, obs);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess) {
@@ -602,6 +726,7 @@ int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs*
         b->g_me = me;
         b->g_obs = obs;
         b->g_grid = b->grid;
+        b->g_sched = b->sched;
     }
     if ((e = hipGraphLaunch(b->exec, b->stream)) != hipSuccess) return xyr::hip_fail(e, "hipGraphLaunch");
     b->sweep += (uint64_t)n_sweeps;
@@ -629,8 +754,11 @@ int xy_batch_autotune(xy_batch* b, int32_t sweeps_per_trial, int32_t* tile_x, in
     }
     double best = 1e300;
     Shape bs = b->shape;
+    int bsched = b->sched;
     int rc = XY_OK;
-    for (const Shape& s : cands) {
+    for (int ci = 0; ci < 2 * (int)cands.size(); ++ci) {
+        const Shape s = cands[ci >> 1];
+        b->sched = (ci & 1) ? XY_BATCH_PERSISTENT : XY_BATCH_PASSES;
         if ((rc = plan_batch(b, s)) != XY_OK) break;
         if ((rc = xy_batch_sweep(b, sweeps_per_trial, 0, nullptr)) != XY_OK) break;   // warm-up, capture
         if ((e = hipEventRecord(e0, b->stream)) != hipSuccess) { rc = xyr::hip_fail(e, "hipEventRecord"); break; }
@@ -642,10 +770,12 @@ int xy_batch_autotune(xy_batch* b, int32_t sweeps_per_trial, int32_t* tile_x, in
         if (ms < best) {
             best = ms;
             bs = s;
+            bsched = b->sched;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    b->sched = bsched;
     if (rc != XY_OK) return rc;
     if ((rc = plan_batch(b, bs)) != XY_OK) return rc;
     if (tile_x) *tile_x = bs.tx;
@@ -666,6 +796,21 @@ int xy_batch_get_tile(const xy_batch* b, int32_t* tile_x, int32_t* tile_y)
     if (!blive(b)) return XY_ESTATE;
     if (tile_x) *tile_x = b->shape.tx;
     if (tile_y) *tile_y = b->shape.ty;
+    return XY_OK;
+}
+
+int xy_batch_set_schedule(xy_batch* b, int32_t schedule)
+{
+    if (!blive(b)) return XY_ESTATE;
+    if (schedule != XY_BATCH_PERSISTENT && schedule != XY_BATCH_PASSES) return XY_EINVAL;
+    b->sched = schedule;
+    return XY_OK;
+}
+
+int xy_batch_get_schedule(const xy_batch* b, int32_t* schedule)
+{
+    if (!blive(b) || !schedule) return XY_ESTATE;
+    *schedule = b->sched;
     return XY_OK;
 }
 

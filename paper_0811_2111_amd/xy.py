@@ -26,6 +26,7 @@ XY_OK, XY_EINVAL, XY_ESIZE, XY_ERANGE, XY_EHIP, XY_ESTATE, XY_ENOMEM, XY_EBARRIE
 XY_FP32, XY_FP16 = 0, 1
 XY_HOT, XY_COLD = 0, 1
 XY_PLAN_AUTO, XY_PLAN_STREAM, XY_PLAN_FUSED, XY_PLAN_STRIP = 0, 1, 2, 3
+XY_BATCH_PERSISTENT, XY_BATCH_PASSES = 0, 1
 _PREC = {"fp32": XY_FP32, "fp16": XY_FP16, XY_FP32: XY_FP32, XY_FP16: XY_FP16}
 _START = {"hot": XY_HOT, "cold": XY_COLD, XY_HOT: XY_HOT, XY_COLD: XY_COLD}
 
@@ -94,6 +95,8 @@ def _load():
         "xy_batch_set_tile": [vp, i32, i32],
         "xy_batch_get_tile": [vp, P(i32), P(i32)],
         "xy_batch_autotune": [vp, i32, P(i32), P(i32)],
+        "xy_batch_set_schedule": [vp, i32],
+        "xy_batch_get_schedule": [vp, P(i32)],
         "xy_batch_status": [vp],
         "xy_batch_free": [vp],
         "xy_hmc_work_bytes": [i32, P(sz)],
@@ -378,10 +381,21 @@ class Batch:
         check(_lib.xy_batch_set_tile(self.h, int(tile_x), int(tile_y)), "xy_batch_set_tile")
 
     def autotune(self, sweeps_per_trial: int = 4):
+        """Pick the fastest tile shape and schedule; returns the shape."""
         tx, ty = ctypes.c_int32(), ctypes.c_int32()
         check(_lib.xy_batch_autotune(self.h, int(sweeps_per_trial), ctypes.byref(tx), ctypes.byref(ty)),
               "xy_batch_autotune")
         return tx.value, ty.value
+
+    @property
+    def schedule(self) -> int:
+        v = ctypes.c_int32()
+        check(_lib.xy_batch_get_schedule(self.h, ctypes.byref(v)), "xy_batch_get_schedule")
+        return v.value
+
+    def set_schedule(self, schedule: int):
+        """XY_BATCH_PERSISTENT (one persistent kernel per call) or XY_BATCH_PASSES (one launch per sweep)."""
+        check(_lib.xy_batch_set_schedule(self.h, int(schedule)), "xy_batch_set_schedule")
 
 
 class Quad:

@@ -286,15 +286,21 @@ def test_full_size_sampled_sites(orc, L, beta, delta):
 
 # ----------------------------------------------------------------- batches
 
-def test_batch_equals_single_and_graph_replays():
+SCHEDULES = [0, 1]      # XY_BATCH_PERSISTENT, XY_BATCH_PASSES
+
+
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_batch_equals_single_and_graph_replays(sched):
     """Each lattice of a batch follows, bit for bit, the trajectory it follows alone;
     the captured graph is replayed correctly call after call (eager work and host
-    synchronisation in between), with odd and even sweep counts."""
+    synchronisation in between), with odd and even sweep counts; both schedules."""
     Ls = [64, 128, 64, 256, 192]
     seeds = [11, 12, 13, 14, 15]
     betas = [0.8, 1.0, 1.2, 1.3, 0.95]
     deltas = [1.0, 1.0, 1.2, 0.8, 1.0]
     b = xy.Batch(Ls, seeds, betas, deltas)
+    b.set_schedule(sched)
+    assert b.schedule == sched
     singles = [xy.Lattice(L, seed=s, beta=bb, delta=d) for L, s, bb, d in zip(Ls, seeds, betas, deltas)]
     for n, me in [(7, 1), (7, 1), (7, 1), (6, 2), (5, 0)]:
         ob = b.sweep(n, me)
@@ -313,10 +319,12 @@ def test_batch_equals_single_and_graph_replays():
     b.status()
 
 
+@pytest.mark.parametrize("sched", SCHEDULES)
 @pytest.mark.parametrize("Ls", [[4, 8, 12], [32, 48, 16], [64, 64, 128]])
-def test_batch_tile_shapes_and_small_lattices(Ls):
+def test_batch_tile_shapes_and_small_lattices(Ls, sched):
     n = len(Ls)
     b = xy.Batch(Ls, list(range(1, n + 1)), [1.0] * n, [1.0] * n)
+    b.set_schedule(sched)
     singles = [xy.Lattice(L, seed=i + 1, beta=1.0, delta=1.0) for i, L in enumerate(Ls)]
     b.sweep(5)
     b.status()
@@ -327,18 +335,26 @@ def test_batch_tile_shapes_and_small_lattices(Ls):
 
 
 def test_batch_set_tile_invariance():
+    """Every tile shape under both schedules, and a switch of schedule between
+    calls, gives the same angles bit for bit."""
     Ls = [64, 128, 256]
     ref = None
     for tile in [(64, 32), (64, 16), (32, 16)]:
-        b = xy.Batch(Ls, [5, 6, 7], [1.1, 1.0, 0.9], [1.0, 1.0, 1.0])
-        b.set_tile(*tile)
-        assert b.tile == tile
-        b.sweep(6)
-        b.status()
-        if ref is None:
-            ref = b.state.clone()
-        else:
-            assert torch.equal(b.state, ref), tile
+        for sched in SCHEDULES:
+            b = xy.Batch(Ls, [5, 6, 7], [1.1, 1.0, 0.9], [1.0, 1.0, 1.0])
+            b.set_tile(*tile)
+            b.set_schedule(sched)
+            assert b.tile == tile
+            b.sweep(3)
+            b.set_schedule(1 - sched)
+            b.sweep(3)
+            b.status()
+            if ref is None:
+                ref = b.state.clone()
+            else:
+                assert torch.equal(b.state, ref), (tile, sched)
+    L_ = xy.lib()
+    assert L_.xy_batch_set_schedule(b.h, 2) == xy.XY_EINVAL
 
 
 # ------------------------------------------------------------- edge cases
