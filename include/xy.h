@@ -276,14 +276,16 @@ int xy_tuned_plan(const char* cache_path, int32_t L, int32_t precision, xy_plan*
  * into a HIP graph and replayed.  Lattice i's angles start at element offset
  * sum_{j<i} L[j]^2 of state_dev, in the single-lattice layout.  A lattice
  * follows exactly the trajectory it would follow alone with the same seed.
- * Two schedules (xy_batch_set_schedule), the same trajectory:
+ * Three schedules (xy_batch_set_schedule), the same trajectory:
  *   XY_BATCH_PERSISTENT: one persistent kernel per call; every workgroup owns a
  *     contiguous range of the tiles of all lattices and waits, before each pass
  *     over a lattice, for the previous pass of that lattice (per-lattice
  *     counters in device memory);
- *   XY_BATCH_PASSES (default): one launch per sweep over all tiles of all
- *     lattices, one workgroup per tile; the kernel boundary orders the sweeps. */
-enum { XY_BATCH_PERSISTENT = 0, XY_BATCH_PASSES = 1 };
+ *   XY_BATCH_PASSES: one launch per sweep over all tiles of all lattices, one
+ *     workgroup per tile; the kernel boundary orders the sweeps;
+ *   XY_BATCH_PASSES_WIDE (default): the same, with 256 x 16 tiles for every
+ *     lattice whose L is a multiple of 256 (the batch's shape for the others). */
+enum { XY_BATCH_PERSISTENT = 0, XY_BATCH_PASSES = 1, XY_BATCH_PASSES_WIDE = 2 };
 int xy_batch_state_bytes(int32_t n, const int32_t* L, int32_t precision,
                          size_t* state, size_t* workspace);
 int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_t* L,
@@ -300,9 +302,9 @@ int xy_batch_get_sweep(const xy_batch* b, uint64_t* sweep);
  * allows; else the largest of 16x16, 8x8, 4x4 that divides every L). */
 int xy_batch_set_tile(xy_batch* b, int32_t tile_x, int32_t tile_y);
 int xy_batch_get_tile(const xy_batch* b, int32_t* tile_x, int32_t* tile_y);
-int xy_batch_set_schedule(xy_batch* b, int32_t schedule);   /* XY_EINVAL if not one of the two */
+int xy_batch_set_schedule(xy_batch* b, int32_t schedule);   /* XY_EINVAL if not one of the three */
 int xy_batch_get_schedule(const xy_batch* b, int32_t* schedule);
-/* Time every candidate tile shape under both schedules for `sweeps_per_trial`
+/* Time every candidate tile shape under every schedule for `sweeps_per_trial`
  * sweeps (after one untimed trial that also captures the graph) and keep the
  * fastest (shape and schedule).  The trials
  * advance the batch: run it on a scratch batch of the same sizes. */

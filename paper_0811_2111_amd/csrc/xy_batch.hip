@@ -48,9 +48,14 @@ struct LatDesc {
     int ntiles;
     int arrivals;         // workgroups owning tiles of this lattice
     int reducer;          // workgroup that reduces this lattice's measurements
+    int wide;             // tiles of kWideX x kWideY instead of the batch's shape (per-sweep schedule)
     uint32_t key0, key1;
     float delta, nbl2e;
 };
+
+// Tile shape of the lattices that take wide tiles under XY_BATCH_PASSES_WIDE:
+// the fastest single-lattice shape.
+constexpr int kWideX = 256, kWideY = 16;
 
 struct Ctrl {
     uint32_t sweep0;      // absolute sweep index of the next pass (advanced by k_batch_advance)
@@ -215,17 +220,26 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
 
 __global__ void k_batch_advance(Ctrl* ctrl, uint32_t n) { ctrl->sweep0 += n; }
 
+// LDS of a per-pass kernel: the larger of the two tile programs it may run, then
+// the workgroup's reduction slots.
+template <int TX, int TY, bool WIDE>
+constexpr size_t pass_lds()
+{
+    constexpr size_t a = Tile1<TX, TY, 256>::lds_bytes, w = Tile1<kWideX, kWideY, 256>::lds_bytes;
+    return (WIDE && w > a ? w : a) + Tile1<TX, TY, 256>::red_bytes;
+}
+
 // One pass of the per-pass schedule: workgroup b sweeps tile t (XCD-aware order:
 // each XCD takes a contiguous run of the work list, so neighbouring tiles share
-// its L2).  MEAS = -1: measured, one record per tile at part[t * 8]; 0: not.
-template <typename T, int TX, int TY, int MEAS>
+// its L2).  WIDE: lattices flagged wide are cut into kWideX x kWideY tiles.
+// MEAS = -1: measured, one record per tile at part[t * 8]; 0: not.
+template <typename T, int TX, int TY, int MEAS, bool WIDE>
 __global__ void __launch_bounds__(256)
 k_batch_pass(const T* __restrict__ src, T* __restrict__ dst, const LatDesc* __restrict__ lat, int nlat,
              int total_tiles, const Ctrl* __restrict__ ctrl, int p, double* __restrict__ part)
 {
     extern __shared__ __align__(16) char smem[];
-    using S = Tile1<TX, TY, 256>;
-    double* red = (double*)(smem + S::lds_bytes);
+    double* red = (double*)(smem + pass_lds<TX, TY, WIDE>() - Tile1<TX, TY, 256>::red_bytes);
     const int b = (int)blockIdx.x;
     const int t = (total_tiles & 7) ? b : (b & 7) * (total_tiles >> 3) + (b >> 3);
     const int i = lattice_of(lat, nlat, t);
@@ -233,9 +247,15 @@ k_batch_pass(const T* __restrict__ src, T* __restrict__ dst, const LatDesc* __re
     const int lt = t - d.first_tile;
     const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
     const Params prm{d.delta, d.nbl2e};
-    tile1_program<T, TX, TY, 256, MEAS>(src + d.off, dst + d.off, (unsigned)((size_t)d.L * d.L * sizeof(T)), d.L,
-                                        tx * TX, ty * TY, ctrl->sweep0 + (uint32_t)p, d.key0, d.key1, prm, MEAS != 0,
-                                        part + (size_t)t * 8, smem, red);
+    const unsigned bytes = (unsigned)((size_t)d.L * d.L * sizeof(T));
+    const uint32_t sweep = ctrl->sweep0 + (uint32_t)p;
+    if (WIDE && d.wide)
+        tile1_program<T, kWideX, kWideY, 256, MEAS>(src + d.off, dst + d.off, bytes, d.L, tx * kWideX, ty * kWideY,
+                                                    sweep, d.key0, d.key1, prm, MEAS != 0, part + (size_t)t * 8,
+                                                    smem, red);
+    else
+        tile1_program<T, TX, TY, 256, MEAS>(src + d.off, dst + d.off, bytes, d.L, tx * TX, ty * TY, sweep, d.key0,
+                                            d.key1, prm, MEAS != 0, part + (size_t)t * 8, smem, red);
 }
 
 // Records of measured pass p (one workgroup per lattice, fixed order): record r of
@@ -381,21 +401,22 @@ static void* kernel_ptr()
     return (void*)k_batch<T, TX, TY, kNT>;
 }
 
-template <typename T, int TX, int TY, int MEAS>
-static void* pass_kernel_ptr()
+template <typename T, int TX, int TY, bool WIDE>
+static void* pass_kernel_ptr(bool meas)
 {
-    return (void*)k_batch_pass<T, TX, TY, MEAS>;
+    return meas ? (void*)k_batch_pass<T, TX, TY, -1, WIDE> : (void*)k_batch_pass<T, TX, TY, 0, WIDE>;
 }
 
-// The per-pass kernel for shape s (measured or not) and its LDS bytes.
-static void* pass_kernel(int precision, Shape s, bool meas, size_t* lds)
+// The per-pass kernel for shape s (wide tiles or not, measured or not) and its LDS bytes.
+static void* pass_kernel(int precision, Shape s, bool wide, bool meas, size_t* lds)
 {
 #define XYB_CASE(TXV, TYV)                                                                          \
     if (s.tx == TXV && s.ty == TYV) {                                                               \
-        *lds = Tile1<TXV, TYV, kNT>::lds_bytes + Tile1<TXV, TYV, kNT>::red_bytes;                   \
+        *lds = wide ? pass_lds<TXV, TYV, true>() : pass_lds<TXV, TYV, false>();                     \
         if (precision == XY_FP16)                                                                   \
-            return meas ? pass_kernel_ptr<__half, TXV, TYV, -1>() : pass_kernel_ptr<__half, TXV, TYV, 0>(); \
-        return meas ? pass_kernel_ptr<float, TXV, TYV, -1>() : pass_kernel_ptr<float, TXV, TYV, 0>();       \
+            return wide ? pass_kernel_ptr<__half, TXV, TYV, true>(meas)                             \
+                        : pass_kernel_ptr<__half, TXV, TYV, false>(meas);                           \
+        return wide ? pass_kernel_ptr<float, TXV, TYV, true>(meas) : pass_kernel_ptr<float, TXV, TYV, false>(meas); \
     }
     XYB_CASE(64, 32)
     XYB_CASE(64, 16)
@@ -478,9 +499,9 @@ static int plan_batch(xy_batch* b, Shape s)
     if (!k) return XY_EINVAL;
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return xyr::hip_fail(e, "hipFuncSetAttribute");
-    for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < 4; ++m) {
         size_t pl = 0;
-        void* pk = pass_kernel(b->precision, s, m == 1, &pl);
+        void* pk = pass_kernel(b->precision, s, (m & 2) != 0, (m & 1) != 0, &pl);
         if (!pk) return XY_EINVAL;
         if ((e = hipFuncSetAttribute(pk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl)) != hipSuccess)
             return xyr::hip_fail(e, "hipFuncSetAttribute");
@@ -499,9 +520,11 @@ static int plan_batch(xy_batch* b, Shape s)
         LatDesc& d = b->desc[i];
         d.off = off;
         d.L = b->L[i];
-        d.tiles_x = d.L / s.tx;
+        d.wide = b->sched == XY_BATCH_PASSES_WIDE && d.L % kWideX == 0 && d.L % kWideY == 0;
+        const int tx = d.wide ? kWideX : s.tx, ty = d.wide ? kWideY : s.ty;
+        d.tiles_x = d.L / tx;
         d.first_tile = total;
-        d.ntiles = (d.L / s.tx) * (d.L / s.ty);
+        d.ntiles = (d.L / tx) * (d.L / ty);
         xyk::SweepArgs a = xyr::sweep_args(b->seed[i], d.L, b->precision, b->beta[i], b->delta[i]);
         d.key0 = a.key0;
         d.key1 = a.key1;
@@ -576,7 +599,7 @@ static hipError_t enqueue_passes(xy_batch* b, hipStream_t s, int npass, int32_t 
     for (int p = 0; p < npass; ++p) {
         const bool meas = me > 0 && ((p + 1) % me) == 0;
         size_t lds = 0;
-        void* k = pass_kernel(b->precision, b->shape, meas, &lds);
+        void* k = pass_kernel(b->precision, b->shape, b->sched == XY_BATCH_PASSES_WIDE, meas, &lds);
         void* src = (p & 1) ? pp : (void*)b->state;
         void* dst = (p & 1) ? (void*)b->state : pp;
         int pv = p;
@@ -652,7 +675,7 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->g_obs = nullptr;
     b->g_grid = 0;
     b->g_sched = -1;
-    b->sched = XY_BATCH_PASSES;
+    b->sched = XY_BATCH_PASSES_WIDE;
     auto fail = [&](int code) {
         drop_graph(b);
         if (b->cap) (void)hipStreamDestroy(b->cap);
@@ -707,8 +730,8 @@ int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs*
         drop_graph(b);
         if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return xyr::hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = b->sched == XY_BATCH_PASSES ? enqueue_passes(b, b->cap, (int)n_sweeps, me, obs)
-                                                    : enqueue_batch(b, b->cap, (int)n_sweeps, me, obs);
+        hipError_t le = b->sched == XY_BATCH_PERSISTENT ? enqueue_batch(b, b->cap, (int)n_sweeps, me, obs)
+                                                        : enqueue_passes(b, b->cap, (int)n_sweeps, me, obs);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess) {
@@ -756,9 +779,10 @@ int xy_batch_autotune(xy_batch* b, int32_t sweeps_per_trial, int32_t* tile_x, in
     Shape bs = b->shape;
     int bsched = b->sched;
     int rc = XY_OK;
-    for (int ci = 0; ci < 2 * (int)cands.size(); ++ci) {
-        const Shape s = cands[ci >> 1];
-        b->sched = (ci & 1) ? XY_BATCH_PERSISTENT : XY_BATCH_PASSES;
+    static const int scheds[3] = {XY_BATCH_PASSES_WIDE, XY_BATCH_PASSES, XY_BATCH_PERSISTENT};
+    for (int ci = 0; ci < 3 * (int)cands.size(); ++ci) {
+        const Shape s = cands[ci / 3];
+        b->sched = scheds[ci % 3];
         if ((rc = plan_batch(b, s)) != XY_OK) break;
         if ((rc = xy_batch_sweep(b, sweeps_per_trial, 0, nullptr)) != XY_OK) break;   // warm-up, capture
         if ((e = hipEventRecord(e0, b->stream)) != hipSuccess) { rc = xyr::hip_fail(e, "hipEventRecord"); break; }
@@ -802,9 +826,14 @@ int xy_batch_get_tile(const xy_batch* b, int32_t* tile_x, int32_t* tile_y)
 int xy_batch_set_schedule(xy_batch* b, int32_t schedule)
 {
     if (!blive(b)) return XY_ESTATE;
-    if (schedule != XY_BATCH_PERSISTENT && schedule != XY_BATCH_PASSES) return XY_EINVAL;
+    if (schedule != XY_BATCH_PERSISTENT && schedule != XY_BATCH_PASSES && schedule != XY_BATCH_PASSES_WIDE)
+        return XY_EINVAL;
+    if (schedule == b->sched) return XY_OK;
+    const int old = b->sched;
     b->sched = schedule;
-    return XY_OK;
+    const int rc = plan_batch(b, b->shape);   // the work list depends on the schedule
+    if (rc != XY_OK) b->sched = old;
+    return rc;
 }
 
 int xy_batch_get_schedule(const xy_batch* b, int32_t* schedule)

@@ -26,7 +26,7 @@ XY_OK, XY_EINVAL, XY_ESIZE, XY_ERANGE, XY_EHIP, XY_ESTATE, XY_ENOMEM, XY_EBARRIE
 XY_FP32, XY_FP16 = 0, 1
 XY_HOT, XY_COLD = 0, 1
 XY_PLAN_AUTO, XY_PLAN_STREAM, XY_PLAN_FUSED, XY_PLAN_STRIP = 0, 1, 2, 3
-XY_BATCH_PERSISTENT, XY_BATCH_PASSES = 0, 1
+XY_BATCH_PERSISTENT, XY_BATCH_PASSES, XY_BATCH_PASSES_WIDE = 0, 1, 2
 _PREC = {"fp32": XY_FP32, "fp16": XY_FP16, XY_FP32: XY_FP32, XY_FP16: XY_FP16}
 _START = {"hot": XY_HOT, "cold": XY_COLD, XY_HOT: XY_HOT, XY_COLD: XY_COLD}
 
@@ -230,7 +230,7 @@ class Lattice:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:   # _lib is None at interpreter shutdown
             _lib.xy_free(h)
             self.h = None
 
@@ -325,7 +325,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:   # _lib is None at interpreter shutdown
             _lib.xy_batch_free(h)
             self.h = None
 
@@ -394,7 +394,8 @@ class Batch:
         return v.value
 
     def set_schedule(self, schedule: int):
-        """XY_BATCH_PERSISTENT (one persistent kernel per call) or XY_BATCH_PASSES (one launch per sweep)."""
+        """XY_BATCH_PERSISTENT (one persistent kernel per call), XY_BATCH_PASSES (one launch per
+        sweep) or XY_BATCH_PASSES_WIDE (the same with 256 x 16 tiles where L allows)."""
         check(_lib.xy_batch_set_schedule(self.h, int(schedule)), "xy_batch_set_schedule")
 
 
@@ -421,7 +422,7 @@ class Quad:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None:   # _lib is None at interpreter shutdown
             _lib.xy_quad_free(h)
             self.h = None
 

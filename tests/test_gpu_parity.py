@@ -286,7 +286,7 @@ def test_full_size_sampled_sites(orc, L, beta, delta):
 
 # ----------------------------------------------------------------- batches
 
-SCHEDULES = [0, 1]      # XY_BATCH_PERSISTENT, XY_BATCH_PASSES
+SCHEDULES = [0, 1, 2]   # XY_BATCH_PERSISTENT, XY_BATCH_PASSES, XY_BATCH_PASSES_WIDE
 
 
 @pytest.mark.parametrize("sched", SCHEDULES)
@@ -335,18 +335,19 @@ def test_batch_tile_shapes_and_small_lattices(Ls, sched):
 
 
 def test_batch_set_tile_invariance():
-    """Every tile shape under both schedules, and a switch of schedule between
-    calls, gives the same angles bit for bit."""
-    Ls = [64, 128, 256]
+    """Every tile shape under every schedule, and a switch of schedule between
+    calls, gives the same angles bit for bit (L = 256 and 512 take wide tiles under
+    XY_BATCH_PASSES_WIDE)."""
+    Ls = [64, 128, 256, 512]
     ref = None
     for tile in [(64, 32), (64, 16), (32, 16)]:
         for sched in SCHEDULES:
-            b = xy.Batch(Ls, [5, 6, 7], [1.1, 1.0, 0.9], [1.0, 1.0, 1.0])
+            b = xy.Batch(Ls, [5, 6, 7, 8], [1.1, 1.0, 0.9, 0.85], [1.0, 1.0, 1.0, 1.1])
             b.set_tile(*tile)
             b.set_schedule(sched)
             assert b.tile == tile
             b.sweep(3)
-            b.set_schedule(1 - sched)
+            b.set_schedule((sched + 1) % 3)
             b.sweep(3)
             b.status()
             if ref is None:
@@ -354,7 +355,7 @@ def test_batch_set_tile_invariance():
             else:
                 assert torch.equal(b.state, ref), (tile, sched)
     L_ = xy.lib()
-    assert L_.xy_batch_set_schedule(b.h, 2) == xy.XY_EINVAL
+    assert L_.xy_batch_set_schedule(b.h, 3) == xy.XY_EINVAL
 
 
 # ------------------------------------------------------------- edge cases
