@@ -28,27 +28,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0                    # MI355X HBM3E
-# VALU issue slots: one wave64 instruction at the FP32 rate (2 cycles per SIMD).
-# 256 CUs x 128 FP32 lanes x 2.4 GHz = 78.6 T slots/s (the FP32 FMA rate, half of
-# the 157.3 TFLOP/s vector peak).
+# VALU issue slots: one slot = the issue cost of one wave64 v_add_f32.  Peak:
+# 256 CUs x 128 FP32 lanes x 2.4 GHz = 78.6 T slots/s (the non-packed FP32 rate,
+# half of the 157.3 TFLOP/s vector FMA peak).
 VALU_PEAK_TSLOTS = 256 * 128 * 2.4e9 / 1e12
-# Algorithmic VALU slots of one site update of a sweep that reads the angles once
-# (v_mad_u64_u32 = 2 slots, sin/cos/exp = 4, every other instruction 1):
-#   half a Philox4x32-10 call: 16 multiplies + 18 xors per call      25
-#   two uniforms (2 alignbit, fma + add, sub)                         5
-#   proposal: multiply, add, fract                                    3
-#   sin and cos of the proposal                                       8
-#   sin and cos of the site's loaded angle (the (cos, sin) cache)     8
-#   two neighbour sums of four terms                                  6
-#   dE (2 sub, mul, fma)                                              4
-#   acceptance (mul, exp2, compare)                                   6
-#   three selects                                                     3
-ALG_SLOTS_PER_UPDATE = 68.0
+# Algorithmic VALU slots of one site update of a sweep that reads the angles once,
+# with the issue costs measured on MI355X relative to v_add_f32
+# (paper_0811_2111_amd/probes/issue_cost.hip: v_mad_u64_u32 2.76, v_sin/v_cos 3.42,
+# v_exp 3.50, v_bitop3_b32 1.72, v_fma/v_fmaak 1.14, v_fract 1.06, others 1) and the
+# instruction counts of the compiled update:
+#   half a Philox4x32-10 call (16.5 v_mad_u64_u32, 13 v_bitop3, 3 v_xor per call)   35.5
+#   two uniforms (2 alignbit, fmaak, 2 add)                                         5.1
+#   proposal: multiply, add, fract                                                  3.1
+#   sin and cos of the proposal                                                     6.8
+#   sin and cos of the site's loaded angle (the (cos, sin) shared with neighbours)  6.8
+#   two neighbour sums of four terms                                                6
+#   dE (2 sub, mul, fma)                                                            4.1
+#   acceptance (mul, exp2, compare)                                                 5.5
+#   three selects                                                                   3
+ALG_SLOTS_PER_UPDATE = 76.0
 ALG_BYTES_FUSED = 8.0                    # bytes per site-update of one fused sweep: read 4 + write 4 (FP32)
 ALG_BYTES_STREAM = 12.0                  # two half-sweep passes: read both colours, write one, per half
 ALG_BYTES_HMC_STEP = 16.0                # one leap-frog step: read and write the angle and the momentum
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
 PLAN_NAMES = {1: "stream", 2: "fused", 3: "strip"}
+BATCH_SCHEDULES = {0: "persistent", 1: "per-sweep launches", 2: "per-sweep launches, 256x16 tiles where L allows"}
 KERNEL_NAMES = {1: "k_half_sweep", 2: "k_fused (LDS-tiled fused red+black sweep)",
                 3: "k_strip (strip segment, rows streamed through LDS rings)"}
 KERNEL_SOURCES = ["xy_device.hpp", "xy_tile1.hpp", "xy_fused.hip"]
@@ -95,6 +99,9 @@ def parse():
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc"], default="l4096",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
+    ap.add_argument("--schedule", type=int, default=None,
+                    help="with --kernel-only --workload batch: batch schedule (0 persistent, 1 per-sweep, "
+                         "2 per-sweep with wide tiles; default: the library's)")
     return ap.parse_args()
 
 
@@ -243,6 +250,8 @@ def profile_leg(args, stream):
     else:
         sc = workloads.temperature_scan()
         b = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+        if args.schedule is not None:
+            b.set_schedule(args.schedule)
         nrec = max(args.steps // sc["measure_every"], 1)
         bobs = torch.empty((len(sc["Ls"]), nrec, 8), dtype=torch.float64, device="cuda")
         b.sweep(args.warmup)
@@ -281,9 +290,11 @@ def extra_legs(stream, main_lat=None):
     sites = sum(L * L for L in sc["Ls"])
     tune = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
     tile = tune.autotune(20)
+    sched = tune.schedule
     del tune
     b = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
     b.set_tile(*tile)
+    b.set_schedule(sched)
     nrec = sc["sweeps"] // sc["measure_every"]
     bobs = torch.empty((n, nrec, 8), dtype=torch.float64, device="cuda")
     b.sweep(20)
@@ -303,6 +314,7 @@ def extra_legs(stream, main_lat=None):
     g_p = float(sites) * per_sweeps / (ms_p * 1e-3) / 1e9
     ex["batched_scan_96"] = {
         "lattices": n, "sites": sites, "sweeps": sc["sweeps"], "tile": list(tile),
+        "schedule": BATCH_SCHEDULES[sched],
         "batched_gupd_s": round(g_b, 2), "batched_ms": round(ms_b, 2),
         "per_lattice_gupd_s": round(g_p, 2), "per_lattice_sweeps_timed": per_sweeps,
         "speedup": round(g_b / g_p, 2)}
@@ -312,6 +324,7 @@ def extra_legs(stream, main_lat=None):
     # parallel tempering over the same scan: ladders of equal L, rounds of 10 sweeps
     tb = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
     tb.set_tile(*tile)
+    tb.set_schedule(sched)
     rounds, K = sc["sweeps"] // sc["measure_every"], sc["measure_every"]
     tb.tempering(2, K, 1)
     trec = torch.empty((rounds, n, 8), dtype=torch.float64, device="cuda")

@@ -10,12 +10,21 @@ using namespace xyd;
 namespace xyk {
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
-// Remap so that each XCD takes whole strips, segment after segment: the halo rows
-// two consecutive segments of a strip share stay in that XCD's L2.
-__device__ __forceinline__ int xcd_strip(int b, int n)
+// Remap so that each XCD takes a band of whole strips and walks it segment row by
+// segment row: the workgroups resident on an XCD at one time hold neighbouring
+// segments of neighbouring strips, so the halo rows shared with the segments
+// above and below and the edge columns shared with the strips beside come from
+// that XCD's L2.
+__device__ __forceinline__ void xcd_strip(int b, int nsx, int nsy, int& sx, int& sy)
 {
-    if ((n & 7) != 0) return b;
-    return (b & 7) * (n >> 3) + (b >> 3);
+    if ((nsx & 7) == 0) {
+        const int spx = nsx >> 3, i = b >> 3;
+        sx = (b & 7) * spx + i % spx;
+        sy = i / spx;
+        return;
+    }
+    sx = b / nsy;
+    sy = b - sx * nsy;
 }
 
 template <typename T, int TX, int SH, bool MEAS>
@@ -24,12 +33,10 @@ k_strip(const T* __restrict__ src, T* __restrict__ dst, int L, uint32_t sweep, u
         double* __restrict__ partials)
 {
     extern __shared__ __align__(16) char smem[];
-    const int nsy = L / SH;
-    const int n = (L / TX) * nsy;
-    const int b = xcd_strip((int)blockIdx.x, n);
-    const int sx = b / nsy, sy = b - sx * nsy;
+    int sx, sy;
+    xcd_strip((int)blockIdx.x, L / TX, L / SH, sx, sy);
     strip_program<T, TX, SH, 256, MEAS>(src, dst, (unsigned)((size_t)L * L * sizeof(T)), L, sx * TX, sy * SH, sweep,
-                                       k0, k1, p, partials + (size_t)b * 4 * 8, smem);
+                                       k0, k1, p, partials + (size_t)blockIdx.x * 4 * 8, smem);
 }
 
 template <typename T, int TX, int SH, bool MEAS>
