@@ -164,7 +164,7 @@ def main():
 
     # dominant kernel: average duration of one fused or strip launch (no measurement),
     # events on the stream; the streaming plan launches two half-sweeps per sweep
-    nrep = 40
+    nrep = 300                               # 600 sweeps: long enough that launch jitter averages out
     tiled = plan[0] in (xy.XY_PLAN_FUSED, xy.XY_PLAN_STRIP)
     ms_k = timed(lambda: lat.sweep(nrep * plan[3] * 2), stream)
     launches = nrep * 2 if tiled else nrep * 2 * plan[3] * 2

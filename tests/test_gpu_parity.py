@@ -240,13 +240,15 @@ def _light_cone_value(orc, seed, L, beta, delta, x, y, s, memo):
     return v
 
 
-@pytest.mark.parametrize("L,beta,delta", [(4096, 1.12, 1.0), (16384, 1.0, 1.2)])
-def test_full_size_sampled_sites(orc, L, beta, delta):
-    """At the benchmark sizes, with the plan the benchmark runs: two sweeps on the
-    device, then 1500 sampled sites (edges included) against the oracle's site-by-site
-    evaluation of their light cones; the two FP64 records against a float64
-    recomputation from the device state."""
-    lat = xy.Lattice(L, seed=1, beta=beta, delta=delta)
+@pytest.mark.parametrize("L,beta,delta,plan", [(4096, 1.12, 1.0, (2, 256, 16, 1)), (16384, 1.0, 1.2, (2, 128, 32, 1)),
+                                                (16384, 1.0, 1.2, (3, 256, 64, 1)),
+                                                (16384, 1.0, 1.2, (3, 256, 128, 1))])
+def test_full_size_sampled_sites(orc, L, beta, delta, plan):
+    """At the benchmark sizes, with the plans the benchmark's autotuner picks among:
+    two sweeps on the device, then 1500 sampled sites (edges included) against the
+    oracle's site-by-site evaluation of their light cones; the two FP64 records
+    against a float64 recomputation from the device state."""
+    lat = xy.Lattice(L, seed=1, beta=beta, delta=delta, plan=plan)
     obs = lat.sweep(2, 1)
     recs = xy.records(obs)
     rng = np.random.default_rng(L)
@@ -356,6 +358,24 @@ def test_batch_set_tile_invariance():
                 assert torch.equal(b.state, ref), (tile, sched)
     L_ = xy.lib()
     assert L_.xy_batch_set_schedule(b.h, 3) == xy.XY_EINVAL
+
+
+def test_scan96_batch_equals_single_lattices():
+    """The benchmark's 96-lattice temperature scan, batched with the default schedule
+    (per-sweep launches, wide tiles where L allows), against each lattice run alone:
+    bit-identical angles and accept counts after 5 sweeps with records."""
+    from paper_0811_2111_amd import workloads
+    sc = workloads.temperature_scan()
+    n = len(sc["Ls"])
+    b = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+    assert b.schedule == xy.XY_BATCH_PASSES_WIDE
+    ob = b.sweep(5, 5)
+    for i in range(n):
+        s = xy.Lattice(sc["Ls"][i], seed=sc["seeds"][i], beta=sc["betas"][i], delta=sc["deltas"][i])
+        os_ = s.sweep(5, 5)
+        assert torch.equal(b.lattice_state(i), s.state), i
+        assert np.array_equal(xy.records(ob[i])["n_accept"], xy.records(os_)["n_accept"]), i
+        del s
 
 
 # ------------------------------------------------------------- edge cases
