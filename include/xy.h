@@ -239,8 +239,9 @@ typedef struct xy_hmc_obs {
     double cx, cy, ix, iy, mx, my;   /* sums as in xy_obs, of the state after the Metropolis step */
 } xy_hmc_obs;
 
-/* Bytes of device workspace xy_hmc needs for an L x L lattice (momenta, saved
- * angles, partial sums, accept flag): 8 L^2 + 256 + 2 * (65536 + 256) * 64. */
+/* Bytes of device workspace xy_hmc needs for an L x L lattice (two momentum
+ * buffers, saved angles, partial sums, accept flag):
+ * 12 L^2 + 256 + 2 * (65536 + 256) * 64. */
 int xy_hmc_work_bytes(int32_t L, size_t* bytes);
 
 /* Run n_traj trajectories of n_md leap-frog steps of size eps (> 0, finite) on
@@ -253,6 +254,15 @@ int xy_hmc_work_bytes(int32_t L, size_t* bytes);
  * 2^32 - 1. */
 int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
            xy_hmc_obs* obs_dev);
+
+/* Leap-frog steps per pass over the lattice (1 .. 8, default 4; XY_EINVAL
+ * otherwise).  With more than one, for L % 32 == 0, a workgroup loads a 32 x 32
+ * tile grown by that many sites on every side, runs the steps on it (the grown
+ * part shrinking by one site per step) and writes the tile back, so HBM traffic
+ * per site and step falls by that factor; the trajectory is bit for bit the
+ * same.  xy_hmc_get_steps_per_pass reports what runs (1 if L % 32 != 0). */
+int xy_hmc_set_steps_per_pass(xy_lattice* h, int32_t steps);
+int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
 
 /* Test support: run ONE sweep with the streaming schedule and write, per site in
  * the state layout (red half then black half), accept_dev[i] = 1/0 and dE_dev[i] =

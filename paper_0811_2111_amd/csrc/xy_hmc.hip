@@ -227,6 +227,120 @@ k_hmc_step2(const float* __restrict__ src, float* __restrict__ dst, float* __res
 
 constexpr int kStepRows = 4;               // rows per thread of k_hmc_step2
 
+// K leap-frog steps per pass (temporal blocking), for L % 32 == 0.  A workgroup
+// owns a 32 x 32 tile of sites (natural coordinates) and loads the angles and
+// momenta of the tile grown by K sites on every side (both colours) into
+// registers (ceil((32 + 2K)^2 / 256) sites per thread); step q updates the sites at distance
+// > q + 1 from the edge of the grown tile, whose neighbours are then all up to
+// date, so after K steps the tile itself is exact and is written to dst / pdst
+// (the momenta ping-pong too: other tiles read this tile's old momenta as
+// their halo).  (cos, sin) of the angles live in two LDS buffers (read one,
+// write the other, one barrier per step).  Every site is updated with exactly
+// the arithmetic of k_hmc_step (neighbour sums (left + right) + (up + down),
+// the same fma), so the trajectory is bit for bit the one-step-per-launch one.
+// kick0: the first step's kick (-beta eps/2 on a trajectory's first step),
+// kick: the others'.  Grid (L/32)^2 workgroups, XCD bands of tile rows.
+constexpr int kMultiTile = 32;
+
+template <int K>
+__global__ void __launch_bounds__(kThreads)
+k_hmc_multi(const float* __restrict__ src, float* __restrict__ dst, const float* __restrict__ psrc,
+            float* __restrict__ pdst, int L, float kick0, float kick, float drift)
+{
+    constexpr int T = kMultiTile, E = T + 2 * K, NE = E * E, M = (NE + kThreads - 1) / kThreads;
+    __shared__ float2 cs[2][NE];
+    const int Hh = L >> 1, nt = L / T;
+    const int b = (int)xcd_band(blockIdx.x, gridDim.x);
+    const int ty = b / nt, tx = b - ty * nt;
+    const int x0 = tx * T - K, y0 = ty * T - K;
+    float th[M], pm[M];
+    unsigned off[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = threadIdx.x + m * kThreads;
+        if (i < NE) {
+            const int ye = i / E, xe = i - ye * E;
+            const int x = wrapi(x0 + xe, L), y = wrapi(y0 + ye, L);
+            off[m] = (unsigned)((((x + y) & 1) * L + y) * Hh + (x >> 1));
+            th[m] = src[off[m]];
+            pm[m] = psrc[off[m]];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = threadIdx.x + m * kThreads;
+        if (i < NE) {
+            float sn, cn;
+            sincos_turn(th[m], sn, cn);
+            cs[0][i] = make_float2(cn, sn);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const float2* cur = cs[q & 1];
+        float2* nxt = cs[(q + 1) & 1];
+        const float kq = q == 0 ? kick0 : kick;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int i = threadIdx.x + m * kThreads;
+            if (i < NE) {
+                const int ye = i / E, xe = i - ye * E;
+                if (xe > q && xe < E - 1 - q && ye > q && ye < E - 1 - q) {
+                    const float2 own = cur[i], l = cur[i - 1], r = cur[i + 1], u = cur[i - E], d = cur[i + E];
+                    Nb n;
+                    n.c = own.x; n.s = own.y;
+                    n.cl = l.x; n.sl = l.y; n.cr = r.x; n.sr = r.y;
+                    n.cu = u.x; n.su = u.y; n.cd = d.x; n.sd = d.y;
+                    pm[m] = __fmaf_rn(kq, sin_sum(n), pm[m]);
+                    th[m] = __builtin_amdgcn_fractf(__fmaf_rn(drift, pm[m], th[m]));
+                    if (q + 1 < K) {
+                        float sn, cn;
+                        sincos_turn(th[m], sn, cn);
+                        nxt[i] = make_float2(cn, sn);
+                    }
+                }
+            }
+        }
+        if (q + 1 < K) __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = threadIdx.x + m * kThreads;
+        if (i < NE) {
+            const int ye = i / E, xe = i - ye * E;
+            if (xe >= K && xe < E - K && ye >= K && ye < E - K) {
+                dst[off[m]] = th[m];
+                pdst[off[m]] = pm[m];
+            }
+        }
+    }
+}
+
+constexpr int kMaxStepsPerPass = 8;
+
+template <int K>
+static void launch_multi(unsigned nb, hipStream_t s, const float* src, float* dst, const float* psrc, float* pdst,
+                         int L, float kick0, float kick, float drift)
+{
+    hipLaunchKernelGGL(k_hmc_multi<K>, dim3(nb), dim3(kThreads), 0, s, src, dst, psrc, pdst, L, kick0, kick, drift);
+}
+
+static void launch_multi_k(int k, unsigned nb, hipStream_t s, const float* src, float* dst, const float* psrc,
+                           float* pdst, int L, float kick0, float kick, float drift)
+{
+    switch (k) {
+    case 1: launch_multi<1>(nb, s, src, dst, psrc, pdst, L, kick0, kick, drift); break;
+    case 2: launch_multi<2>(nb, s, src, dst, psrc, pdst, L, kick0, kick, drift); break;
+    case 3: launch_multi<3>(nb, s, src, dst, psrc, pdst, L, kick0, kick, drift); break;
+    case 4: launch_multi<4>(nb, s, src, dst, psrc, pdst, L, kick0, kick, drift); break;
+    case 5: launch_multi<5>(nb, s, src, dst, psrc, pdst, L, kick0, kick, drift); break;
+    case 6: launch_multi<6>(nb, s, src, dst, psrc, pdst, L, kick0, kick, drift); break;
+    case 7: launch_multi<7>(nb, s, src, dst, psrc, pdst, L, kick0, kick, drift); break;
+    default: launch_multi<8>(nb, s, src, dst, psrc, pdst, L, kick0, kick, drift); break;
+    }
+}
+
 // Final half kick and the partial records of H_new; `copy` != NULL receives the
 // angles (the final ones may sit in the second buffer).  Grid as k_hmc_begin.
 __global__ void __launch_bounds__(kThreads)
@@ -328,7 +442,7 @@ int hmc_records(int L) { return hmc_cols(L) * hmc_row_blocks(L) * (kThreads / 64
 size_t hmc_work_bytes(int L)
 {
     const size_t n = (size_t)L * (size_t)L;
-    return 256 + 2 * n * sizeof(float) + 2 * (size_t)(kHmcMaxRecords + kHmcMaxChunks) * 8 * sizeof(double);
+    return 256 + 3 * n * sizeof(float) + 2 * (size_t)(kHmcMaxRecords + kHmcMaxChunks) * 8 * sizeof(double);
 }
 
 HmcWork hmc_carve(void* work, int L)
@@ -342,6 +456,8 @@ HmcWork hmc_carve(void* work, int L)
     b += n * sizeof(float);
     w.saved = (float*)b;
     b += n * sizeof(float);
+    w.p2 = (float*)b;
+    b += n * sizeof(float);
     w.rec_old = (double*)b;
     b += (size_t)kHmcMaxRecords * 8 * sizeof(double);
     w.rec_new = (double*)b;
@@ -352,8 +468,11 @@ HmcWork hmc_carve(void* work, int L)
     return w;
 }
 
+bool hmc_multi_supported(int L) { return L >= kMultiTile && L % kMultiTile == 0; }
+
 hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w, int L, double beta, double eps,
-                                 int n_md, uint32_t traj, uint32_t k0, uint32_t k1, xy_hmc_obs* obs, hipStream_t s)
+                                 int n_md, int steps_per_pass, uint32_t traj, uint32_t k0, uint32_t k1,
+                                 xy_hmc_obs* obs, hipStream_t s)
 {
     const int cols = hmc_cols(L), rb = hmc_row_blocks(L);
     const dim3 grec((unsigned)(cols * rb)), gstep(cols, L), block(kThreads);
@@ -363,20 +482,40 @@ hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w
     hipLaunchKernelGGL(k_hmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, cols, rb, w.rec_old);
     float* src = state;
     float* dst = pingpong;
-    const bool pairs = (L % (4 * kStepRows)) == 0;
-    const unsigned nstep2 = (unsigned)(2 * ((L / 4 + kThreads - 1) / kThreads)) * (unsigned)(L / kStepRows);
-    for (int q = 0; q < n_md; ++q) {
-        const float kick = (float)(-beta * (q == 0 ? 0.5 * eps : eps));
-        if (pairs)
-            hipLaunchKernelGGL(k_hmc_step2<kStepRows>, dim3(nstep2), block, 0, s, src, dst, w.p, L, kick, drift);
-        else
-            hipLaunchKernelGGL(k_hmc_step, gstep, block, 0, s, src, dst, w.p, L, kick, drift);
-        float* t = src;
-        src = dst;
-        dst = t;
+    float* p = w.p;
+    const float kick_half = (float)(-beta * 0.5 * eps), kick_full = (float)(-beta * eps);
+    if (steps_per_pass > 1 && hmc_multi_supported(L)) {
+        // passes of up to steps_per_pass steps; the momenta ping-pong between p and p2
+        float* pn = w.p2;
+        const unsigned nb = (unsigned)((L / kMultiTile) * (L / kMultiTile));
+        const int kmax = steps_per_pass < kMaxStepsPerPass ? steps_per_pass : kMaxStepsPerPass;
+        for (int q = 0; q < n_md;) {
+            const int k = n_md - q < kmax ? n_md - q : kmax;
+            launch_multi_k(k, nb, s, src, dst, p, pn, L, q == 0 ? kick_half : kick_full, kick_full, drift);
+            float* t = src;
+            src = dst;
+            dst = t;
+            t = p;
+            p = pn;
+            pn = t;
+            q += k;
+        }
+    } else {
+        const bool pairs = (L % (4 * kStepRows)) == 0;
+        const unsigned nstep2 = (unsigned)(2 * ((L / 4 + kThreads - 1) / kThreads)) * (unsigned)(L / kStepRows);
+        for (int q = 0; q < n_md; ++q) {
+            const float kick = q == 0 ? kick_half : kick_full;
+            if (pairs)
+                hipLaunchKernelGGL(k_hmc_step2<kStepRows>, dim3(nstep2), block, 0, s, src, dst, p, L, kick, drift);
+            else
+                hipLaunchKernelGGL(k_hmc_step, gstep, block, 0, s, src, dst, p, L, kick, drift);
+            float* t = src;
+            src = dst;
+            dst = t;
+        }
     }
-    hipLaunchKernelGGL(k_hmc_end, grec, block, 0, s, src, src == state ? nullptr : state, w.p, L,
-                       (float)(-beta * 0.5 * eps), cols, rb, w.rec_new);
+    hipLaunchKernelGGL(k_hmc_end, grec, block, 0, s, src, src == state ? nullptr : state, p, L, kick_half, cols, rb,
+                       w.rec_new);
     hipError_t e = launch_reduce_chunks(w.rec_old, nrec, w.chunk_old, s);
     if (e == hipSuccess) e = launch_reduce_chunks(w.rec_new, nrec, w.chunk_new, s);
     if (e != hipSuccess) return e;

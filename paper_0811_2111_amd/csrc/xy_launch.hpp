@@ -76,6 +76,7 @@ struct HmcWork {
     unsigned* flag;     // accept flag of the last trajectory
     float* p;           // momenta, state layout
     float* saved;       // angles at the start of the trajectory
+    float* p2;          // second momentum buffer (passes of several steps)
     double* rec_old;    // partial records of H_old (8 doubles each)
     double* rec_new;    // partial records of H_new
     double* chunk_old;  // sums of 256 records each
@@ -86,8 +87,12 @@ HmcWork hmc_carve(void* work, int L);
 int hmc_records(int L);
 // One trajectory from the FP32 angles in `state` (result back in `state`),
 // `pingpong` a second state-sized buffer; record to obs if not NULL.
+// steps_per_pass > 1 (and L % 32 == 0): leap-frog steps in passes of up to
+// min(steps_per_pass, 8) steps (temporal blocking); else one step per launch.
 hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w, int L, double beta, double eps,
-                                 int n_md, uint32_t traj, uint32_t k0, uint32_t k1, xy_hmc_obs* obs, hipStream_t s);
+                                 int n_md, int steps_per_pass, uint32_t traj, uint32_t k0, uint32_t k1,
+                                 xy_hmc_obs* obs, hipStream_t s);
+bool hmc_multi_supported(int L);
 bool fused_supported(int L, int tile_x, int tile_y, int m);
 
 // Fill n u64 words with zero (kernel, not a memset node: safe inside graphs).

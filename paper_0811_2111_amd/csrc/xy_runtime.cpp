@@ -165,6 +165,7 @@ struct xy_lattice {
     uint64_t sweep;
     xy_plan plan;
     xyk::Work w;
+    int32_t hmc_steps;     // leap-frog steps per pass of xy_hmc (1 .. 8)
 };
 
 static bool live(const xy_lattice* h) { return h && h->magic == kMagic; }
@@ -210,6 +211,7 @@ static int make_handle(xy_lattice** out, uint64_t seed, int32_t L, double beta, 
     h->work_len = work_len;
     h->stream = (hipStream_t)hip_stream;
     h->sweep = 0;
+    h->hmc_steps = 4;
     h->w = xyk::carve(work_dev, L, precision);
     xy_plan p;
     if (!cache_lookup(env_cache_path(), L, precision, &p)) p = default_plan(L);
@@ -360,11 +362,26 @@ int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_wo
     const uint32_t k0 = (uint32_t)(h->seed & 0xffffffffu), k1 = (uint32_t)(h->seed >> 32);
     for (int64_t j = 0; j < n_traj; ++j) {
         hipError_t e = xyk::launch_hmc_trajectory((float*)h->state, (float*)h->w.pingpong, w, h->L, h->beta, eps,
-                                                  n_md, (uint32_t)h->sweep, k0, k1, obs_dev ? obs_dev + j : nullptr,
-                                                  h->stream);
+                                                  n_md, h->hmc_steps, (uint32_t)h->sweep, k0, k1,
+                                                  obs_dev ? obs_dev + j : nullptr, h->stream);
         if (e != hipSuccess) return hip_fail(e, "hmc trajectory launch");
         h->sweep += 1;
     }
+    return XY_OK;
+}
+
+int xy_hmc_set_steps_per_pass(xy_lattice* h, int32_t steps)
+{
+    if (!live(h)) return XY_ESTATE;
+    if (steps < 1 || steps > 8) return XY_EINVAL;
+    h->hmc_steps = steps;
+    return XY_OK;
+}
+
+int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps)
+{
+    if (!live(h) || !steps) return XY_ESTATE;
+    *steps = xyk::hmc_multi_supported(h->L) ? h->hmc_steps : 1;
     return XY_OK;
 }
 

@@ -96,6 +96,8 @@ def _load():
         "xy_batch_get_tile": [vp, P(i32), P(i32)],
         "xy_batch_autotune": [vp, i32, P(i32), P(i32)],
         "xy_batch_set_schedule": [vp, i32],
+        "xy_hmc_set_steps_per_pass": [vp, i32],
+        "xy_hmc_get_steps_per_pass": [vp, P(i32)],
         "xy_batch_get_schedule": [vp, P(i32)],
         "xy_batch_status": [vp],
         "xy_batch_free": [vp],
@@ -242,6 +244,16 @@ class Lattice:
         rc = _lib.xy_sweep(self.h, int(n), int(measure_every), _ptr(out) if nrec else None)
         check(rc, "xy_sweep")
         return out
+
+    @property
+    def hmc_steps_per_pass(self) -> int:
+        """Leap-frog steps per pass that xy_hmc runs (1 if L % 32 != 0)."""
+        v = ctypes.c_int32()
+        check(_lib.xy_hmc_get_steps_per_pass(self.h, ctypes.byref(v)), "xy_hmc_get_steps_per_pass")
+        return v.value
+
+    def set_hmc_steps_per_pass(self, steps: int):
+        check(_lib.xy_hmc_set_steps_per_pass(self.h, int(steps)), "xy_hmc_set_steps_per_pass")
 
     def hmc(self, n_traj: int, n_md: int, eps: float, out=None):
         """n_traj HMC trajectories of n_md leap-frog steps of size eps; returns a

@@ -146,7 +146,7 @@ def test_init_without_gpu_reports_hip_error():
 @pytest.mark.parametrize("L", [4, 32, 130, 4096])
 def test_hmc_work_bytes(L):
     b = xy.xy_hmc_work_bytes(L)
-    assert b == 256 + 8 * L * L + 2 * (65536 + 256) * 64   # flag, momenta + saved angles, records + chunk sums
+    assert b == 256 + 12 * L * L + 2 * (65536 + 256) * 64   # flag, 2 momenta + saved angles, records + chunk sums
 
 
 def test_hmc_validation_without_gpu():
