@@ -230,9 +230,9 @@ constexpr int kStepRows = 4;               // rows per thread of k_hmc_step2
 // K leap-frog steps per pass (temporal blocking), for L % 32 == 0.  A workgroup
 // owns a 32 x 32 tile of sites (natural coordinates) and loads the angles and
 // momenta of the tile grown by K sites on every side (both colours) into
-// registers (ceil((32 + 2K)^2 / 256) sites per thread); step q updates the sites at distance
-// > q + 1 from the edge of the grown tile, whose neighbours are then all up to
-// date, so after K steps the tile itself is exact and is written to dst / pdst
+// registers (ceil((32 + 2K)^2 / 256) sites per thread); step q updates the sites
+// more than q sites from the edge of the grown tile, whose neighbours are then all
+// up to date, so after K steps the tile itself is exact and is written to dst / pdst
 // (the momenta ping-pong too: other tiles read this tile's old momenta as
 // their halo).  (cos, sin) of the angles live in two LDS buffers (read one,
 // write the other, one barrier per step).  Every site is updated with exactly
