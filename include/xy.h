@@ -105,8 +105,13 @@ typedef struct xy_obs {
  *                   beside it, recomputed.  Needs tile_x | L, tile_y | L, (tile_x,
  *                   tile_y) one of (128, 32|64|128), (256, 32|64|128|256),
  *                   sweeps_per_pass = 1.
+ *   XY_PLAN_RESIDENT: every sweep of a call in one launch of one workgroup that
+ *                   holds the whole lattice in LDS (angles of both colours and the
+ *                   (cos, sin) of one colour, 8 L^2 bytes): no halo and no HBM
+ *                   traffic between sweeps.  Needs L <= 128, L % 4 == 0; tile_x,
+ *                   tile_y ignored, sweeps_per_pass = 1.
  *   XY_PLAN_AUTO  : the tuned plan for (L, precision) if one is cached, else a default. */
-enum { XY_PLAN_AUTO = 0, XY_PLAN_STREAM = 1, XY_PLAN_FUSED = 2, XY_PLAN_STRIP = 3 };
+enum { XY_PLAN_AUTO = 0, XY_PLAN_STREAM = 1, XY_PLAN_FUSED = 2, XY_PLAN_STRIP = 3, XY_PLAN_RESIDENT = 4 };
 typedef struct xy_plan {
     int32_t kind;
     int32_t tile_x;

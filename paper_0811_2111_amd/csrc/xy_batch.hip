@@ -22,7 +22,10 @@
 // XCD's L2 cache, whereas a kernel boundary does that once per pass; when many
 // workgroups share a lattice the boundary is the cheaper barrier.  Records of a
 // measured pass are one partial per tile, summed per lattice in a fixed order by
-// a second small kernel.
+// a second small kernel.  Under these schedules lattices of L <= 32 are not cut
+// into tiles: one workgroup per such lattice holds it in LDS for every sweep of
+// the call (xy_resident.hpp), on a second stream that runs beside the per-sweep
+// launches and joins them before the copy back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,6 +35,7 @@
 
 #include "xy.h"
 #include "xy_launch.hpp"
+#include "xy_resident.hpp"
 #include "xy_runtime.hpp"
 #include "xy_tile.hpp"
 #include "xy_tile1.hpp"
@@ -49,6 +53,7 @@ struct LatDesc {
     int arrivals;         // workgroups owning tiles of this lattice
     int reducer;          // workgroup that reduces this lattice's measurements
     int wide;             // tiles of kWideX x kWideY instead of the batch's shape (per-sweep schedule)
+    int resident;         // held in one workgroup's LDS for a whole call (per-sweep schedules, L <= 32)
     uint32_t key0, key1;
     float delta, nbl2e;
 };
@@ -56,6 +61,8 @@ struct LatDesc {
 // Tile shape of the lattices that take wide tiles under XY_BATCH_PASSES_WIDE:
 // the fastest single-lattice shape.
 constexpr int kWideX = 256, kWideY = 16;
+// Lattices up to this size are LDS-resident under the per-sweep schedules.
+constexpr int kBatchResidentMaxL = 32;
 
 struct Ctrl {
     uint32_t sweep0;      // absolute sweep index of the next pass (advanced by k_batch_advance)
@@ -259,14 +266,33 @@ k_batch_pass(const T* __restrict__ src, T* __restrict__ dst, const LatDesc* __re
 }
 
 // Records of measured pass p (one workgroup per lattice, fixed order): record r of
-// lattice i at obs[i * nrec + r], sweep count sweep0 + p + 1.
+// lattice i at obs[i * nrec + r], sweep count sweep0 + p + 1.  LDS-resident
+// lattices write their own records.
 __global__ void __launch_bounds__(256)
 k_batch_reduce(const LatDesc* __restrict__ lat, const Ctrl* __restrict__ ctrl, int p, const double* __restrict__ part,
                xy_obs* __restrict__ obs, int nrec, int r)
 {
     __shared__ double red[4 * 7];
     const int i = (int)blockIdx.x;
+    if (lat[i].resident) return;
     reduce_lattice<256>(lat[i], part, obs + (size_t)i * nrec + r, (uint64_t)ctrl->sweep0 + (uint64_t)p + 1u, red);
+}
+
+// The LDS-resident lattices of a per-sweep call: workgroup b runs every sweep of
+// lattice ridx[b] from `state`, writes the result to `out` (the buffer that holds
+// the other lattices after the last pass) and its records to obs[i * nrec ..].
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_batch_resident(const T* __restrict__ state, T* __restrict__ out, const LatDesc* __restrict__ lat,
+                 const int* __restrict__ ridx, const Ctrl* __restrict__ ctrl, int npass, int me,
+                 xy_obs* __restrict__ obs, int nrec)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int i = ridx[blockIdx.x];
+    const LatDesc d = lat[i];
+    const Params prm{d.delta, d.nbl2e};
+    resident_program<T, 256>(state + d.off, out + d.off, d.L, ctrl->sweep0, npass, me, d.key0, d.key1, prm,
+                             (me > 0 && obs) ? obs + (size_t)i * nrec : nullptr, smem);
 }
 
 // dst <- src, n16 16-byte words
@@ -359,7 +385,7 @@ static std::vector<Shape> candidates(int n, const int32_t* L)
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, part_off, pt_off, total;
+    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, res_off, part_off, pt_off, total;
     long long max_tiles;
 };
 
@@ -389,7 +415,8 @@ static Layout layout(int n, const int32_t* L, int precision)
     lo.ctrl_off = align256(lo.state_bytes);
     lo.bar_off = lo.ctrl_off + 256;
     lo.desc_off = align256(lo.bar_off + (size_t)n * sizeof(unsigned));
-    lo.part_off = align256(lo.desc_off + (size_t)n * sizeof(LatDesc));
+    lo.res_off = align256(lo.desc_off + (size_t)n * sizeof(LatDesc));
+    lo.part_off = align256(lo.res_off + (size_t)n * sizeof(int));
     lo.pt_off = align256(lo.part_off + (size_t)2 * lo.max_tiles * 8 * sizeof(double));
     lo.total = lo.pt_off + pt_bytes(n);
     return lo;
@@ -467,7 +494,10 @@ struct xy_batch {
     uint64_t sweep;
     Layout lo;
     Shape shape;
-    int sched;             // XY_BATCH_PERSISTENT or XY_BATCH_PASSES
+    int sched;             // XY_BATCH_PERSISTENT, XY_BATCH_PASSES or XY_BATCH_PASSES_WIDE
+    hipStream_t cap2;      // second capture stream: the LDS-resident lattices
+    hipEvent_t ev_fork, ev_join;
+    int nres, res_maxL;    // LDS-resident lattices and their largest L
     int grid;
     int total_tiles;
     std::vector<LatDesc> desc;
@@ -481,6 +511,20 @@ struct xy_batch {
 };
 
 static bool blive(const xy_batch* b) { return b && b->magic == kBatchMagic; }
+
+static void drop_graph(xy_batch* b);
+
+// Graph, streams and events of a batch, then the handle itself.
+static void release(xy_batch* b)
+{
+    drop_graph(b);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->cap2) (void)hipStreamDestroy(b->cap2);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    b->magic = 0;
+    delete b;
+}
 
 static void drop_graph(xy_batch* b)
 {
@@ -520,11 +564,12 @@ static int plan_batch(xy_batch* b, Shape s)
         LatDesc& d = b->desc[i];
         d.off = off;
         d.L = b->L[i];
+        d.resident = b->sched != XY_BATCH_PERSISTENT && d.L <= kBatchResidentMaxL && xyk::resident_supported(d.L);
         d.wide = b->sched == XY_BATCH_PASSES_WIDE && d.L % kWideX == 0 && d.L % kWideY == 0;
         const int tx = d.wide ? kWideX : s.tx, ty = d.wide ? kWideY : s.ty;
         d.tiles_x = d.L / tx;
         d.first_tile = total;
-        d.ntiles = (d.L / tx) * (d.L / ty);
+        d.ntiles = d.resident ? 0 : (d.L / tx) * (d.L / ty);
         xyk::SweepArgs a = xyr::sweep_args(b->seed[i], d.L, b->precision, b->beta[i], b->delta[i]);
         d.key0 = a.key0;
         d.key1 = a.key1;
@@ -555,9 +600,22 @@ static int plan_batch(xy_batch* b, Shape s)
     b->shape = s;
     b->grid = G;
     b->total_tiles = total;
+    std::vector<int> ridx;
+    b->res_maxL = 0;
+    for (int i = 0; i < b->n; ++i)
+        if (b->desc[i].resident) {
+            ridx.push_back(i);
+            b->res_maxL = std::max(b->res_maxL, b->desc[i].L);
+        }
+    b->nres = (int)ridx.size();
     e = hipMemcpyAsync(b->work + b->lo.desc_off, b->desc.data(), sizeof(LatDesc) * b->n, hipMemcpyHostToDevice,
                        b->stream);
     if (e != hipSuccess) return xyr::hip_fail(e, "hipMemcpyAsync(desc)");
+    if (b->nres > 0) {
+        e = hipMemcpyAsync(b->work + b->lo.res_off, ridx.data(), sizeof(int) * ridx.size(), hipMemcpyHostToDevice,
+                           b->stream);
+        if (e != hipSuccess) return xyr::hip_fail(e, "hipMemcpyAsync(resident list)");
+    }
     if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return xyr::hip_fail(e, "hipStreamSynchronize");
     drop_graph(b);
     return XY_OK;
@@ -596,7 +654,25 @@ static hipError_t enqueue_passes(xy_batch* b, hipStream_t s, int npass, int32_t 
     void* pp = b->work + b->lo.pp_off;
     int nlat = b->n, tt = b->total_tiles;
     hipError_t e = hipSuccess;
-    for (int p = 0; p < npass; ++p) {
+    if (b->nres > 0) {
+        // the LDS-resident lattices on the second stream, beside the passes below
+        if ((e = hipEventRecord(b->ev_fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(b->cap2, b->ev_fork, 0)) != hipSuccess) return e;
+        void* out = (npass & 1) ? pp : (void*)b->state;
+        const int* ridx = (const int*)(b->work + b->lo.res_off);
+        const size_t lds = resident_lds_bytes(b->res_maxL, kNT);
+        if (b->precision == XY_FP16)
+            hipLaunchKernelGGL(k_batch_resident<__half>, dim3(b->nres), dim3(kNT), lds, b->cap2,
+                               (const __half*)b->state, (__half*)out, desc, ridx, (const Ctrl*)ctrl, npass, me, obs,
+                               nrec);
+        else
+            hipLaunchKernelGGL(k_batch_resident<float>, dim3(b->nres), dim3(kNT), lds, b->cap2,
+                               (const float*)b->state, (float*)out, desc, ridx, (const Ctrl*)ctrl, npass, me, obs,
+                               nrec);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipEventRecord(b->ev_join, b->cap2)) != hipSuccess) return e;
+    }
+    for (int p = 0; p < npass && tt > 0; ++p) {
         const bool meas = me > 0 && ((p + 1) % me) == 0;
         size_t lds = 0;
         void* k = pass_kernel(b->precision, b->shape, b->sched == XY_BATCH_PASSES_WIDE, meas, &lds);
@@ -611,6 +687,7 @@ static hipError_t enqueue_passes(xy_batch* b, hipStream_t s, int npass, int32_t 
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
     }
+    if (b->nres > 0 && (e = hipStreamWaitEvent(s, b->ev_join, 0)) != hipSuccess) return e;
     if (npass & 1) {
         const size_t n16 = b->lo.state_bytes / 16;
         const int grid = (int)std::min<size_t>((n16 + kNT - 1) / kNT, 4096);
@@ -665,6 +742,11 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->work_len = work_len;
     b->stream = (hipStream_t)hip_stream;
     b->cap = nullptr;
+    b->cap2 = nullptr;
+    b->ev_fork = nullptr;
+    b->ev_join = nullptr;
+    b->nres = 0;
+    b->res_maxL = 0;
     b->sweep = 0;
     b->pt_round = 0;
     b->lo = layout(n, L, precision);
@@ -677,16 +759,25 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->g_sched = -1;
     b->sched = XY_BATCH_PASSES_WIDE;
     auto fail = [&](int code) {
-        drop_graph(b);
-        if (b->cap) (void)hipStreamDestroy(b->cap);
-        b->magic = 0;
-        delete b;
+        release(b);
         return code;
     };
     hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
         b->cap = nullptr;
         return fail(xyr::hip_fail(e, "hipStreamCreate"));
+    }
+    if ((e = hipStreamCreateWithFlags(&b->cap2, hipStreamNonBlocking)) != hipSuccess) {
+        b->cap2 = nullptr;
+        return fail(xyr::hip_fail(e, "hipStreamCreate"));
+    }
+    if ((e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming)) != hipSuccess) {
+        b->ev_fork = nullptr;
+        return fail(xyr::hip_fail(e, "hipEventCreate"));
+    }
+    if ((e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming)) != hipSuccess) {
+        b->ev_join = nullptr;
+        return fail(xyr::hip_fail(e, "hipEventCreate"));
     }
     rc = plan_batch(b, candidates(n, L).front());
     if (rc != XY_OK) return fail(rc);
@@ -938,10 +1029,7 @@ int xy_batch_status(xy_batch* b)
 int xy_batch_free(xy_batch* b)
 {
     if (!blive(b)) return XY_ESTATE;
-    drop_graph(b);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
-    b->magic = 0;
-    delete b;
+    release(b);
     return XY_OK;
 }
 

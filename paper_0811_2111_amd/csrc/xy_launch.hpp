@@ -66,6 +66,11 @@ int fused_records(int L, int tile_x, int tile_y, int m);
 // tile_x columns x tile_y rows; measured: one record per wave (4 per segment) at
 // partials[(segment * 4 + wave) * 8].
 bool strip_supported(int L, int tile_x, int tile_y);
+// Whole lattice resident in one workgroup's LDS (L <= 128, L % 4 == 0): n sweeps
+// in place from a.src (= a.dst), records of every me-th sweep of the call to
+// obs[0 ..] (none if me == 0 or obs == NULL).
+bool resident_supported(int L);
+hipError_t launch_resident(const SweepArgs& a, int n, int me, xy_obs* obs, hipStream_t s);
 hipError_t launch_strip(const SweepArgs& a, int tile_x, int tile_y, bool meas, double* partials, hipStream_t s);
 int strip_records(int L, int tile_x, int tile_y);
 

@@ -67,6 +67,7 @@ bool plan_ok(int32_t L, const xy_plan& p)
     if (p.kind == XY_PLAN_STREAM) return true;
     if (p.kind == XY_PLAN_FUSED) return xyk::fused_supported(L, p.tile_x, p.tile_y, p.sweeps_per_pass);
     if (p.kind == XY_PLAN_STRIP) return p.sweeps_per_pass == 1 && xyk::strip_supported(L, p.tile_x, p.tile_y);
+    if (p.kind == XY_PLAN_RESIDENT) return xyk::resident_supported(L);
     return false;
 }
 
@@ -295,6 +296,22 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
         return XY_OK;
     }
 
+    if (h->plan.kind == XY_PLAN_RESIDENT) {
+        // every sweep of the call in one launch; calls longer than 2^30 sweeps are
+        // split at a multiple of measure_every
+        const int64_t cap = meas ? ((int64_t)1 << 30) / measure_every * measure_every : ((int64_t)1 << 30);
+        for (int64_t done = 0; done < n_sweeps;) {
+            const int64_t m = std::min<int64_t>(cap, n_sweeps - done);
+            xyk::SweepArgs a = args_of(h);
+            hipError_t e = xyk::launch_resident(a, (int)m, meas ? measure_every : 0,
+                                                meas ? obs_dev + done / measure_every : nullptr, h->stream);
+            if (e != hipSuccess) return hip_fail(e, "resident sweep launch");
+            h->sweep += (uint64_t)m;
+            done += m;
+        }
+        return XY_OK;
+    }
+
     // Fused schedule: an even number of ping-pong passes (state -> pingpong ->
     // state ...), so the angles end in the caller's buffer; the remaining sweeps
     // run in place with the streaming schedule (same trajectory).
@@ -462,6 +479,7 @@ int xy_autotune(xy_lattice* h, int32_t sweeps_per_trial, const char* cache_path,
         xy_plan p{XY_PLAN_FUSED, s[0], s[1], s[2]};
         if (plan_ok(h->L, p)) cands.push_back(p);
     }
+    if (plan_ok(h->L, xy_plan{XY_PLAN_RESIDENT, 0, 0, 1})) cands.push_back({XY_PLAN_RESIDENT, 0, 0, 1});
     static const int strips[][2] = {{128, 32}, {128, 64}, {128, 128}, {256, 32}, {256, 64}, {256, 128}, {256, 256}};
     for (auto& s : strips) {
         xy_plan p{XY_PLAN_STRIP, s[0], s[1], 1};

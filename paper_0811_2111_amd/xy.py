@@ -25,7 +25,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "xy.h")
 XY_OK, XY_EINVAL, XY_ESIZE, XY_ERANGE, XY_EHIP, XY_ESTATE, XY_ENOMEM, XY_EBARRIER = 0, -1, -2, -3, -4, -5, -6, -7
 XY_FP32, XY_FP16 = 0, 1
 XY_HOT, XY_COLD = 0, 1
-XY_PLAN_AUTO, XY_PLAN_STREAM, XY_PLAN_FUSED, XY_PLAN_STRIP = 0, 1, 2, 3
+XY_PLAN_AUTO, XY_PLAN_STREAM, XY_PLAN_FUSED, XY_PLAN_STRIP, XY_PLAN_RESIDENT = 0, 1, 2, 3, 4
 XY_BATCH_PERSISTENT, XY_BATCH_PASSES, XY_BATCH_PASSES_WIDE = 0, 1, 2
 _PREC = {"fp32": XY_FP32, "fp16": XY_FP16, XY_FP32: XY_FP32, XY_FP16: XY_FP16}
 _START = {"hot": XY_HOT, "cold": XY_COLD, XY_HOT: XY_HOT, XY_COLD: XY_COLD}

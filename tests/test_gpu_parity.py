@@ -41,6 +41,13 @@ def strip_plans(L):
     return [(3, tx, sh, 1) for (tx, sh) in STRIP_SHAPES if L % tx == 0 and L % sh == 0]
 
 
+RESIDENT = (4, 0, 0, 1)
+
+
+def resident_plans(L):
+    return [RESIDENT] if 4 <= L <= 128 and L % 4 == 0 else []
+
+
 def dilate(mask, r):
     """Periodic Manhattan dilation of a boolean (L, L) mask by radius r."""
     out = mask.copy()
@@ -130,7 +137,7 @@ def test_c1_trajectory_fp32(orc):
 
 @pytest.mark.parametrize("L,plan", [(64, (2, 64, 16, 1)), (64, (2, 64, 32, 2)), (128, (2, 128, 32, 1)),
                                     (256, (2, 256, 32, 1)), (128, (3, 128, 32, 1)), (256, (3, 256, 64, 1)),
-                                    (256, (3, 256, 256, 1))])
+                                    (256, (3, 256, 256, 1)), (32, RESIDENT), (128, RESIDENT)])
 def test_fused_trajectory_fp32(orc, L, plan):
     lat = xy.Lattice(L, seed=2, beta=1.12, delta=1.0, plan=plan)
     per = 2 * plan[3]
@@ -138,7 +145,7 @@ def test_fused_trajectory_fp32(orc, L, plan):
     print("first divergence:", div)
 
 
-@pytest.mark.parametrize("L,plan", [(64, STREAM), (64, (2, 64, 32, 1)), (128, (3, 128, 64, 1))])
+@pytest.mark.parametrize("L,plan", [(64, STREAM), (64, (2, 64, 32, 1)), (128, (3, 128, 64, 1)), (64, RESIDENT)])
 def test_fp16_trajectory(orc, L, plan):
     lat = xy.Lattice(L, seed=4, beta=1.0, delta=1.0, precision="fp16", plan=plan)
     follow(orc, lat, 4, 1.0, 1.0, n_calls=15, per_call=2, prec="fp16")
@@ -173,12 +180,12 @@ def test_debug_decisions_and_dE(orc):
 @pytest.mark.parametrize("L", [64, 128, 256, 512])
 def test_schedule_invariance(L, prec):
     """Every plan (streaming, every fused tile shape, one or two sweeps per pass, every
-    strip shape) gives
+    strip shape, the LDS-resident lattice) gives
     the same angles bit for bit and the same accept counts; observables agree to
     summation-order rounding (FP32 per-thread partials of a few sites, then FP64):
     within 1e-7 N, ten times inside the oracle tolerance."""
     res = []
-    for plan in [STREAM] + fused_plans(L) + strip_plans(L):
+    for plan in [STREAM] + fused_plans(L) + strip_plans(L) + resident_plans(L):
         lat = xy.Lattice(L, seed=7, beta=0.9, delta=1.0, precision=prec, plan=plan)
         obs = lat.sweep(7, 1)
         res.append((plan, lat.state.clone(), xy.records(obs)))
@@ -291,12 +298,14 @@ def test_full_size_sampled_sites(orc, L, beta, delta, plan):
 SCHEDULES = [0, 1, 2]   # XY_BATCH_PERSISTENT, XY_BATCH_PASSES, XY_BATCH_PASSES_WIDE
 
 
+@pytest.mark.parametrize("Ls", [[64, 128, 64, 256, 192], [16, 64, 32, 256, 8]])
 @pytest.mark.parametrize("sched", SCHEDULES)
-def test_batch_equals_single_and_graph_replays(sched):
+def test_batch_equals_single_and_graph_replays(sched, Ls):
     """Each lattice of a batch follows, bit for bit, the trajectory it follows alone;
     the captured graph is replayed correctly call after call (eager work and host
-    synchronisation in between), with odd and even sweep counts; both schedules."""
-    Ls = [64, 128, 64, 256, 192]
+    synchronisation in between), with odd and even sweep counts; every schedule
+    (the second batch has LDS-resident lattices under the per-sweep schedules,
+    running beside the per-sweep launches)."""
     seeds = [11, 12, 13, 14, 15]
     betas = [0.8, 1.0, 1.2, 1.3, 0.95]
     deltas = [1.0, 1.0, 1.2, 0.8, 1.0]
@@ -497,3 +506,19 @@ def test_fp16_storage_statistics_close_to_fp32():
     err = math.hypot(res["fp16"][1], res["fp32"][1])
     print("FP16 - FP32 <e> = %.5f +- %.5f" % (d, err))
     assert abs(d) < 5 * err + 0.01
+
+
+def test_resident_long_call_and_records():
+    """The LDS-resident plan runs a whole call in one launch: 1000 sweeps of the
+    L = 32 lattice with a record every 7 sweeps equal, bit for bit in the angles and
+    accept counts, to the streaming plan, and the record sweep numbers count on
+    across calls."""
+    a = xy.Lattice(32, seed=1, beta=1.0, delta=1.0, plan=RESIDENT)
+    b = xy.Lattice(32, seed=1, beta=1.0, delta=1.0, plan=STREAM)
+    ra, rb = xy.records(a.sweep(1000, 7)), xy.records(b.sweep(1000, 7))
+    assert torch.equal(a.state, b.state)
+    assert np.array_equal(ra["n_accept"], rb["n_accept"]) and np.array_equal(ra["sweep"], rb["sweep"])
+    for f in ["cx", "cy", "ix", "iy", "mx", "my"]:
+        np.testing.assert_allclose(ra[f], rb[f], rtol=0, atol=1e-7 * 32 * 32)
+    r2 = xy.records(a.sweep(14, 7))
+    assert list(r2["sweep"]) == [1007, 1014]
