@@ -104,7 +104,7 @@ typedef struct xy_obs {
  *                   red row above and below the segment plus one red entry per row
  *                   beside it, recomputed.  Needs tile_x | L, tile_y | L, (tile_x,
  *                   tile_y) one of (128, 32|64|128), (256, 32|64|128|256),
- *                   sweeps_per_pass = 1.
+ *                   (512, 64|128|256), sweeps_per_pass = 1.
  *   XY_PLAN_RESIDENT: every sweep of a call in one launch of one workgroup that
  *                   holds the whole lattice in LDS (angles of both colours and the
  *                   (cos, sin) of one colour, 8 L^2 bytes): no halo and no HBM

@@ -480,7 +480,8 @@ int xy_autotune(xy_lattice* h, int32_t sweeps_per_trial, const char* cache_path,
         if (plan_ok(h->L, p)) cands.push_back(p);
     }
     if (plan_ok(h->L, xy_plan{XY_PLAN_RESIDENT, 0, 0, 1})) cands.push_back({XY_PLAN_RESIDENT, 0, 0, 1});
-    static const int strips[][2] = {{128, 32}, {128, 64}, {128, 128}, {256, 32}, {256, 64}, {256, 128}, {256, 256}};
+    static const int strips[][2] = {{128, 32},  {128, 64},  {128, 128}, {256, 32}, {256, 64},
+                                    {256, 128}, {256, 256}, {512, 64},  {512, 128}, {512, 256}};
     for (auto& s : strips) {
         xy_plan p{XY_PLAN_STRIP, s[0], s[1], 1};
         if (plan_ok(h->L, p)) cands.push_back(p);

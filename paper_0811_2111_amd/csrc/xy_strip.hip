@@ -65,7 +65,10 @@ static hipError_t run_strip_k(const SweepArgs& a, double* partials, hipStream_t 
     X(256, 32)             \
     X(256, 64)             \
     X(256, 128)            \
-    X(256, 256)
+    X(256, 256)            \
+    X(512, 64)             \
+    X(512, 128)            \
+    X(512, 256)
 
 bool strip_supported(int L, int tile_x, int tile_y)
 {

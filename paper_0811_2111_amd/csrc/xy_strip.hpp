@@ -36,7 +36,7 @@ namespace xyd {
 
 template <int TX, int SH, int NT>
 struct Strip {
-    static_assert(TX == 128 || TX == 256, "strip width: 128 or 256");
+    static_assert(TX == 128 || TX == 256 || TX == 512, "strip width: 128, 256 or 512");
     static_assert(NT == 256, "four waves");
     static constexpr int TQ = TX / 4;                  // Philox pairs per half-row
     static constexpr int LGQ = __builtin_ctz(TQ);
@@ -252,8 +252,13 @@ __device__ __forceinline__ void strip_program(const T* __restrict__ src, T* __re
     g.P = g.Hh >> 1;
     g.kb = x0 >> 1;
     g.y0 = y0;
-    g.s = lane & (S::TQ - 1);
-    g.rt = 4 * (lane >> S::LGQ) + w;   // wave w: rows w, w + 4 (same parity)
+    if constexpr (S::TQ <= 64) {
+        g.s = lane & (S::TQ - 1);
+        g.rt = 4 * (lane >> S::LGQ) + w;   // wave w: rows w, w + 4 (same parity)
+    } else {                               // a half-row spans two waves: waves 2r, 2r+1 take row r
+        g.s = (w & 1) * 64 + lane;
+        g.rt = w >> 1;
+    }
 
     // ---- edge columns: black entries kb-1 (side 0) and kb+TX/2 (side 1) of rows
     // y0-2 .. y0+SH+1; then the ring red entries of rows y0-1 .. y0+SH

@@ -30,7 +30,8 @@ FUSED_SHAPES = [(64, 16, 1), (64, 32, 1), (128, 16, 1), (128, 32, 1), (128, 64, 
 OPREC = {"fp32": "f32", "fp16": "f16"}
 
 
-STRIP_SHAPES = [(128, 32), (128, 64), (128, 128), (256, 32), (256, 64), (256, 128), (256, 256)]
+STRIP_SHAPES = [(128, 32), (128, 64), (128, 128), (256, 32), (256, 64), (256, 128), (256, 256), (512, 64),
+                (512, 128), (512, 256)]
 
 
 def fused_plans(L):
@@ -137,7 +138,8 @@ def test_c1_trajectory_fp32(orc):
 
 @pytest.mark.parametrize("L,plan", [(64, (2, 64, 16, 1)), (64, (2, 64, 32, 2)), (128, (2, 128, 32, 1)),
                                     (256, (2, 256, 32, 1)), (128, (3, 128, 32, 1)), (256, (3, 256, 64, 1)),
-                                    (256, (3, 256, 256, 1)), (32, RESIDENT), (128, RESIDENT)])
+                                    (256, (3, 256, 256, 1)), (512, (3, 512, 64, 1)), (32, RESIDENT),
+                                    (128, RESIDENT)])
 def test_fused_trajectory_fp32(orc, L, plan):
     lat = xy.Lattice(L, seed=2, beta=1.12, delta=1.0, plan=plan)
     per = 2 * plan[3]
