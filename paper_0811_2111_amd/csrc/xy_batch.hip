@@ -1,9 +1,9 @@
-// xy_batch.hip -- many lattices of uneven size and temperature in one persistent launch.
+// xy_batch.hip -- many lattices of uneven size and temperature advanced together.
 //
 // The replicas of the paper's GLSL variant (four lattices, possibly at different
 // temperatures, in one RGBA texture, section 3.2) and its remark that the device
-// must be "sufficiently filled" motivate running a whole temperature scan as one
-// launch: small lattices alone cannot fill 256 CUs.
+// performs well only with enough work in flight motivate running a whole
+// temperature scan as one work list: small lattices alone cannot fill 256 CUs.
 //
 // Work list: every lattice is cut into TX x TY tiles; the tiles of all lattices,
 // lattice by lattice, form one list that is split into contiguous ranges, one per
