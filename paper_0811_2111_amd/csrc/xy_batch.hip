@@ -242,15 +242,15 @@ constexpr size_t pass_lds()
 // MEAS = -1: measured, one record per tile at part[t * 8]; 0: not.
 template <typename T, int TX, int TY, int MEAS, bool WIDE>
 __global__ void __launch_bounds__(256)
-k_batch_pass(const T* __restrict__ src, T* __restrict__ dst, const LatDesc* __restrict__ lat, int nlat,
-             int total_tiles, const Ctrl* __restrict__ ctrl, int p, double* __restrict__ part)
+k_batch_pass(const T* __restrict__ src, T* __restrict__ dst, const LatDesc* __restrict__ lat,
+             const int* __restrict__ tile_lat, int total_tiles, const Ctrl* __restrict__ ctrl, int p,
+             double* __restrict__ part)
 {
     extern __shared__ __align__(16) char smem[];
     double* red = (double*)(smem + pass_lds<TX, TY, WIDE>() - Tile1<TX, TY, 256>::red_bytes);
     const int b = (int)blockIdx.x;
     const int t = (total_tiles & 7) ? b : (b & 7) * (total_tiles >> 3) + (b >> 3);
-    const int i = lattice_of(lat, nlat, t);
-    const LatDesc d = lat[i];
+    const LatDesc d = lat[tile_lat[t]];      // a table, not a search: two loads before the tile starts
     const int lt = t - d.first_tile;
     const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
     const Params prm{d.delta, d.nbl2e};
@@ -385,7 +385,7 @@ static std::vector<Shape> candidates(int n, const int32_t* L)
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, res_off, part_off, pt_off, total;
+    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, res_off, tile_off, part_off, pt_off, total;
     long long max_tiles;
 };
 
@@ -416,7 +416,8 @@ static Layout layout(int n, const int32_t* L, int precision)
     lo.bar_off = lo.ctrl_off + 256;
     lo.desc_off = align256(lo.bar_off + (size_t)n * sizeof(unsigned));
     lo.res_off = align256(lo.desc_off + (size_t)n * sizeof(LatDesc));
-    lo.part_off = align256(lo.res_off + (size_t)n * sizeof(int));
+    lo.tile_off = align256(lo.res_off + (size_t)n * sizeof(int));
+    lo.part_off = align256(lo.tile_off + (size_t)lo.max_tiles * sizeof(int));
     lo.pt_off = align256(lo.part_off + (size_t)2 * lo.max_tiles * 8 * sizeof(double));
     lo.total = lo.pt_off + pt_bytes(n);
     return lo;
@@ -616,6 +617,15 @@ static int plan_batch(xy_batch* b, Shape s)
                            b->stream);
         if (e != hipSuccess) return xyr::hip_fail(e, "hipMemcpyAsync(resident list)");
     }
+    // tile -> lattice table of the work list (the per-sweep kernels read it)
+    std::vector<int> tl((size_t)total);
+    for (int i = 0; i < b->n; ++i)
+        for (int t = 0; t < b->desc[i].ntiles; ++t) tl[(size_t)b->desc[i].first_tile + t] = i;
+    if (total > 0) {
+        e = hipMemcpyAsync(b->work + b->lo.tile_off, tl.data(), sizeof(int) * tl.size(), hipMemcpyHostToDevice,
+                           b->stream);
+        if (e != hipSuccess) return xyr::hip_fail(e, "hipMemcpyAsync(tile table)");
+    }
     if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return xyr::hip_fail(e, "hipStreamSynchronize");
     drop_graph(b);
     return XY_OK;
@@ -679,7 +689,8 @@ static hipError_t enqueue_passes(xy_batch* b, hipStream_t s, int npass, int32_t 
         void* src = (p & 1) ? pp : (void*)b->state;
         void* dst = (p & 1) ? (void*)b->state : pp;
         int pv = p;
-        void* args[] = {&src, &dst, &desc, &nlat, &tt, &ctrl, &pv, &part};
+        const int* tile_lat = (const int*)(b->work + b->lo.tile_off);
+        void* args[] = {&src, &dst, &desc, &tile_lat, &tt, &ctrl, &pv, &part};
         if ((e = hipLaunchKernel(k, dim3(tt), dim3(kNT), args, lds, s)) != hipSuccess) return e;
         if (meas) {
             hipLaunchKernelGGL(k_batch_reduce, dim3(nlat), dim3(kNT), 0, s, desc, (const Ctrl*)ctrl, p,
