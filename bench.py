@@ -164,10 +164,20 @@ def main():
 
     # dominant kernel: average duration of one fused or strip launch (no measurement),
     # events on the stream; the streaming plan launches two half-sweeps per sweep
-    nrep = 300                               # 600 sweeps: long enough that launch jitter averages out
+    # Events on the library's stream bracket each call of 20 sweeps (20 launches
+    # back to back for the tiled plans), so a pause of the host between calls is
+    # not counted; the per-launch average is the sum over 30 calls / launches.
+    nrep, per_call = 30, 20
     tiled = plan[0] in (xy.XY_PLAN_FUSED, xy.XY_PLAN_STRIP)
-    ms_k = timed(lambda: lat.sweep(nrep * plan[3] * 2), stream)
-    launches = nrep * 2 if tiled else nrep * 2 * plan[3] * 2
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nrep)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record(stream)
+        lat.sweep(plan[3] * per_call)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms_k = sum(e0.elapsed_time(e1) for e0, e1 in ev)
+    launches = nrep * per_call if tiled else nrep * per_call * plan[3] * 2
     per_launch_ms = ms_k / launches
     sweeps_per_launch = plan[3] if tiled else 0.5
     upd_per_launch = N * sweeps_per_launch
