@@ -242,7 +242,8 @@ __device__ __forceinline__ void strip_program(const T* __restrict__ src, T* __re
 {
     using S = Strip<TX, SH, NT>;
     float2* cs = (float2*)smem;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // wave index through the scalar unit: row indices and their wraps are scalar work
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, state_bytes);
     const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, state_bytes);
 

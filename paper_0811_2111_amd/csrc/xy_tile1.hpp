@@ -332,7 +332,10 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     g.x0 = x0;
     g.y0 = y0;
     {
-        const int lane = tid & 63, w = tid >> 6;
+        // The wave index is uniform; read through the scalar unit, so that for
+        // 256-wide tiles (one half-row per wave) every row index, its wrap and the
+        // row part of each address are scalar work.
+        const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
         g.s = lane & (S::TQ - 1);
         const int i = lane >> S::LGQ;
         g.rt = 2 * (i * (S::NW / 2) + (w >> 1)) + (w & 1);   // parity of the wave

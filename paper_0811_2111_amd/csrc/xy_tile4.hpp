@@ -276,7 +276,7 @@ __device__ __forceinline__ void tile4_program(const float4* __restrict__ src, fl
     g.x0 = x0;
     g.y0 = y0;
     {
-        const int lane = tid & 63, w = tid >> 6;
+        const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: scalar row work
         g.s = lane & (S::TQ - 1);
         const int i = lane >> S::LGQ;
         g.rt = 2 * (i * (S::NW / 2) + (w >> 1)) + (w & 1);
