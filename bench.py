@@ -167,10 +167,14 @@ def main():
     # Events on the library's stream bracket each call of 20 sweeps (20 launches
     # back to back for the tiled plans), so a pause of the host between calls is
     # not counted; the per-launch average is the sum over 30 calls / launches.
+    # 200 untimed sweeps are queued right before the first event: after the host
+    # work above the GPU has been idle, and its clock takes a few milliseconds to
+    # come back up.
     nrep, per_call = 30, 20
     tiled = plan[0] in (xy.XY_PLAN_FUSED, xy.XY_PLAN_STRIP)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nrep)]
     torch.cuda.synchronize()
+    lat.sweep(plan[3] * 200)
     for e0, e1 in ev:
         e0.record(stream)
         lat.sweep(plan[3] * per_call)

@@ -305,25 +305,12 @@ __device__ __forceinline__ void tile1_black(const T1Geom& g, const float2* __res
     }
 }
 
-// src/dst: the two state buffers (same layout); `state_bytes` bounds the buffer
-// descriptors.  MEAS selects the measurement at compile time:
-//   MEAS = 0 : never measure;
-//   MEAS = 1 : always measure, one partial record per wave at part[wave * 8 ..]
-//              (no barrier and no cross-wave step: the records are summed later in
-//              a fixed order);
-//   MEAS = -1: measure if `meas`, one partial record per tile at part[0 .. 8].
-// A record is (Cx, Cy, Ix, Iy, Mx, My, accepts, 0).
-template <typename T, int TX, int TY, int NT, int MEAS = -1>
-__device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __restrict__ dst, unsigned state_bytes,
-                                              int L, int x0, int y0, uint32_t sweep, uint32_t k0, uint32_t k1,
-                                              const Params& p, bool meas, double* part, char* smem, double* red)
+// Per-tile geometry: the tile at (x0, y0) of an L x L lattice.
+template <int TX, int TY, int NT>
+__device__ __forceinline__ T1Geom tile1_geom(int L, int x0, int y0)
 {
     using S = Tile1<TX, TY, NT>;
-    float2* cs = (float2*)smem;
     const int tid = threadIdx.x;
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, state_bytes);
-    const __amdgpu_buffer_rsrc_t rd = make_rsrc(dst, state_bytes);
-
     T1Geom g;
     g.L = L;
     g.Hh = L >> 1;
@@ -331,26 +318,40 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     g.kb = x0 >> 1;
     g.x0 = x0;
     g.y0 = y0;
-    {
-        // The wave index is uniform; read through the scalar unit, so that for
-        // 256-wide tiles (one half-row per wave) every row index, its wrap and the
-        // row part of each address are scalar work.
-        const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
-        g.s = lane & (S::TQ - 1);
-        const int i = lane >> S::LGQ;
-        g.rt = 2 * (i * (S::NW / 2) + (w >> 1)) + (w & 1);   // parity of the wave
-    }
+    // The wave index is uniform; read through the scalar unit, so that for
+    // 256-wide tiles (one half-row per wave) every row index, its wrap and the
+    // row part of each address are scalar work.
+    const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    g.s = lane & (S::TQ - 1);
+    const int i = lane >> S::LGQ;
+    g.rt = 2 * (i * (S::NW / 2) + (w >> 1)) + (w & 1);   // parity of the wave
     g.edge_tile = (y0 < 2) || (y0 + TY + 2 > L);
+    return g;
+}
 
-    // ---- loads: red pairs, black pairs and this thread's edge entry, all issued first
-    float2 thr[S::NQR], thb[S::NQB];
+// The angles one thread loads for a tile: its red and black pairs and, for the
+// threads e = NT-1-tid < NEDGE, one edge entry (red edge entries land on the last
+// wave).
+template <int TX, int TY, int NT>
+struct T1Regs {
+    float2 thr[Tile1<TX, TY, NT>::NQR], thb[Tile1<TX, TY, NT>::NQB];
+    float the;
+    int e_row, e_col, e_red, e_k;
+};
+
+// Issue every load of the tile (no wait).
+template <typename T, int TX, int TY, int NT>
+__device__ __forceinline__ void tile1_load(const T1Geom& g, __amdgpu_buffer_rsrc_t rs, T1Regs<TX, TY, NT>& a)
+{
+    using S = Tile1<TX, TY, NT>;
+    const int L = g.L, y0 = g.y0;
     const unsigned col = (unsigned)(g.kb + 2 * g.s);
 #pragma unroll
     for (int q = 0; q < S::NQR; ++q) {
         if (red_valid<S>(g, q)) {
             const int y0r = y0 - 1 + red_row<S>(g, q);
             const int y = g.edge_tile ? wrapi(y0r, L) : y0r;
-            thr[q] = bio<T>::ld2(rs, (unsigned)y * (unsigned)g.Hh + col);
+            a.thr[q] = bio<T>::ld2(rs, (unsigned)y * (unsigned)g.Hh + col);
         }
     }
 #pragma unroll
@@ -358,36 +359,44 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
         if (black_valid<S>(g, q)) {
             const int y0b = y0 - 2 + black_row<S>(g, q);
             const int y = g.edge_tile ? wrapi(y0b, L) : y0b;
-            thb[q] = bio<T>::ld2(rs, ((unsigned)L + (unsigned)y) * (unsigned)g.Hh + col);
+            a.thb[q] = bio<T>::ld2(rs, ((unsigned)L + (unsigned)y) * (unsigned)g.Hh + col);
         }
     }
-    const int e = NT - 1 - tid;            // red edge entries land on the last wave
-    float the = 0.0f;
-    int e_row = 0, e_col = 0, e_red = 0, e_k = 0;
+    const int e = NT - 1 - (int)threadIdx.x;
+    a.the = 0.0f;
+    a.e_row = 0; a.e_col = 0; a.e_red = 0; a.e_k = 0;
     if (e < S::NEDGE) {
         int yl, side;
         if (e < S::RR) {                   // red row y0-1+e: the side its ring update needs
-            e_red = 1;
-            e_row = e;
+            a.e_red = 1;
+            a.e_row = e;
             yl = y0 - 1 + e;
             side = ((yl & 1) == 0);        // o = 0 -> right column, o = 1 -> left column
         } else {
             const int e2 = e - S::RR;
-            e_row = e2 >> 1;
-            yl = y0 - 2 + e_row;
+            a.e_row = e2 >> 1;
+            yl = y0 - 2 + a.e_row;
             side = e2 & 1;
         }
-        e_k = side ? g.kb + TX / 2 : g.kb - 1;
-        e_col = side ? TX / 2 + 2 : 1;
-        the = bio<T>::ld1(rs, ((unsigned)(e_red ? 0 : L) + (unsigned)wrapi(yl, L)) * (unsigned)g.Hh +
-                                  (unsigned)wrapi(e_k, g.Hh));
+        a.e_k = side ? g.kb + TX / 2 : g.kb - 1;
+        a.e_col = side ? TX / 2 + 2 : 1;
+        a.the = bio<T>::ld1(rs, ((unsigned)(a.e_red ? 0 : L) + (unsigned)wrapi(yl, L)) * (unsigned)g.Hh +
+                                    (unsigned)wrapi(a.e_k, g.Hh));
     }
+}
+
+// (cos, sin) of every loaded entry into LDS (waits for the loads); the caller
+// places the barrier.
+template <int TX, int TY, int NT>
+__device__ __forceinline__ void tile1_fill(const T1Geom& g, float2* __restrict__ cs, const T1Regs<TX, TY, NT>& a)
+{
+    using S = Tile1<TX, TY, NT>;
 #pragma unroll
     for (int q = 0; q < S::NQR; ++q) {
         if (red_valid<S>(g, q)) {
             float sa, ca, sb, cb;
-            sincos_turn(thr[q].x, sa, ca);
-            sincos_turn(thr[q].y, sb, cb);
+            sincos_turn(a.thr[q].x, sa, ca);
+            sincos_turn(a.thr[q].y, sb, cb);
             *(float4*)&cs[red_row<S>(g, q) * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
         }
     }
@@ -395,33 +404,44 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     for (int q = 0; q < S::NQB; ++q) {
         if (black_valid<S>(g, q)) {
             float sa, ca, sb, cb;
-            sincos_turn(thb[q].x, sa, ca);
-            sincos_turn(thb[q].y, sb, cb);
+            sincos_turn(a.thb[q].x, sa, ca);
+            sincos_turn(a.thb[q].y, sb, cb);
             *(float4*)&cs[S::BLACK0 + black_row<S>(g, q) * S::WS + 2 * g.s + 2] = make_float4(ca, sa, cb, sb);
         }
     }
-    if (e < S::NEDGE) {
+    if (NT - 1 - (int)threadIdx.x < S::NEDGE) {
         float s_, c_;
-        sincos_turn(the, s_, c_);
-        cs[(e_red ? 0 : S::BLACK0) + e_row * S::WS + e_col] = make_float2(c_, s_);
+        sincos_turn(a.the, s_, c_);
+        cs[(a.e_red ? 0 : S::BLACK0) + a.e_row * S::WS + a.e_col] = make_float2(c_, s_);
     }
-    __syncthreads();
+}
 
+// Both half-sweeps of a filled tile (after the fill's barrier); the updated angles
+// go to rd.  MEAS as for tile1_program.  Ends with the black updates (no barrier).
+template <typename T, int TX, int TY, int NT, int MEAS>
+__device__ __forceinline__ void tile1_sweep(const T1Geom& g, float2* __restrict__ cs, T1Regs<TX, TY, NT>& a,
+                                            __amdgpu_buffer_rsrc_t rd, uint32_t sweep, uint32_t k0, uint32_t k1,
+                                            const Params& p, bool meas, double* part, double* red)
+{
+    const int tid = threadIdx.x;
+    const int e = NT - 1 - tid;
     int acc = 0;
     MeasAcc m;
     // wave-uniform (rt has the wave's parity): made scalar so both phases branch per
     // wave instead of running both parity variants under exec masks
-    const bool red_odd = __builtin_amdgcn_readfirstlane((y0 + g.rt) & 1) != 0;
+    const bool red_odd = __builtin_amdgcn_readfirstlane((g.y0 + g.rt) & 1) != 0;
     if (red_odd)
-        tile1_red<T, TX, TY, NT, 1>(g, cs, thr, rd, sweep, k0, k1, p, the, e, e_row, e_col, e_red, e_k, acc);
+        tile1_red<T, TX, TY, NT, 1>(g, cs, a.thr, rd, sweep, k0, k1, p, a.the, e, a.e_row, a.e_col, a.e_red, a.e_k,
+                                    acc);
     else
-        tile1_red<T, TX, TY, NT, 0>(g, cs, thr, rd, sweep, k0, k1, p, the, e, e_row, e_col, e_red, e_k, acc);
+        tile1_red<T, TX, TY, NT, 0>(g, cs, a.thr, rd, sweep, k0, k1, p, a.the, e, a.e_row, a.e_col, a.e_red, a.e_k,
+                                    acc);
     __syncthreads();
     if (MEAS == 1 || (MEAS == -1 && meas)) {
         if (red_odd)
-            tile1_black<T, TX, TY, NT, 0, true>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
+            tile1_black<T, TX, TY, NT, 0, true>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
         else
-            tile1_black<T, TX, TY, NT, 1, true>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
+            tile1_black<T, TX, TY, NT, 1, true>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
         double v[7] = {(double)m.cx, (double)m.cy, (double)m.ix, (double)m.iy, (double)m.mx, (double)m.my,
                        (double)acc};
         if constexpr (MEAS == 1) {
@@ -443,10 +463,32 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
         }
     } else {
         if (red_odd)
-            tile1_black<T, TX, TY, NT, 0, false>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
+            tile1_black<T, TX, TY, NT, 0, false>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
         else
-            tile1_black<T, TX, TY, NT, 1, false>(g, cs, thb, rd, sweep, k0, k1, p, acc, m);
+            tile1_black<T, TX, TY, NT, 1, false>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
     }
+}
+
+// src/dst: the two state buffers (same layout); `state_bytes` bounds the buffer
+// descriptors.  MEAS selects the measurement at compile time:
+//   MEAS = 0 : never measure;
+//   MEAS = 1 : always measure, one partial record per wave at part[wave * 8 ..]
+//              (no barrier and no cross-wave step: the records are summed later in
+//              a fixed order);
+//   MEAS = -1: measure if `meas`, one partial record per tile at part[0 .. 8].
+// A record is (Cx, Cy, Ix, Iy, Mx, My, accepts, 0).
+template <typename T, int TX, int TY, int NT, int MEAS = -1>
+__device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __restrict__ dst, unsigned state_bytes,
+                                              int L, int x0, int y0, uint32_t sweep, uint32_t k0, uint32_t k1,
+                                              const Params& p, bool meas, double* part, char* smem, double* red)
+{
+    float2* cs = (float2*)smem;
+    const T1Geom g = tile1_geom<TX, TY, NT>(L, x0, y0);
+    T1Regs<TX, TY, NT> a;
+    tile1_load<T, TX, TY, NT>(g, make_rsrc(src, state_bytes), a);
+    tile1_fill<TX, TY, NT>(g, cs, a);
+    __syncthreads();
+    tile1_sweep<T, TX, TY, NT, MEAS>(g, cs, a, make_rsrc(dst, state_bytes), sweep, k0, k1, p, meas, part, red);
 }
 
 }  // namespace xyd
