@@ -295,6 +295,68 @@ def test_full_size_sampled_sites(orc, L, beta, delta, plan):
     assert recs[1]["sweep"] == 2 and 0 < recs[1]["n_accept"] < L * L
 
 
+def _records_by_row_chunks(state, L, rows=1024):
+    """(cx, cy, ix, iy, mx, my) of a state in float64, computed on the device in
+    chunks of rows (natural layout of rows r0 .. r1 plus the row below)."""
+    tp = 2 * math.pi                                       # angles are stored in turns
+    sums = [0.0] * 6
+    kk = torch.arange(L // 2, device="cuda")[None, :]
+    for r0 in range(0, L, rows):
+        r1 = min(L, r0 + rows)
+        ys = torch.arange(r0, r1 + 1, device="cuda") % L          # rows r0 .. r1 (wrapping)
+        nat = torch.empty((r1 - r0 + 1, L), dtype=torch.float64, device="cuda")
+        yy = ys[:, None]
+        for c in (0, 1):
+            nat[torch.arange(r1 - r0 + 1, device="cuda")[:, None].expand(-1, L // 2),
+                2 * kk + ((c + yy) & 1)] = state[c][ys].double()
+        body = nat[:-1]
+        right = torch.roll(body, -1, 1)
+        down = nat[1:]
+        vals = [torch.cos(tp * (body - right)).sum(), torch.cos(tp * (body - down)).sum(),
+                torch.sin(tp * (body - right)).sum(), torch.sin(tp * (body - down)).sum(),
+                torch.cos(tp * body).sum(), torch.sin(tp * body).sum()]
+        for i, v in enumerate(vals):
+            sums[i] += float(v)
+        del nat, body, right, down
+    return sums
+
+
+@pytest.mark.parametrize("L,plan", [(32704, (2, 64, 16, 1)), (32640, (3, 128, 64, 1)), (46340, STREAM)])
+def test_maximum_sizes_sampled_sites(orc, L, plan):
+    """The largest lattices: 32704 and 32640 keep 4 L^2 bytes of state just below
+    the 4 GiB that the tile and strip kernels' 32-bit buffer offsets address;
+    46340 is the largest L the interface accepts (L^2 < 2^31), on the streaming
+    plan.  Two sweeps, 600 sampled sites (corners and edges included) against the
+    oracle's light cones, the last record against a float64 recomputation."""
+    beta, delta = 1.0, 1.2
+    lat = xy.Lattice(L, seed=1, beta=beta, delta=delta, plan=plan)
+    assert lat.plan == plan
+    obs = lat.sweep(2, 1)
+    recs = xy.records(obs)
+    rng = np.random.default_rng(L)
+    pts = [(0, 0), (L - 1, L - 1), (0, L - 1), (L - 1, 0), (1, 0), (0, 1), (L - 2, L - 1), (L // 2, L - 1)]
+    pts += [tuple(map(int, p)) for p in rng.integers(0, L, size=(600, 2))]
+    xs = torch.tensor([p[0] for p in pts], device="cuda")
+    ys = torch.tensor([p[1] for p in pts], device="cuda")
+    cs = (xs + ys) & 1
+    g = lat.state[cs, ys, xs >> 1].double().cpu().numpy()
+    memo = {}
+    checked = 0
+    for i, (x, y) in enumerate(pts):
+        v, marg = _light_cone_value(orc, 1, L, beta, delta, x, y, 2, memo)
+        if marg < EXEMPT:
+            continue
+        assert g[i] == v, (L, x, y, g[i], v)
+        checked += 1
+    assert checked > 560
+    ref = _records_by_row_chunks(lat.state, L)
+    for name, r in zip(["cx", "cy", "ix", "iy", "mx", "my"], ref):
+        assert abs(float(recs[1][name]) - r) <= obs_tol(r, L * L), (name, float(recs[1][name]), r)
+    assert recs[1]["sweep"] == 2 and 0 < recs[1]["n_accept"] < L * L
+    del lat, obs
+    torch.cuda.empty_cache()
+
+
 # ----------------------------------------------------------------- batches
 
 SCHEDULES = [0, 1, 2]   # XY_BATCH_PERSISTENT, XY_BATCH_PASSES, XY_BATCH_PASSES_WIDE
