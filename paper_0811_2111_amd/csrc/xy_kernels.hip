@@ -48,6 +48,7 @@ Work carve(void* work, int L, int precision)
     w.pingpong = p;
     p += align256(state_bytes(L, precision));
     w.counter = (unsigned long long*)p;
+    w.arrive = (unsigned*)(w.counter + 2);    // within the 4 u64 zeroed at init
     p += 256;
     w.partials = (double*)p;
     w.max_partials = max_partials_for(L);
@@ -338,10 +339,65 @@ hipError_t launch_reduce_chunks(const double* partials, int nparts, double* out,
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* partials, int nparts, unsigned long long* counter, xy_obs* out,
-                           uint64_t sweep_after, hipStream_t s, double* scratch)
+// Both levels in one launch: every workgroup sums its chunk of 256 records as
+// k_reduce_chunks does and writes the result to `chunks`; the workgroup that
+// arrives last (a counter in device memory, released and acquired at device
+// scope) sums the chunk results as k_finalize does, writes the record and sets
+// the counter back to zero.  The sums, and their order, are those of the two
+// separate kernels.
+__global__ void __launch_bounds__(256)
+k_reduce_finalize(const double* __restrict__ partials, int nparts, double* __restrict__ chunks,
+                  unsigned* __restrict__ arrive, unsigned long long* __restrict__ counter, xy_obs* __restrict__ out,
+                  uint64_t sweep_after)
 {
-    if (nparts > 2048 && scratch) {
+    __shared__ double red[4 * 7];
+    __shared__ int last;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (i < nparts) {
+        const double* q = partials + (size_t)i * 8;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) v[k] = q[k];
+    }
+    block_sum7_256(v, red);
+    if (threadIdx.x == 0) {
+        double* o = chunks + (size_t)blockIdx.x * 8;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) o[k] = v[k];
+        o[7] = 0.0;
+        __threadfence();
+        last = atomicAdd(arrive, 1u) == gridDim.x - 1u;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int nb = (int)gridDim.x;
+    double w[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int c = threadIdx.x; c < nb; c += 256) {
+        const double* q = chunks + (size_t)c * 8;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) w[k] += q[k];
+    }
+    block_sum7_256(w, red);
+    if (threadIdx.x == 0) {
+        xy_obs o;
+        o.sweep = sweep_after;
+        o.n_accept = (counter ? *counter : 0ull) + (unsigned long long)w[6];
+        o.cx = w[0]; o.cy = w[1]; o.ix = w[2]; o.iy = w[3]; o.mx = w[4]; o.my = w[5];
+        *out = o;
+        if (counter) *counter = 0ull;
+        *arrive = 0u;
+    }
+}
+
+hipError_t launch_finalize(const double* partials, int nparts, unsigned long long* counter, xy_obs* out,
+                           uint64_t sweep_after, hipStream_t s, double* scratch, unsigned* arrive)
+{
+    if (nparts > 2048 && scratch && arrive) {
+        const int nb = (nparts + 255) / 256;
+        hipLaunchKernelGGL(k_reduce_finalize, dim3(nb), dim3(256), 0, s, partials, nparts, scratch, arrive, counter,
+                           out, sweep_after);
+    } else if (nparts > 2048 && scratch) {
         const int nb = (nparts + 255) / 256;
         hipLaunchKernelGGL(k_reduce_chunks, dim3(nb), dim3(256), 0, s, partials, nparts, scratch);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, scratch, nb, counter, out, sweep_after);

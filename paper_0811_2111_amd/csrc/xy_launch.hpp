@@ -23,6 +23,7 @@ struct SweepArgs {
 struct Work {
     void* pingpong;                 // second state buffer (fused schedule)
     unsigned long long* counter;    // accept counter (one u64)
+    unsigned* arrive;               // arrival counter of the one-launch finalize (zeroed with counter)
     double* partials;               // per-workgroup measurement partials, 8 doubles each
     int max_partials;
     double* chunks;                 // second-level sums of 256 partials each
@@ -49,8 +50,12 @@ hipError_t launch_measure(const void* st, int L, int precision, double* partials
 // Sums of 256 consecutive records (slots 0..6) into out[chunk * 8 ..], fixed order.
 hipError_t launch_reduce_chunks(const double* partials, int nparts, double* out, hipStream_t s);
 
+// partials -> one record.  More than 2048 partials take two levels through
+// `scratch`: in one launch when `arrive` (a zeroed u32 in device memory, zero again
+// afterwards) is given, else in two.
 hipError_t launch_finalize(const double* partials, int nparts, unsigned long long* counter,
-                           xy_obs* out, uint64_t sweep_after, hipStream_t s, double* scratch);
+                           xy_obs* out, uint64_t sweep_after, hipStream_t s, double* scratch,
+                           unsigned* arrive = nullptr);
 
 // Fused tiled sweep(s): `m` sweeps (1 or 2) per launch from a.src to a.dst.
 // meas_mask bit j set: measure after sub-sweep j into the 8-double record

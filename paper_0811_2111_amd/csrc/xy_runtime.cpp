@@ -273,7 +273,8 @@ static int stream_sweep(xy_lattice* h, bool measured, xy_obs* rec, uint8_t* dbg_
         int np = 0;
         e = xyk::launch_measure(h->state, h->L, h->precision, h->w.partials, h->w.max_partials, &np, h->stream);
         if (e == hipSuccess)
-            e = xyk::launch_finalize(h->w.partials, np, h->w.counter, rec, h->sweep, h->stream, h->w.chunks);
+            e = xyk::launch_finalize(h->w.partials, np, h->w.counter, rec, h->sweep, h->stream, h->w.chunks,
+                                     h->w.arrive);
         if (e != hipSuccess) return hip_fail(e, "measure launch");
     }
     return XY_OK;
@@ -336,7 +337,7 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
         for (int js = 0; js < m; ++js) {
             if (!(mask & (1u << js))) continue;
             e = xyk::launch_finalize(h->w.partials + (size_t)js * nrec * 8, nrec, nullptr,
-                                     rec_of(j + js + 1), h->sweep + js + 1, h->stream, h->w.chunks);
+                                     rec_of(j + js + 1), h->sweep + js + 1, h->stream, h->w.chunks, h->w.arrive);
             if (e != hipSuccess) return hip_fail(e, "finalize launch");
         }
         h->sweep += m;
@@ -355,7 +356,8 @@ int xy_measure(xy_lattice* h, xy_obs* obs_dev)
     if (!obs_dev) return XY_ESTATE;
     int np = 0;
     hipError_t e = xyk::launch_measure(h->state, h->L, h->precision, h->w.partials, h->w.max_partials, &np, h->stream);
-    if (e == hipSuccess) e = xyk::launch_finalize(h->w.partials, np, nullptr, obs_dev, h->sweep, h->stream, h->w.chunks);
+    if (e == hipSuccess)
+        e = xyk::launch_finalize(h->w.partials, np, nullptr, obs_dev, h->sweep, h->stream, h->w.chunks, h->w.arrive);
     if (e != hipSuccess) return hip_fail(e, "measure launch");
     return XY_OK;
 }
