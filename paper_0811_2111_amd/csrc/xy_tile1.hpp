@@ -485,9 +485,14 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     float2* cs = (float2*)smem;
     const T1Geom g = tile1_geom<TX, TY, NT>(L, x0, y0);
     T1Regs<TX, TY, NT> a;
+    // The fill (loads, sin/cos, LDS writes) holds up the whole workgroup at its
+    // barrier; its waves issue ahead of other workgroups' update work on the same
+    // SIMD (measured: +2% on a sweep with records every 10, neutral otherwise).
+    __builtin_amdgcn_s_setprio(2);
     tile1_load<T, TX, TY, NT>(g, make_rsrc(src, state_bytes), a);
     tile1_fill<TX, TY, NT>(g, cs, a);
     __syncthreads();
+    __builtin_amdgcn_s_setprio(0);
     tile1_sweep<T, TX, TY, NT, MEAS>(g, cs, a, make_rsrc(dst, state_bytes), sweep, k0, k1, p, meas, part, red);
 }
 
