@@ -97,7 +97,8 @@ def parse():
                     help="fixed plan 'kind,tile_x,tile_y,sweeps_per_pass' instead of autotuning")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc"], default="l4096",
+    ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc", "quad", "fp16", "tempering"],
+                    default="l4096",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
     ap.add_argument("--schedule", type=int, default=None,
                     help="with --kernel-only --workload batch: batch schedule (0 persistent, 1 per-sweep, "
@@ -235,7 +236,7 @@ def main():
 
 
 def profile_leg(args, stream):
-    """Only the sweeps of the L = 16384 or the batched configuration (profiler runs)."""
+    """Only the sweeps of one non-default configuration (profiler runs)."""
     import torch
 
     from paper_0811_2111_amd import workloads, xy
@@ -261,6 +262,33 @@ def profile_leg(args, stream):
         ms = timed(lambda: lat.hmc(args.steps, hc["n_md"], hc["eps"]), stream)
         print(json.dumps({"workload": "HMC L16384", "trajectories": args.steps, "ms": ms,
                           "g_site_steps_s": float(hc["L"]) ** 2 * hc["n_md"] * args.steps / (ms * 1e-3) / 1e9}))
+    elif args.workload == "quad":
+        qc = workloads.QUAD_4096
+        qd = xy.Quad(qc["L"], qc["seeds"], qc["betas"], [qc["delta"]] * 4)
+        nrec = max(args.steps // qc["measure_every"], 1)
+        qobs = torch.empty((nrec, 4, 8), dtype=torch.float64, device="cuda")
+        qd.sweep(args.warmup)
+        ms = timed(lambda: qd.sweep(args.steps, qc["measure_every"], out=qobs), stream)
+        print(json.dumps({"workload": "quad L4096", "sweeps": args.steps, "ms": ms,
+                          "gupd_s": 4.0 * float(qc["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}))
+    elif args.workload == "fp16":
+        pc = workloads.PRECISION
+        plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
+        lat = xy.Lattice(pc["L"], seed=pc["seed"], beta=1.0, delta=pc["delta"], precision="fp16", plan=plan)
+        lat.sweep(args.warmup)
+        ms = timed(lambda: lat.sweep(args.steps, 10), stream)
+        print(json.dumps({"workload": "FP16 L8192", "sweeps": args.steps, "ms": ms, "plan": list(lat.plan),
+                          "gupd_s": float(pc["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}))
+    elif args.workload == "tempering":
+        sc = workloads.temperature_scan()
+        tb = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+        K = sc["measure_every"]
+        rounds = max(args.steps // K, 1)
+        tb.tempering(max(args.warmup // K, 1), K, 1)
+        ms = timed(lambda: tb.tempering(rounds, K, 1), stream)
+        sites = sum(L * L for L in sc["Ls"])
+        print(json.dumps({"workload": "tempering scan", "rounds": rounds, "ms": ms,
+                          "gupd_s": float(sites) * rounds * K / (ms * 1e-3) / 1e9}))
     else:
         sc = workloads.temperature_scan()
         b = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
@@ -362,6 +390,8 @@ def extra_legs(stream, main_lat=None):
         res[prec] = round(float(pc["L"]) ** 2 * 200 / (ms_x * 1e-3) / 1e9, 2)
         del lt
     ex["L8192_storage_gupd_s"] = res
+    # algorithmic bytes of a fused sweep: 8 B per update in FP32, 4 B in FP16
+    ex["L8192_storage_alg_GBps"] = {"fp32": round(res["fp32"] * 8.0, 1), "fp16": round(res["fp16"] * 4.0, 1)}
 
     # four replicas of L = 4096 in one float4 state vs the same four as single lattices
     qc = workloads.QUAD_4096
@@ -384,6 +414,7 @@ def extra_legs(stream, main_lat=None):
     torch.cuda.empty_cache()
     upd = 4.0 * qc["L"] ** 2 * qc["sweeps"]
     ex["quad_L4096"] = {"gupd_s": round(upd / (ms_q * 1e-3) / 1e9, 2), "tile": list(tile_q),
+                        "alg_GBps_8B": round(upd / (ms_q * 1e-3) / 1e9 * 8.0, 1),
                         "four_single_lattices_gupd_s": round(upd / (ms_s * 1e-3) / 1e9, 2),
                         "sweeps": qc["sweeps"], "betas": qc["betas"]}
 
