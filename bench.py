@@ -97,7 +97,7 @@ def parse():
                     help="fixed plan 'kind,tile_x,tile_y,sweeps_per_pass' instead of autotuning")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc", "quad", "fp16", "tempering"],
+    ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc", "quad", "fp16", "tempering", "small"],
                     default="l4096",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
     ap.add_argument("--schedule", type=int, default=None,
@@ -279,6 +279,24 @@ def profile_leg(args, stream):
         ms = timed(lambda: lat.sweep(args.steps, 10), stream)
         print(json.dumps({"workload": "FP16 L8192", "sweeps": args.steps, "ms": ms, "plan": list(lat.plan),
                           "gupd_s": float(pc["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}))
+    elif args.workload == "small":
+        # the parity configuration (L = 32, a record every sweep) on the LDS-resident
+        # plan and on the streaming plan, then a batch of 2048 such lattices
+        pc = workloads.PARITY_32
+        res = {}
+        for name, plan in (("resident", (xy.XY_PLAN_RESIDENT, 0, 0, 1)), ("stream", (xy.XY_PLAN_STREAM, 0, 0, 1))):
+            lat = xy.Lattice(pc["L"], seed=pc["seed"], beta=pc["beta"], delta=pc["delta"], plan=plan)
+            lat.sweep(args.warmup, 1)
+            ms = timed(lambda: lat.sweep(args.steps, 1), stream)
+            res[name] = {"us_per_sweep": ms * 1e3 / args.steps,
+                         "gupd_s": float(pc["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}
+            del lat
+        n = 2048
+        b = xy.Batch([pc["L"]] * n, [pc["seed"] + i for i in range(n)], [pc["beta"]] * n, [pc["delta"]] * n)
+        b.sweep(args.warmup)
+        ms = timed(lambda: b.sweep(args.steps, 10), stream)
+        res["batch_2048"] = {"gupd_s": float(pc["L"]) ** 2 * n * args.steps / (ms * 1e-3) / 1e9}
+        print(json.dumps({"workload": "L32", "sweeps": args.steps, **res}))
     elif args.workload == "tempering":
         sc = workloads.temperature_scan()
         tb = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
