@@ -367,6 +367,88 @@ k_hmc_end(const float* __restrict__ st, float* __restrict__ copy, const float* _
     write_record(v, rec, t);
 }
 
+// Begin and end of a trajectory for L % 4 == 0, by pairs: a thread takes the
+// entries 2j, 2j+1 of colour c in a run of consecutive rows; the other plane's
+// pair j of the rows above, at and below a row are kept in registers as a
+// rolling window, so each row loads one new other-plane pair and one edge entry
+// (2j-1 or 2j+2) and computes 2.5 sines and cosines per site instead of 5.
+// 1-D grid of cols2 = 2 ceil(J/256) column blocks (colour interleaved) times rb
+// row blocks, remapped by xcd_band; one partial record per wave.
+struct PairCS {
+    float c0, s0, c1, s1;
+};
+__device__ __forceinline__ PairCS pair_cs(float2 t)
+{
+    PairCS q;
+    sincos_turn(t.x, q.s0, q.c0);
+    sincos_turn(t.y, q.s1, q.c1);
+    return q;
+}
+
+// Neighbourhoods of the pair (entries 2j, 2j+1) of row y: own (cos, sin) in a,
+// b; the other plane's row above (u), at (h) and below (d) and the edge entry e.
+__device__ __forceinline__ void pair_nb(const PairCS& own, const PairCS& u, const PairCS& h, const PairCS& d,
+                                       float ce, float se, int o, Nb& na, Nb& nb)
+{
+    na.c = own.c0; na.s = own.s0;
+    nb.c = own.c1; nb.s = own.s1;
+    // entry 2j: left = (o ? h0 : e), right = (o ? h1 : h0); 2j+1: left = (o ? h1 : h0), right = (o ? e : h1)
+    na.cl = o ? h.c0 : ce;   na.sl = o ? h.s0 : se;
+    na.cr = o ? h.c1 : h.c0; na.sr = o ? h.s1 : h.s0;
+    nb.cl = o ? h.c1 : h.c0; nb.sl = o ? h.s1 : h.s0;
+    nb.cr = o ? ce : h.c1;   nb.sr = o ? se : h.s1;
+    na.cu = u.c0; na.su = u.s0; nb.cu = u.c1; nb.su = u.s1;
+    na.cd = d.c0; na.sd = d.s0; nb.cd = d.c1; nb.sd = d.s1;
+}
+
+template <bool BEGIN>
+__global__ void __launch_bounds__(kThreads)
+k_hmc_ends2(const float* __restrict__ st, float* __restrict__ p, float* __restrict__ copy, int L, uint32_t traj,
+            uint32_t k0, uint32_t k1, float nbeta_kick, int cols, int rb, double* __restrict__ rec)
+{
+    const int Hh = L >> 1, J = Hh >> 1;
+    const unsigned t = xcd_band(blockIdx.x, gridDim.x);
+    const int col = (int)(t % (unsigned)cols);
+    const int c = col & 1;
+    const int j = (col >> 1) * kThreads + threadIdx.x;
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int R = (L + rb - 1) / rb, y0 = (int)(t / (unsigned)cols) * R, y1 = y0 + R < L ? y0 + R : L;
+    if (j < J && y0 < y1) {
+        const float* own = st + (size_t)c * L * Hh;
+        const float* oth = st + (size_t)(1 - c) * L * Hh;
+        PairCS u = pair_cs(((const float2*)(oth + (size_t)wrapi(y0 - 1, L) * Hh))[j]);
+        PairCS h = pair_cs(((const float2*)(oth + (size_t)y0 * Hh))[j]);
+        for (int y = y0; y < y1; ++y) {
+            const int o = (c + y) & 1;
+            const size_t row = ((size_t)c * L + y) * Hh;
+            const float2 th = ((const float2*)(own + (size_t)y * Hh))[j];
+            const PairCS d = pair_cs(((const float2*)(oth + (size_t)wrapi(y + 1, L) * Hh))[j]);
+            float se, ce;
+            sincos_turn(oth[(size_t)y * Hh + (o ? wrapi(2 * j + 2, Hh) : wrapi(2 * j - 1, Hh))], se, ce);
+            Nb na, nb;
+            pair_nb(pair_cs(th), u, h, d, ce, se, o, na, nb);
+            float pa, pb;
+            if constexpr (BEGIN) {
+                ((float2*)(copy + row))[j] = th;       // saved angles
+                const u32x4 r = philox10(traj, (uint32_t)c, 2u, (uint32_t)y * (uint32_t)J + (uint32_t)j, k0, k1);
+                pa = box_muller(r.x, r.y);
+                pb = box_muller(r.z, r.w);
+                ((float2*)(p + row))[j] = make_float2(pa, pb);
+            } else {
+                if (copy) ((float2*)(copy + row))[j] = th;
+                const float2 pv = ((const float2*)(p + row))[j];
+                pa = __fmaf_rn(nbeta_kick, sin_sum(na), pv.x);
+                pb = __fmaf_rn(nbeta_kick, sin_sum(nb), pv.y);
+            }
+            accumulate(v, na, c, __fmul_rn(0.5f, __fmul_rn(pa, pa)));
+            accumulate(v, nb, c, __fmul_rn(0.5f, __fmul_rn(pb, pb)));
+            u = h;
+            h = d;
+        }
+    }
+    write_record(v, rec, t);              // every lane reaches the wave sums
+}
+
 // Sum of one set of records in a fixed order (thread t: records t, t + 256, ...,
 // then the wave sums and the four waves in order); thread 0 gets the totals.
 __device__ void sum_records(const double* __restrict__ rec, int nrec, double out[7], double* red)
@@ -437,7 +519,20 @@ static int hmc_row_blocks(int L)
     return gy < 1 ? 1 : gy;
 }
 
-int hmc_records(int L) { return hmc_cols(L) * hmc_row_blocks(L) * (kThreads / 64); }
+static bool hmc_pairs(int L) { return L % 4 == 0; }
+static int hmc_cols2(int L) { return 2 * (((L >> 2) + kThreads - 1) / kThreads); }
+static int hmc_row_blocks2(int L)
+{
+    int gy = kHmcMaxRecords / (hmc_cols2(L) * (kThreads / 64));
+    if (gy > L) gy = L;
+    return gy < 1 ? 1 : gy;
+}
+
+int hmc_records(int L)
+{
+    if (hmc_pairs(L)) return hmc_cols2(L) * hmc_row_blocks2(L) * (kThreads / 64);
+    return hmc_cols(L) * hmc_row_blocks(L) * (kThreads / 64);
+}
 
 size_t hmc_work_bytes(int L)
 {
@@ -474,12 +569,17 @@ hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w
                                  int n_md, int steps_per_pass, uint32_t traj, uint32_t k0, uint32_t k1,
                                  xy_hmc_obs* obs, hipStream_t s)
 {
-    const int cols = hmc_cols(L), rb = hmc_row_blocks(L);
-    const dim3 grec((unsigned)(cols * rb)), gstep(cols, L), block(kThreads);
+    const bool pairs2 = hmc_pairs(L);
+    const int cols = pairs2 ? hmc_cols2(L) : hmc_cols(L), rb = pairs2 ? hmc_row_blocks2(L) : hmc_row_blocks(L);
+    const dim3 grec((unsigned)(cols * rb)), gstep(hmc_cols(L), L), block(kThreads);
     const int nrec = hmc_records(L);
     const int nchunk = (nrec + 255) / 256;
     const float drift = (float)(eps / (2.0 * 3.14159265358979323846));
-    hipLaunchKernelGGL(k_hmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, cols, rb, w.rec_old);
+    if (pairs2)
+        hipLaunchKernelGGL(k_hmc_ends2<true>, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, 0.0f, cols, rb,
+                           w.rec_old);
+    else
+        hipLaunchKernelGGL(k_hmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, cols, rb, w.rec_old);
     float* src = state;
     float* dst = pingpong;
     float* p = w.p;
@@ -514,8 +614,12 @@ hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w
             dst = t;
         }
     }
-    hipLaunchKernelGGL(k_hmc_end, grec, block, 0, s, src, src == state ? nullptr : state, p, L, kick_half, cols, rb,
-                       w.rec_new);
+    if (pairs2)
+        hipLaunchKernelGGL(k_hmc_ends2<false>, grec, block, 0, s, src, p, src == state ? nullptr : state, L, traj, k0,
+                           k1, kick_half, cols, rb, w.rec_new);
+    else
+        hipLaunchKernelGGL(k_hmc_end, grec, block, 0, s, src, src == state ? nullptr : state, p, L, kick_half, cols,
+                           rb, w.rec_new);
     hipError_t e = launch_reduce_chunks(w.rec_old, nrec, w.chunk_old, s);
     if (e == hipSuccess) e = launch_reduce_chunks(w.rec_new, nrec, w.chunk_new, s);
     if (e != hipSuccess) return e;

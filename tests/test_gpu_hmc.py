@@ -57,8 +57,11 @@ def test_momenta_match_oracle(orc):
         assert np.max(np.abs(p_dev - p_ref) / np.maximum(1.0, np.abs(p_ref))) < 3e-6
 
 
-def test_one_trajectory_matches_oracle(orc):
-    L, seed, beta, eps, n = 32, 3, 1.0, 0.1, 10
+@pytest.mark.parametrize("L", [32, 130])
+def test_one_trajectory_matches_oracle(orc, L):
+    """L = 32 takes the pair kernels for the trajectory's ends, L = 130 (L % 4 = 2)
+    the single-entry ones."""
+    seed, beta, eps, n = 3, 1.0, 0.1, 10
     lat = xy.Lattice(L, seed=seed, beta=beta)
     phi = orc.hot_start(seed, L, "f32")
     np.testing.assert_array_equal(natural(lat.state), phi)
