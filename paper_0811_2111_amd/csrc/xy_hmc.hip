@@ -317,12 +317,112 @@ k_hmc_multi(const float* __restrict__ src, float* __restrict__ dst, const float*
     }
 }
 
+// The same pass on larger tiles: T x T sites grown by K, NT threads, and with
+// SINGLE one LDS buffer of (cos, sin) (every update of a step reads its
+// neighbours, barrier, the new values are written, barrier), which halves the LDS
+// so that 64 x 64 tiles keep three workgroups of 512 threads on a CU.  The grown
+// tile is 1.27 times the tile at T = 64, K = 4 (1.56 at T = 32), so less of the
+// work goes to the halo.  Per site the arithmetic is that of k_hmc_step.
+template <int K, int T, int NT, bool SINGLE>
+__global__ void __launch_bounds__(NT)
+k_hmc_multi_g(const float* __restrict__ src, float* __restrict__ dst, const float* __restrict__ psrc,
+              float* __restrict__ pdst, int L, float kick0, float kick, float drift)
+{
+    constexpr int E = T + 2 * K, NE = E * E, M = (NE + NT - 1) / NT;
+    __shared__ float2 cs[SINGLE ? 1 : 2][NE];
+    const int Hh = L >> 1, nt = L / T;
+    const int b = (int)xcd_band(blockIdx.x, gridDim.x);
+    const int ty = b / nt, tx = b - ty * nt;
+    const int x0 = tx * T - K, y0 = ty * T - K;
+    float th[M], pm[M];
+    unsigned off[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = threadIdx.x + m * NT;
+        if (i < NE) {
+            const int ye = i / E, xe = i - ye * E;
+            const int x = wrapi(x0 + xe, L), y = wrapi(y0 + ye, L);
+            off[m] = (unsigned)((((x + y) & 1) * L + y) * Hh + (x >> 1));
+            th[m] = src[off[m]];
+            pm[m] = psrc[off[m]];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = threadIdx.x + m * NT;
+        if (i < NE) {
+            float sn, cn;
+            sincos_turn(th[m], sn, cn);
+            cs[0][i] = make_float2(cn, sn);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const float2* cur = cs[SINGLE ? 0 : (q & 1)];
+        float2* nxt = cs[SINGLE ? 0 : ((q + 1) & 1)];
+        const float kq = q == 0 ? kick0 : kick;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int i = threadIdx.x + m * NT;
+            if (i < NE) {
+                const int ye = i / E, xe = i - ye * E;
+                if (xe > q && xe < E - 1 - q && ye > q && ye < E - 1 - q) {
+                    const float2 own = cur[i], l = cur[i - 1], r = cur[i + 1], u = cur[i - E], d = cur[i + E];
+                    Nb n;
+                    n.c = own.x; n.s = own.y;
+                    n.cl = l.x; n.sl = l.y; n.cr = r.x; n.sr = r.y;
+                    n.cu = u.x; n.su = u.y; n.cd = d.x; n.sd = d.y;
+                    pm[m] = __fmaf_rn(kq, sin_sum(n), pm[m]);
+                    th[m] = __builtin_amdgcn_fractf(__fmaf_rn(drift, pm[m], th[m]));
+                }
+            }
+        }
+        if (q + 1 < K) {
+            if constexpr (SINGLE) __syncthreads();
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int i = threadIdx.x + m * NT;
+                if (i < NE) {
+                    const int ye = i / E, xe = i - ye * E;
+                    if (xe > q && xe < E - 1 - q && ye > q && ye < E - 1 - q) {
+                        float sn, cn;
+                        sincos_turn(th[m], sn, cn);
+                        nxt[i] = make_float2(cn, sn);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = threadIdx.x + m * NT;
+        if (i < NE) {
+            const int ye = i / E, xe = i - ye * E;
+            if (xe >= K && xe < E - K && ye >= K && ye < E - K) {
+                dst[off[m]] = th[m];
+                pdst[off[m]] = pm[m];
+            }
+        }
+    }
+}
+
 constexpr int kMaxStepsPerPass = 8;
 
+constexpr int kWideTile = 64, kWideThreads = 512;
+
+// L % 64 == 0: 64 x 64 tiles, 512 threads, one LDS buffer; else 32 x 32 tiles.
 template <int K>
 static void launch_multi(unsigned nb, hipStream_t s, const float* src, float* dst, const float* psrc, float* pdst,
                          int L, float kick0, float kick, float drift)
 {
+    if (L % kWideTile == 0) {
+        const unsigned nbw = (unsigned)((L / kWideTile) * (L / kWideTile));
+        hipLaunchKernelGGL((k_hmc_multi_g<K, kWideTile, kWideThreads, true>), dim3(nbw), dim3(kWideThreads), 0, s, src,
+                           dst, psrc, pdst, L, kick0, kick, drift);
+        return;
+    }
     hipLaunchKernelGGL(k_hmc_multi<K>, dim3(nb), dim3(kThreads), 0, s, src, dst, psrc, pdst, L, kick0, kick, drift);
 }
 
