@@ -260,12 +260,13 @@ int xy_hmc_work_bytes(int32_t L, size_t* bytes);
 int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
            xy_hmc_obs* obs_dev);
 
-/* Leap-frog steps per pass over the lattice (1 .. 8, default 4; XY_EINVAL
- * otherwise).  With more than one, for L % 32 == 0, a workgroup loads a 32 x 32
- * tile grown by that many sites on every side, runs the steps on it (the grown
- * part shrinking by one site per step) and writes the tile back, so HBM traffic
- * per site and step falls by that factor; the trajectory is bit for bit the
- * same.  xy_hmc_get_steps_per_pass reports what runs (1 if L % 32 != 0). */
+/* Leap-frog steps per pass over the lattice (1 .. 8, default 5; XY_EINVAL
+ * otherwise).  With more than one, for L % 32 == 0, a workgroup loads a 64 x 64
+ * tile (32 x 32 if L % 64 != 0) grown by that many sites on every side, runs the
+ * steps on it (the grown part shrinking by one site per step) and writes the
+ * tile back, so HBM traffic per site and step falls by that factor; the
+ * trajectory is bit for bit the same.  xy_hmc_get_steps_per_pass reports what
+ * runs (1 if L % 32 != 0). */
 int xy_hmc_set_steps_per_pass(xy_lattice* h, int32_t steps);
 int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
 

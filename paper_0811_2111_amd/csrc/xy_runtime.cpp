@@ -212,7 +212,7 @@ static int make_handle(xy_lattice** out, uint64_t seed, int32_t L, double beta, 
     h->work_len = work_len;
     h->stream = (hipStream_t)hip_stream;
     h->sweep = 0;
-    h->hmc_steps = 4;
+    h->hmc_steps = 5;
     h->w = xyk::carve(work_dev, L, precision);
     xy_plan p;
     if (!cache_lookup(env_cache_path(), L, precision, &p)) p = default_plan(L);

@@ -174,14 +174,14 @@ def test_hmc_error_codes():
     assert L_.xy_hmc(half.h, 1, 1, 0.1, *args, None) == xy.XY_EINVAL
 
 
-@pytest.mark.parametrize("L", [32, 64, 96])
+@pytest.mark.parametrize("L", [32, 64, 96, 128])
 def test_steps_per_pass_bit_identical(L):
-    """Passes of several leap-frog steps (temporal blocking over 32 x 32 tiles with a
-    halo of that many sites) give, bit for bit, the angles and records of one step
-    per launch, including a last pass with fewer steps (n_md = 7) and trajectories
-    that are rejected."""
+    """Passes of several leap-frog steps (temporal blocking over 64 x 64 tiles when
+    L % 64 == 0, else 32 x 32, with a halo of that many sites) give, bit for bit,
+    the angles and records of one step per launch, including a last pass with
+    fewer steps (n_md = 7) and trajectories that are rejected."""
     recs, states = {}, {}
-    for k in (1, 2, 3, 4, 8):
+    for k in (1, 2, 3, 4, 5, 8):
         lat = xy.Lattice(L, seed=21, beta=1.05)
         lat.set_hmc_steps_per_pass(k)
         assert lat.hmc_steps_per_pass == k
@@ -190,7 +190,7 @@ def test_steps_per_pass_bit_identical(L):
         assert int(r2["accepted"][0]) == 0
         recs[k] = (r, r2)
         states[k] = lat.state.clone()
-    for k in (2, 3, 4, 8):
+    for k in (2, 3, 4, 5, 8):
         assert torch.equal(states[k], states[1]), k
         for a, b in zip(recs[k], recs[1]):
             assert np.array_equal(a["accepted"], b["accepted"]), k
@@ -204,7 +204,7 @@ def test_steps_per_pass_settings():
     lat = xy.Lattice(48, seed=1)
     assert lat.hmc_steps_per_pass == 1                       # 48 % 32 != 0: one step per launch
     lat64 = xy.Lattice(64, seed=1)
-    assert lat64.hmc_steps_per_pass == 4                     # the default
+    assert lat64.hmc_steps_per_pass == 5                     # the default
     assert L_.xy_hmc_set_steps_per_pass(lat64.h, 0) == xy.XY_EINVAL
     assert L_.xy_hmc_set_steps_per_pass(lat64.h, 9) == xy.XY_EINVAL
     assert L_.xy_hmc_set_steps_per_pass(None, 2) == xy.XY_ESTATE
