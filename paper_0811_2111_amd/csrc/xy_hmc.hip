@@ -320,7 +320,7 @@ k_hmc_multi(const float* __restrict__ src, float* __restrict__ dst, const float*
 // The same pass on larger tiles: T x T sites grown by K, NT threads, and with
 // SINGLE one LDS buffer of (cos, sin) (every update of a step reads its
 // neighbours, barrier, the new values are written, barrier), which halves the LDS
-// so that 64 x 64 tiles keep three workgroups of 512 threads on a CU.  The grown
+// so that 64 x 64 tiles keep two workgroups of 1024 threads on a CU.  The grown
 // tile is 1.27 times the tile at T = 64, K = 4 (1.56 at T = 32), so less of the
 // work goes to the halo.  Per site the arithmetic is that of k_hmc_step.
 template <int K, int T, int NT, bool SINGLE>
@@ -410,9 +410,9 @@ k_hmc_multi_g(const float* __restrict__ src, float* __restrict__ dst, const floa
 
 constexpr int kMaxStepsPerPass = 8;
 
-constexpr int kWideTile = 64, kWideThreads = 512;
+constexpr int kWideTile = 64, kWideThreads = 1024;
 
-// L % 64 == 0: 64 x 64 tiles, 512 threads, one LDS buffer; else 32 x 32 tiles.
+// L % 64 == 0: 64 x 64 tiles, 1024 threads, one LDS buffer; else 32 x 32 tiles.
 template <int K>
 static void launch_multi(unsigned nb, hipStream_t s, const float* src, float* dst, const float* psrc, float* pdst,
                          int L, float kick0, float kick, float drift)
