@@ -1,7 +1,7 @@
 """Storage-precision bias from independent replicas (FP32 and FP16 storage on the
 device against FP64 storage in the oracle).
 
-Not collected by pytest (a long measurement, run by hand on a GPU machine):
+Not collected by pytest (a long measurement, run by hand on an MI355X):
 
     python tests/precision_replicas.py --out results.json [--replicas 16 --sweeps 4000 --discard 1000]
 

@@ -1,6 +1,6 @@
 """Precision study: FP16 vs FP32 angle storage against the FP64 oracle.
 
-Not collected by pytest (a long measurement, run by hand on a GPU machine):
+Not collected by pytest (a long measurement, run by hand on an MI355X):
 
     python tests/precision_study.py --out results.json [--sweeps 20000 --discard 2000]
 
