@@ -402,8 +402,11 @@ def extra_legs(stream, main_lat=None):
     pc = workloads.PRECISION
     res = {}
     for prec in ("fp32", "fp16"):
-        lt = xy.Lattice(pc["L"], seed=pc["seed"], beta=1.0, delta=pc["delta"], precision=prec)
-        lt.sweep(4)
+        scratch = xy.Lattice(pc["L"], seed=pc["seed"] + 1000, beta=1.0, delta=pc["delta"], precision=prec)
+        tuned_x = scratch.autotune(20)
+        del scratch
+        lt = xy.Lattice(pc["L"], seed=pc["seed"], beta=1.0, delta=pc["delta"], precision=prec, plan=tuned_x)
+        lt.sweep(20)
         ms_x = timed(lambda: lt.sweep(200, 10), stream)
         res[prec] = round(float(pc["L"]) ** 2 * 200 / (ms_x * 1e-3) / 1e9, 2)
         del lt

@@ -50,7 +50,7 @@ xyk::SweepArgs sweep_args(uint64_t seed, int L, int precision, double beta, doub
 xy_plan default_plan(int32_t L)
 {
     xy_plan p{XY_PLAN_STREAM, 0, 0, 1};
-    static const int cand[][3] = {{128, 32, 1}, {64, 32, 1}, {64, 16, 1}};
+    static const int cand[][3] = {{256, 16, 1}, {128, 32, 1}, {64, 32, 1}, {64, 16, 1}};
     for (auto& c : cand)
         if (xyk::fused_supported(L, c[0], c[1], c[2])) {
             p.kind = XY_PLAN_FUSED;
