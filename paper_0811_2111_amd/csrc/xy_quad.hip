@@ -129,9 +129,11 @@ size_t quad_state_bytes(int L) { return (size_t)L * (size_t)L * sizeof(float4); 
 // tiles (32 x 16, 64 x 8, 128 x 4) hold 512 sites
 size_t quad_max_records(int L) { return (size_t)L * (size_t)L / 512 * 4 * 4; }
 size_t quad_chunks(int L) { return (quad_max_records(L) / 4 + 255) / 256 * 4; }
+// ping-pong state, 256 bytes for the finalize's arrival counter, partials, chunks
 size_t quad_work_bytes(int L)
 {
-    return ((quad_state_bytes(L) + 255) & ~(size_t)255) + (quad_max_records(L) + quad_chunks(L)) * 8 * sizeof(double);
+    return ((quad_state_bytes(L) + 255) & ~(size_t)255) + 256 +
+           (quad_max_records(L) + quad_chunks(L)) * 8 * sizeof(double);
 }
 
 bool quad_L_ok(int32_t L)
@@ -151,6 +153,7 @@ struct xy_quad {
     float4* pingpong;
     double* partials;
     double* chunks;
+    unsigned* arrive;      // arrival counter of the one-launch record reduction (zero between calls)
     hipStream_t stream;
     uint64_t sweep;
     int32_t tile_x, tile_y;
@@ -204,6 +207,8 @@ int xy_quad_init(xy_quad** out, const uint64_t* seeds, int32_t L, const double* 
     char* w = (char*)work_dev;
     q->pingpong = (float4*)w;
     w += (quad_state_bytes(L) + 255) & ~(size_t)255;
+    q->arrive = (unsigned*)w;
+    w += 256;
     q->partials = (double*)w;
     q->chunks = q->partials + quad_max_records(L) * 8;
     q->stream = (hipStream_t)hip_stream;
@@ -214,6 +219,7 @@ int xy_quad_init(xy_quad** out, const uint64_t* seeds, int32_t L, const double* 
     hipLaunchKernelGGL(xyk::k_quad_init, dim3((P + 63) / 64, (L + 3) / 4, 2), dim3(64, 4), 0, q->stream, q->state, L,
                        quad_params(q), start == XY_HOT ? 1 : 0);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = xyk::launch_zero_u64((unsigned long long*)q->arrive, 4, q->stream);
     if (e != hipSuccess) {
         q->magic = 0;
         delete q;
@@ -245,7 +251,7 @@ int xy_quad_sweep(xy_quad* q, int64_t n_sweeps, int32_t measure_every, xy_obs* o
             xy_obs* rec = obs_dev + (size_t)(j / measure_every - 1) * 4;
             for (int r = 0; r < 4; ++r) {
                 e = xyk::launch_finalize(q->partials + (size_t)r * nrec * 8, nrec, nullptr, rec + r, q->sweep,
-                                         q->stream, q->chunks + (size_t)r * nchunk * 8);
+                                         q->stream, q->chunks + (size_t)r * nchunk * 8, q->arrive);
                 if (e != hipSuccess) return xyr::hip_fail(e, "xy_quad_sweep: finalize");
             }
         }
