@@ -314,31 +314,44 @@ struct Rung {
     float delta, nbl2e;      // as in LatDesc
 };
 
+// One workgroup; slots k = 0 .. n-1 of `member` (ladders are contiguous runs of
+// slots).  First every slot's record and rung of the round are written, then the
+// exchanges run one thread per pair of slots (the pairs of a round are disjoint,
+// and each decision depends only on its own pair).
+__device__ __forceinline__ int ladder_of(const int2* __restrict__ ladders, int nlad, int k)
+{
+    int g = 0;
+    while (g + 1 < nlad && ladders[g + 1].x <= k) ++g;
+    return g;
+}
+
 __global__ void __launch_bounds__(256)
 k_batch_exchange(LatDesc* __restrict__ lat, int* __restrict__ member, const int2* __restrict__ ladders, int nlad,
                  const Rung* __restrict__ rung, const xy_obs* __restrict__ round_obs, uint32_t round, uint32_t k0,
                  uint32_t k1, xy_obs* __restrict__ obs_out, int32_t* __restrict__ rung_out)
 {
-    for (int g = threadIdx.x; g < nlad; g += 256) {
-        const int start = ladders[g].x, len = ladders[g].y;
-        for (int t = 0; t < len; ++t) {
-            const int i = member[start + t];
-            if (obs_out) obs_out[i] = round_obs[i];
-            if (rung_out) rung_out[i] = t;
-        }
-        for (int t = (int)(round & 1u); t + 1 < len; t += 2) {
-            const int a = member[start + t], b = member[start + t + 1];
-            const double ea = -(round_obs[a].cx + round_obs[a].cy), eb = -(round_obs[b].cx + round_obs[b].cy);
-            const Rung ra = rung[start + t], rb = rung[start + t + 1];
-            const u32x4 w = philox10(round, (uint32_t)g, 4u, (uint32_t)t, k0, k1);
-            if ((double)u01(w.x) < exp((ra.beta - rb.beta) * (ea - eb))) {
-                member[start + t] = b;
-                member[start + t + 1] = a;
-                lat[a].delta = rb.delta;
-                lat[a].nbl2e = rb.nbl2e;
-                lat[b].delta = ra.delta;
-                lat[b].nbl2e = ra.nbl2e;
-            }
+    const int n = ladders[nlad - 1].x + ladders[nlad - 1].y;
+    for (int k = threadIdx.x; k < n; k += 256) {
+        const int i = member[k];
+        if (obs_out) obs_out[i] = round_obs[i];
+        if (rung_out) rung_out[i] = k - ladders[ladder_of(ladders, nlad, k)].x;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += 256) {
+        const int g = ladder_of(ladders, nlad, k);
+        const int start = ladders[g].x, len = ladders[g].y, t = k - start;
+        if (((t ^ (int)round) & 1) != 0 || t + 1 >= len) continue;
+        const int a = member[k], b = member[k + 1];
+        const double ea = -(round_obs[a].cx + round_obs[a].cy), eb = -(round_obs[b].cx + round_obs[b].cy);
+        const Rung ra = rung[k], rb = rung[k + 1];
+        const u32x4 w = philox10(round, (uint32_t)g, 4u, (uint32_t)t, k0, k1);
+        if ((double)u01(w.x) < exp((ra.beta - rb.beta) * (ea - eb))) {
+            member[k] = b;
+            member[k + 1] = a;
+            lat[a].delta = rb.delta;
+            lat[a].nbl2e = rb.nbl2e;
+            lat[b].delta = ra.delta;
+            lat[b].nbl2e = ra.nbl2e;
         }
     }
 }
