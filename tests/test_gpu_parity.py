@@ -225,25 +225,25 @@ def test_checkpoint_resume():
 
 # -------------------------------------------------- full sizes, sampled sites
 
-def _light_cone_value(orc, seed, L, beta, delta, x, y, s, memo):
+def _light_cone_value(orc, seed, L, beta, delta, x, y, s, memo, prec="f32"):
     """Angle of site (x, y) after s sweeps, from the oracle's single-site updates
     over the site's light cone; also the smallest |dE - T| met on the way."""
     key = (x, y, s)
     if key in memo:
         return memo[key]
     if s == 0:
-        v = (orc.hot_start_site(seed, L, x, y, "f32"), math.inf)
+        v = (orc.hot_start_site(seed, L, x, y, prec), math.inf)
         memo[key] = v
         return v
     red = ((x + y) & 1) == 0
-    own, m0 = _light_cone_value(orc, seed, L, beta, delta, x, y, s - 1, memo)
+    own, m0 = _light_cone_value(orc, seed, L, beta, delta, x, y, s - 1, memo, prec)
     ns = s - 1 if red else s
     nb, marg = [], m0
     for (xx, yy) in [((x - 1) % L, y), ((x + 1) % L, y), (x, (y - 1) % L), (x, (y + 1) % L)]:
-        v, m = _light_cone_value(orc, seed, L, beta, delta, xx, yy, ns, memo)
+        v, m = _light_cone_value(orc, seed, L, beta, delta, xx, yy, ns, memo, prec)
         nb.append(v)
         marg = min(marg, m)
-    t, _, dE, thr, _ = orc.site_update(seed, L, x, y, s - 1, beta, delta, own, nb, "f32")
+    t, _, dE, thr, _ = orc.site_update(seed, L, x, y, s - 1, beta, delta, own, nb, prec)
     v = (t, min(marg, abs(dE - thr)))
     memo[key] = v
     return v
@@ -321,15 +321,17 @@ def _records_by_row_chunks(state, L, rows=1024):
     return sums
 
 
-@pytest.mark.parametrize("L,plan", [(32704, (2, 64, 16, 1)), (32640, (3, 128, 64, 1)), (46340, STREAM)])
-def test_maximum_sizes_sampled_sites(orc, L, plan):
+@pytest.mark.parametrize("L,plan,prec", [(32704, (2, 64, 16, 1), "fp32"), (32640, (3, 128, 64, 1), "fp32"),
+                                         (46340, STREAM, "fp32"), (32704, (2, 64, 16, 1), "fp16")])
+def test_maximum_sizes_sampled_sites(orc, L, plan, prec):
     """The largest lattices: 32704 and 32640 keep 4 L^2 bytes of state just below
     the 4 GiB that the tile and strip kernels' 32-bit buffer offsets address;
     46340 is the largest L the interface accepts (L^2 < 2^31), on the streaming
-    plan.  Two sweeps, 600 sampled sites (corners and edges included) against the
-    oracle's light cones, the last record against a float64 recomputation."""
+    plan; FP16 storage on the largest tiled lattice.  Two sweeps, 600 sampled
+    sites (corners and edges included) against the oracle's light cones, the last
+    record against a float64 recomputation."""
     beta, delta = 1.0, 1.2
-    lat = xy.Lattice(L, seed=1, beta=beta, delta=delta, plan=plan)
+    lat = xy.Lattice(L, seed=1, beta=beta, delta=delta, plan=plan, precision=prec)
     assert lat.plan == plan
     obs = lat.sweep(2, 1)
     recs = xy.records(obs)
@@ -343,7 +345,7 @@ def test_maximum_sizes_sampled_sites(orc, L, plan):
     memo = {}
     checked = 0
     for i, (x, y) in enumerate(pts):
-        v, marg = _light_cone_value(orc, 1, L, beta, delta, x, y, 2, memo)
+        v, marg = _light_cone_value(orc, 1, L, beta, delta, x, y, 2, memo, OPREC[prec])
         if marg < EXEMPT:
             continue
         assert g[i] == v, (L, x, y, g[i], v)
