@@ -322,12 +322,13 @@ def _records_by_row_chunks(state, L, rows=1024):
 
 
 @pytest.mark.parametrize("L,plan,prec", [(32704, (2, 64, 16, 1), "fp32"), (32640, (3, 128, 64, 1), "fp32"),
-                                         (46340, STREAM, "fp32"), (32704, (2, 64, 16, 1), "fp16")])
+                                         (46340, STREAM, "fp32"), (32704, (2, 64, 16, 1), "fp16"),
+                                         (46340, STREAM, "fp16")])
 def test_maximum_sizes_sampled_sites(orc, L, plan, prec):
     """The largest lattices: 32704 and 32640 keep 4 L^2 bytes of state just below
     the 4 GiB that the tile and strip kernels' 32-bit buffer offsets address;
     46340 is the largest L the interface accepts (L^2 < 2^31), on the streaming
-    plan; FP16 storage on the largest tiled lattice.  Two sweeps, 600 sampled
+    plan; FP16 storage on both.  Two sweeps, 600 sampled
     sites (corners and edges included) against the oracle's light cones, the last
     record against a float64 recomputation."""
     beta, delta = 1.0, 1.2
