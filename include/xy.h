@@ -72,6 +72,7 @@ extern "C" {
 #define XY_ENOMEM (-6)  /* host allocation of a handle failed */
 #define XY_EBARRIER (-7) /* a batch barrier wait hit its spin limit: the GPU did not hold every
                             workgroup of the persistent launch at once; results are invalid */
+#define XY_EIO    (-8)  /* a file (the tune cache) could not be written */
 
 enum { XY_FP32 = 0, XY_FP16 = 1 };
 enum { XY_HOT = 0, XY_COLD = 1 };
@@ -124,36 +125,63 @@ typedef struct xy_batch xy_batch;
 
 /* Bytes of device memory a lattice needs: *state for the angles (layout above),
  * *workspace for the ping-pong copy and the reduction partials.  Either output
- * pointer may be NULL. */
+ * pointer may be NULL.  The lattice lives in device memory and is staged through
+ * on-chip memory tile by tile (section 2.2).
+ * XY_EINVAL: L odd, L < 4, L^2 >= 2^31, or a bad precision. */
 int xy_state_bytes(int32_t L, int32_t precision, size_t* state, size_t* workspace);
 
-/* Create a lattice on the caller's stream (hipStream_t passed as void*, NULL =
- * the null stream) and initialise the angles: XY_HOT draws phi = u from the
- * purpose-1 stream (exact in FP32; FP16 storage rounds it once), XY_COLD sets
- * phi = 0.  The sweep counter starts at 0.
- * beta >= 0 finite; 0 < delta <= pi. */
+/* Create a lattice of the model of section 1.2, eq. 1 on the caller's stream
+ * (hipStream_t passed as void*, NULL = the null stream) and initialise the
+ * angles: XY_HOT draws phi = u from the purpose-1 stream (exact in FP32; FP16
+ * storage rounds it once), XY_COLD sets phi = 0.  The sweep counter starts at 0.
+ * beta >= 0 finite (the weight exp(-beta H)); 0 < delta <= pi.
+ * state_dev: xy_state_bytes' *state bytes, layout above; work_dev: its
+ * *workspace bytes, contents owned by the library while the handle lives.
+ * Both are caller-owned device memory and must outlive the handle.
+ * XY_EINVAL: bad L, beta, delta, start or precision; XY_ESTATE: out, state_dev
+ * or work_dev NULL; XY_ESIZE: a buffer too short; XY_EHIP: the initialising
+ * launch failed (no handle is returned). */
 int xy_init(xy_lattice** out, uint64_t seed, int32_t L, double beta, double delta,
             int32_t start, int32_t precision,
             void* state_dev, size_t state_len, void* work_dev, size_t work_len,
             void* hip_stream);
 
-/* Same as xy_init but keeps the angles already in state_dev (a checkpoint) and
- * sets the sweep counter to `sweep`. */
+/* Same as xy_init (section 1.2, eq. 1) but keeps the angles already in
+ * state_dev (a checkpoint) and sets the sweep counter to `sweep`.  Because the
+ * random numbers depend only on (seed, sweep, site), the continued trajectory
+ * is bit for bit the uninterrupted one.  XY_ERANGE: sweep >= 2^32 - 1; other
+ * codes as xy_init. */
 int xy_attach(xy_lattice** out, uint64_t seed, int32_t L, double beta, double delta,
               int32_t precision, uint64_t sweep,
               void* state_dev, size_t state_len, void* work_dev, size_t work_len,
               void* hip_stream);
 
-/* Run n_sweeps sweeps from the handle's sweep counter.  If measure_every > 0 and
- * obs_dev != NULL, after every sweep j (1-based within this call) with
- * j % measure_every == 0 one xy_obs is written to obs_dev[j / measure_every - 1]
- * (device memory, floor(n_sweeps / measure_every) records).  On return the
- * angles are in state_dev. */
+/* Run n_sweeps Metropolis sweeps of the ensemble exp(-beta H), H of section
+ * 1.2, eq. 1 (red sites, then black sites, the update in the preamble) from the
+ * handle's sweep counter.  If measure_every > 0 and obs_dev != NULL, after every
+ * sweep j (1-based within this call) with j % measure_every == 0 one xy_obs with
+ * the FP64 global sums of section 1.2 is written to
+ * obs_dev[j / measure_every - 1] (caller-owned device memory of
+ * floor(n_sweeps / measure_every) * 64 bytes; the library does not know its
+ * length).  On return (asynchronously, on the handle's stream) the angles are
+ * in state_dev.  XY_EINVAL: n_sweeps < 0 or measure_every < 0; XY_ERANGE: the
+ * counter would pass 2^32 - 1 (nothing is run); XY_EHIP: a launch failed (the
+ * counter then stands after the last sweep enqueued). */
 int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs_dev);
 
-/* Measure the current state into obs_dev[0] (device memory). */
+/* Measure the current state into obs_dev[0] (caller-owned device memory, 64
+ * bytes): the global sums of the energy (section 1.2, in FP64 as the paper
+ * keeps them), the bond sines of the helicity modulus and the magnetisation;
+ * n_accept = 0.  XY_ESTATE: obs_dev NULL; XY_EHIP: a launch failed. */
 int xy_measure(xy_lattice* h, xy_obs* obs_dev);
 
+/* Handle accessors.  xy_set_params: the (beta, delta) of the update of section
+ * 1.2 for later sweeps (XY_EINVAL as xy_init).  xy_get_sweep / xy_set_sweep: the
+ * sweep counter that keys the random numbers (XY_ERANGE for >= 2^32 - 1).
+ * xy_set_stream: later work goes to this stream.  xy_set_plan / xy_get_plan: the
+ * schedule (XY_EINVAL if the plan does not fit L).  xy_free: releases the host
+ * handle (never the caller's device memory).  XY_ESTATE for a NULL or freed
+ * handle or a NULL output pointer. */
 int xy_set_params(xy_lattice* h, double beta, double delta);
 int xy_get_sweep(const xy_lattice* h, uint64_t* sweep);
 int xy_set_sweep(xy_lattice* h, uint64_t sweep);
@@ -162,7 +190,10 @@ int xy_set_plan(xy_lattice* h, const xy_plan* plan);
 int xy_get_plan(const xy_lattice* h, xy_plan* plan);
 int xy_free(xy_lattice* h);
 
-/* Parallel tempering over a batch.  Lattices of equal L form a ladder (ladders in
+/* Parallel tempering over a batch: the replicas at different temperatures of
+ * section 3.2, which the paper keeps side by side, exchange temperatures
+ * (standard parallel tempering; the paper gives no exchange rule).  Lattices of
+ * equal L form a ladder (ladders in
  * order of L), its rungs ordered by the beta each lattice holds when the call
  * starts (ties by index); rung t keeps that (beta_t, delta_t).  Each of n_rounds
  * rounds runs sweeps_per_round sweeps of every lattice (the last one measured),
@@ -180,8 +211,8 @@ int xy_free(xy_lattice* h);
 int xy_batch_tempering(xy_batch* b, int64_t n_rounds, int32_t sweeps_per_round, uint64_t pt_seed,
                        xy_obs* obs_dev, int32_t* rung_dev);
 
-/* The (beta, delta) each lattice of the batch currently runs at (host arrays of
- * n; either may be NULL). */
+/* The (beta, delta) each lattice of the batch currently runs at after the
+ * exchanges of section 3.2's replicas (host arrays of n; either may be NULL). */
 int xy_batch_get_params(const xy_batch* b, double* beta, double* delta);
 
 /* ------------------------------------------------ four-replica lattices
@@ -270,23 +301,42 @@ int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_wo
 int xy_hmc_set_steps_per_pass(xy_lattice* h, int32_t steps);
 int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
 
-/* Test support: run ONE sweep with the streaming schedule and write, per site in
- * the state layout (red half then black half), accept_dev[i] = 1/0 and dE_dev[i] =
- * the FP32 energy change of the proposal.  Either output may be NULL. */
+/* Profiling support: time the tiled sweep kernel launches (XY_PLAN_FUSED and
+ * XY_PLAN_STRIP; one launch per pass) of the handle's next calls with HIP events
+ * recorded on its stream right before and after each launch, for up to
+ * `capacity` launches (0 turns the timer off and frees its events; host objects
+ * only).  xy_kernel_timer_read waits for the last timed launch, returns the sum
+ * of their durations in ms and their number, and restarts the count.  The
+ * events order each timed launch after the work before it, so timed calls lose
+ * the little overlap between consecutive launches.  XY_EINVAL: capacity < 0. */
+int xy_kernel_timer(xy_lattice* h, int32_t capacity);
+int xy_kernel_timer_read(xy_lattice* h, double* total_ms, int64_t* launches);
+
+/* Test support: run ONE sweep (section 1.2, eq. 1; the update in the preamble)
+ * with the streaming schedule and write, per site in the state layout (red half
+ * then black half), accept_dev[i] = 1/0 and dE_dev[i] = the FP32 energy change of
+ * the proposal (caller-owned device buffers of L^2 entries).  Either output may
+ * be NULL.  XY_ERANGE: the counter would pass 2^32 - 1. */
 int xy_debug_sweep(xy_lattice* h, uint8_t* accept_dev, float* dE_dev);
 
 /* Time each candidate plan for `sweeps_per_trial` sweeps (after one untimed
  * trial) on the handle's stream and select the fastest; *best receives it and
- * the handle keeps it.  The trials advance the handle's state and counter: run
- * it on a scratch lattice.  If cache_path != NULL the result is merged into that
- * JSON file under the key "gfx950/L/precision". */
+ * the handle keeps it.  The plans differ in how sublattices are staged through
+ * on-chip memory with duplicated borders (section 2.2), never in the trajectory.
+ * The trials advance the handle's state and counter: run it on a scratch
+ * lattice.  If cache_path != NULL the result is merged into that JSON file under
+ * the key "gfx950/L/precision".  XY_EINVAL: sweeps_per_trial < 2; XY_EIO: the
+ * cache file could not be written (the handle still keeps the best plan). */
 int xy_autotune(xy_lattice* h, int32_t sweeps_per_trial, const char* cache_path, xy_plan* best);
 
-/* Look up a tuned plan for (L, precision) in the JSON cache file; XY_EINVAL if
- * the file or the entry is missing. */
+/* Look up a tuned plan for (L, precision) in the JSON cache file written by
+ * xy_autotune; XY_EINVAL if the file or the entry is missing. */
 int xy_tuned_plan(const char* cache_path, int32_t L, int32_t precision, xy_plan* plan);
 
 /* ----------------------------------------------------------------- batches
+ * Many lattices in one device launch, so that the device is "sufficiently
+ * filled" (section 3.2, where four replicas at different temperatures share one
+ * texture and the best performance came from the largest workload).
  * n lattices of sizes L[i] >= 4, L[i] % 4 == 0 (possibly different), with their own seed,
  * beta and delta, advanced together; the launches of one call are captured once
  * into a HIP graph and replayed.  Lattice i's angles start at element offset
@@ -302,14 +352,27 @@ int xy_tuned_plan(const char* cache_path, int32_t L, int32_t precision, xy_plan*
  *   XY_BATCH_PASSES_WIDE (default): the same, with 256 x 16 tiles for every
  *     lattice whose L is a multiple of 256 (the batch's shape for the others). */
 enum { XY_BATCH_PERSISTENT = 0, XY_BATCH_PASSES = 1, XY_BATCH_PASSES_WIDE = 2 };
+/* Device bytes of a batch (section 3.2's replicas, here of any sizes): *state =
+ * sum of the lattices' state bytes (lattices back to back), *workspace = the
+ * ping-pong copy, barrier counters, descriptors and partial sums.
+ * XY_EINVAL: n < 1, a bad L[i] or precision; XY_ESTATE: L NULL. */
 int xy_batch_state_bytes(int32_t n, const int32_t* L, int32_t precision,
                          size_t* state, size_t* workspace);
+/* Create a batch of n lattices of section 1.2's model (seeds, L, beta, delta:
+ * host arrays of n; the replicas at several temperatures of section 3.2) on the
+ * caller's stream and initialise every lattice as xy_init does.  Buffers are
+ * caller-owned device memory that must outlive the handle.  Error codes as
+ * xy_init, for any lattice. */
 int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_t* L,
                   const double* beta, const double* delta, int32_t start, int32_t precision,
                   void* state_dev, size_t state_len, void* work_dev, size_t work_len,
                   void* hip_stream);
-/* obs_dev: n * floor(n_sweeps / measure_every) records, lattice-major
- * (record r of lattice i at obs_dev[i * n_rec + r]). */
+/* Run n_sweeps sweeps (section 1.2, eq. 1; the update in the preamble) of every
+ * lattice of the batch.  obs_dev: NULL, or caller-owned device memory for
+ * n * floor(n_sweeps / measure_every) records (FP64 global sums of section
+ * 1.2), lattice-major (record r of lattice i at obs_dev[i * n_rec + r]).
+ * XY_EINVAL: n_sweeps < 0 or measure_every < 0; XY_ERANGE: the counter would
+ * pass 2^32 - 1; XY_EHIP: a launch or the graph failed. */
 int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs* obs_dev);
 int xy_batch_get_sweep(const xy_batch* b, uint64_t* sweep);
 /* Tile shape of the batch's work list (every L[i] is a multiple of it).  The
@@ -326,13 +389,31 @@ int xy_batch_get_schedule(const xy_batch* b, int32_t* schedule);
  * advance the batch: run it on a scratch batch of the same sizes. */
 int xy_batch_autotune(xy_batch* b, int32_t sweeps_per_trial, int32_t* tile_x, int32_t* tile_y);
 /* Wait for the batch's stream and report whether any launch so far hit a barrier
- * spin limit (XY_EBARRIER) -- a guard for GPUs shared with other work. */
+ * spin limit (XY_EBARRIER) -- a guard for GPUs shared with other work.  The flag
+ * is sticky: once set, the batch's later results are void as well. */
 int xy_batch_status(xy_batch* b);
+/* Test support (failure handling): the number of polls after which a barrier
+ * wait of the persistent schedule gives up (default 2^27, several seconds).
+ * After one wait has given up every later wait of the launch returns at once,
+ * so the grid drains and the kernel exits normally; xy_batch_status then
+ * reports XY_EBARRIER.  A limit of a few polls forces that path from the host.
+ * XY_EINVAL: polls == 0. */
+int xy_batch_set_spin_limit(xy_batch* b, uint32_t polls);
 int xy_batch_free(xy_batch* b);
 
 const char* xy_strerror(int code);
 /* Name of the last failing HIP call and its error string (thread-local). */
 const char* xy_last_hip_error(void);
+
+/* Test support (failure handling): arm one injected failure.  The (after + 1)-th
+ * launch point the library reaches from now on (a kernel launch of xy_init,
+ * xy_attach, xy_sweep, xy_measure, xy_hmc or a batch graph launch, in any
+ * thread) fails with hipErrorLaunchFailure without enqueueing anything, so the
+ * call returns XY_EHIP and xy_last_hip_error() ends in "[injected]".  The
+ * handle stays usable: its sweep counter counts exactly the sweeps that were
+ * enqueued and their angles are in the caller's state buffer, so a later call
+ * continues the same trajectory.  after = -1 disarms; XY_EINVAL below -1. */
+int xy_test_inject_failure(int32_t after);
 
 #ifdef __cplusplus
 }

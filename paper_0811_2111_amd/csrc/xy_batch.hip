@@ -66,25 +66,32 @@ constexpr int kBatchResidentMaxL = 32;
 
 struct Ctrl {
     uint32_t sweep0;      // absolute sweep index of the next pass (advanced by k_batch_advance)
-    uint32_t timed_out;   // set if a barrier wait gave up (never cleared by the kernel)
-    uint32_t pad[62];
+    uint32_t timed_out;   // set if a barrier wait gave up (sticky: the batch's results are void)
+    uint32_t spin_limit;  // polls before a barrier wait gives up
+    uint32_t pad[61];
 };
 
-// Spin limit of one barrier wait: 2^27 polls with s_sleep 2 (~128 cycles each),
-// several seconds at 2.4 GHz, far beyond any legitimate wait.  A wait that gives
-// up flags ctrl->timed_out and lets the workgroup run on, so every wave exits.
+// Default spin limit of one barrier wait: 2^27 polls with s_sleep 2 (~128
+// cycles each), several seconds at 2.4 GHz, far beyond any legitimate wait.
 static constexpr unsigned kSpinLimit = 1u << 27;
 
 // Barrier wait: thread 0 polls the counter with relaxed loads (no cache
 // maintenance per poll), then one agent-scope acquire fence makes the other
-// workgroups' writes visible before the workgroup reads them.
+// workgroups' writes visible before the workgroup reads them.  A wait that
+// reaches the spin limit flags ctrl->timed_out and lets the workgroup run on;
+// every wait, before and while it polls, leaves at once once that flag is set,
+// so after one wait has given up the whole grid drains without waiting again
+// (the sweeps then run on stale data, whose indices never depend on it, and
+// xy_batch_status reports XY_EBARRIER).
 __device__ __forceinline__ void wait_at_least(unsigned* ctr, unsigned target, Ctrl* ctrl)
 {
     if (threadIdx.x == 0) {
+        const unsigned limit = ctrl->spin_limit;
         unsigned spins = 0;
         while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(&ctrl->timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
             __builtin_amdgcn_s_sleep(2);
-            if (++spins == kSpinLimit) {
+            if (++spins >= limit) {
                 __hip_atomic_store(&ctrl->timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 break;
             }
@@ -365,7 +372,10 @@ __global__ void k_set_sweep(Ctrl* ctrl, uint32_t v)
 {
     ctrl->sweep0 = v;
     ctrl->timed_out = 0u;
+    ctrl->spin_limit = kSpinLimit;
 }
+
+__global__ void k_set_spin_limit(Ctrl* ctrl, uint32_t v) { ctrl->spin_limit = v; }
 
 }  // namespace xyb
 
@@ -379,6 +389,8 @@ struct Shape {
 // the small ones exist so that any batch of L % 4 == 0 lattices can run.
 static const Shape kShapes[] = {{64, 32}, {64, 16}, {32, 16}, {16, 16}, {8, 8}, {4, 4}};
 static constexpr int kNT = 256;
+// Longest per-sweep launch sequence captured in one graph (longer calls replay it).
+static constexpr int kMaxGraphPasses = 16384;
 
 static std::vector<Shape> candidates(int n, const int32_t* L)
 {
@@ -520,6 +532,7 @@ struct xy_batch {
     int64_t g_n;
     int32_t g_me;
     xy_obs* g_obs;
+    int g_nrec;
     int g_grid;
     int g_sched;
 };
@@ -644,7 +657,7 @@ static int plan_batch(xy_batch* b, Shape s)
     return XY_OK;
 }
 
-static hipError_t enqueue_batch(xy_batch* b, hipStream_t s, int npass, int32_t me, xy_obs* obs)
+static hipError_t enqueue_batch(xy_batch* b, hipStream_t s, int npass, int32_t me, xy_obs* obs, int nrec)
 {
     size_t lds = 0;
     void* k = batch_kernel(b->precision, b->shape, &lds);
@@ -652,7 +665,6 @@ static hipError_t enqueue_batch(xy_batch* b, hipStream_t s, int npass, int32_t m
     Ctrl* ctrl = (Ctrl*)(b->work + b->lo.ctrl_off);
     const LatDesc* desc = (const LatDesc*)(b->work + b->lo.desc_off);
     double* part = (double*)(b->work + b->lo.part_off);
-    const int nrec = me > 0 ? npass / me : 0;
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, bar, b->n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -668,12 +680,11 @@ static hipError_t enqueue_batch(xy_batch* b, hipStream_t s, int npass, int32_t m
 
 // Per-pass schedule: one launch per pass over all tiles, a record kernel after each
 // measured pass, a copy back for an odd pass count, then the sweep counter.
-static hipError_t enqueue_passes(xy_batch* b, hipStream_t s, int npass, int32_t me, xy_obs* obs)
+static hipError_t enqueue_passes(xy_batch* b, hipStream_t s, int npass, int32_t me, xy_obs* obs, int nrec)
 {
     Ctrl* ctrl = (Ctrl*)(b->work + b->lo.ctrl_off);
     const LatDesc* desc = (const LatDesc*)(b->work + b->lo.desc_off);
     double* part = (double*)(b->work + b->lo.part_off);
-    const int nrec = me > 0 ? npass / me : 0;
     void* pp = b->work + b->lo.pp_off;
     int nlat = b->n, tt = b->total_tiles;
     hipError_t e = hipSuccess;
@@ -778,6 +789,7 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->exec = nullptr;
     b->g_n = -1;
     b->g_me = -1;
+    b->g_nrec = -1;
     b->g_obs = nullptr;
     b->g_grid = 0;
     b->g_sched = -1;
@@ -817,36 +829,18 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     return XY_OK;
 }
 
-int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs* obs_dev)
+// One launch sequence of n sweeps (graph captured once per (n, records, stride,
+// grid, schedule) and replayed); records of lattice i at obs[i * nrec + r].
+static int batch_sweep_chunk(xy_batch* b, int n, int32_t me, xy_obs* obs, int nrec)
 {
-    if (!blive(b)) return XY_ESTATE;
-    if (n_sweeps < 0 || measure_every < 0) return XY_EINVAL;
-    if (b->sweep + (uint64_t)n_sweeps >= 0xffffffffull) return XY_ERANGE;
-    if (n_sweeps == 0) return XY_OK;
-    // barrier targets are pass * arrivals in 32 bits: split very long calls
-    int max_arr = 1;
-    for (const LatDesc& d : b->desc) max_arr = std::max(max_arr, d.arrivals);
-    const int64_t chunk = std::max<int64_t>(1, (int64_t)(0xffffffffu / (unsigned)max_arr) - 1);
-    if (n_sweeps > chunk) {
-        if (measure_every > 0 && obs_dev) return XY_EINVAL;  // records would be split across calls
-        for (int64_t done = 0; done < n_sweeps;) {
-            const int64_t m = std::min(chunk, n_sweeps - done);
-            int rc = xy_batch_sweep(b, m, 0, nullptr);
-            if (rc != XY_OK) return rc;
-            done += m;
-        }
-        return XY_OK;
-    }
-    const int32_t me = (obs_dev && measure_every > 0) ? measure_every : 0;
-    xy_obs* obs = me ? obs_dev : nullptr;
     hipError_t e;
-    if (!b->exec || b->g_n != n_sweeps || b->g_me != me || b->g_obs != obs || b->g_grid != b->grid ||
+    if (!b->exec || b->g_n != n || b->g_me != me || b->g_obs != obs || b->g_nrec != nrec || b->g_grid != b->grid ||
         b->g_sched != b->sched) {
         drop_graph(b);
         if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return xyr::hip_fail(e, "hipStreamBeginCapture");
-        hipError_t le = b->sched == XY_BATCH_PERSISTENT ? enqueue_batch(b, b->cap, (int)n_sweeps, me, obs)
-                                                        : enqueue_passes(b, b->cap, (int)n_sweeps, me, obs);
+        hipError_t le = b->sched == XY_BATCH_PERSISTENT ? enqueue_batch(b, b->cap, n, me, obs, nrec)
+                                                        : enqueue_passes(b, b->cap, n, me, obs, nrec);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess) {
@@ -860,14 +854,45 @@ int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs*
             drop_graph(b);
             return xyr::hip_fail(e, "hipGraphInstantiate");
         }
-        b->g_n = n_sweeps;
+        b->g_n = n;
         b->g_me = me;
         b->g_obs = obs;
+        b->g_nrec = nrec;
         b->g_grid = b->grid;
         b->g_sched = b->sched;
     }
-    if ((e = hipGraphLaunch(b->exec, b->stream)) != hipSuccess) return xyr::hip_fail(e, "hipGraphLaunch");
-    b->sweep += (uint64_t)n_sweeps;
+    if ((e = XY_LAUNCH(hipGraphLaunch(b->exec, b->stream))) != hipSuccess) return xyr::hip_fail(e, "hipGraphLaunch");
+    b->sweep += (uint64_t)n;
+    return XY_OK;
+}
+
+int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs* obs_dev)
+{
+    if (!blive(b)) return XY_ESTATE;
+    if (n_sweeps < 0 || measure_every < 0) return XY_EINVAL;
+    if (b->sweep + (uint64_t)n_sweeps >= 0xffffffffull) return XY_ERANGE;
+    if (n_sweeps == 0) return XY_OK;
+    const int32_t me = (obs_dev && measure_every > 0) ? measure_every : 0;
+    xy_obs* obs = me ? obs_dev : nullptr;
+    const int64_t nrec = me ? n_sweeps / me : 0;   // records per lattice: the stride of obs_dev
+    if (nrec > INT32_MAX) return XY_EINVAL;
+    // Split long calls: barrier targets are pass * arrivals in 32 bits and pass
+    // counts are ints (at most 2^30 sweeps per launch sequence), and the per-sweep
+    // schedules capture one launch per sweep (at most kMaxGraphPasses per graph).
+    // Chunks are multiples of measure_every, so the records of chunk c start at
+    // record done / measure_every of every lattice, with the call's stride.
+    int max_arr = 1;
+    for (const LatDesc& d : b->desc) max_arr = std::max(max_arr, d.arrivals);
+    int64_t cap = std::min<int64_t>((int64_t)1 << 30,
+                                    std::max<int64_t>(1, (int64_t)(0xffffffffu / (unsigned)max_arr) - 1));
+    if (b->sched != XY_BATCH_PERSISTENT) cap = std::min<int64_t>(cap, kMaxGraphPasses);
+    if (me) cap = std::max<int64_t>(cap / me, 1) * me;
+    for (int64_t done = 0; done < n_sweeps;) {
+        const int64_t m = std::min(cap, n_sweeps - done);
+        int rc = batch_sweep_chunk(b, (int)m, me, obs ? obs + done / me : nullptr, (int)nrec);
+        if (rc != XY_OK) return rc;
+        done += m;
+    }
     return XY_OK;
 }
 
@@ -1037,6 +1062,16 @@ int xy_batch_get_params(const xy_batch* b, double* beta, double* delta)
         if (beta) beta[i] = b->beta[i];
         if (delta) delta[i] = b->delta[i];
     }
+    return XY_OK;
+}
+
+int xy_batch_set_spin_limit(xy_batch* b, uint32_t polls)
+{
+    if (!blive(b)) return XY_ESTATE;
+    if (polls == 0) return XY_EINVAL;
+    hipLaunchKernelGGL(k_set_spin_limit, dim3(1), dim3(1), 0, b->stream, (Ctrl*)(b->work + b->lo.ctrl_off), polls);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return xyr::hip_fail(e, "xy_batch_set_spin_limit");
     return XY_OK;
 }
 

@@ -3,6 +3,7 @@
 // error mapping and the plan autotuner.  Batches live in xy_batch.hip.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -19,10 +20,28 @@
 namespace xyr {
 
 thread_local char g_hip_err[256] = "";
+// Launch points left before the injected failure (-1: none armed), and whether the
+// last failure on this thread was injected.
+static std::atomic<int> g_inject_countdown{-1};
+thread_local bool g_injected = false;
+
+bool inject_due()
+{
+    int v = g_inject_countdown.load(std::memory_order_relaxed);
+    while (v >= 0) {
+        if (g_inject_countdown.compare_exchange_weak(v, v - 1, std::memory_order_relaxed)) {
+            if (v == 0) g_injected = true;
+            return v == 0;
+        }
+    }
+    return false;
+}
 
 int hip_fail(hipError_t e, const char* what)
 {
-    snprintf(g_hip_err, sizeof(g_hip_err), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    snprintf(g_hip_err, sizeof(g_hip_err), "%s: %s (%d)%s", what, hipGetErrorString(e), (int)e,
+             g_injected ? " [injected]" : "");
+    g_injected = false;
     return XY_EHIP;
 }
 
@@ -167,6 +186,9 @@ struct xy_lattice {
     xy_plan plan;
     xyk::Work w;
     int32_t hmc_steps;     // leap-frog steps per pass of xy_hmc (1 .. 8)
+    // kernel timer (xy_kernel_timer): event pairs around the sweep kernel launches
+    hipEvent_t* tev;       // 2 * tcap events, or nullptr
+    int32_t tcap, tn;
 };
 
 static bool live(const xy_lattice* h) { return h && h->magic == kMagic; }
@@ -213,6 +235,8 @@ static int make_handle(xy_lattice** out, uint64_t seed, int32_t L, double beta, 
     h->stream = (hipStream_t)hip_stream;
     h->sweep = 0;
     h->hmc_steps = 5;
+    h->tev = nullptr;
+    h->tcap = h->tn = 0;
     h->w = xyk::carve(work_dev, L, precision);
     xy_plan p;
     if (!cache_lookup(env_cache_path(), L, precision, &p)) p = default_plan(L);
@@ -230,9 +254,9 @@ int xy_init(xy_lattice** out, uint64_t seed, int32_t L, double beta, double delt
     int rc = make_handle(out, seed, L, beta, delta, precision, state_dev, state_len, work_dev, work_len, hip_stream);
     if (rc != XY_OK) return rc;
     xy_lattice* h = *out;
-    hipError_t e = xyk::launch_init(h->state, L, precision, (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32),
-                                    start == XY_HOT, h->stream);
-    if (e == hipSuccess) e = xyk::launch_zero_u64(h->w.counter, 4, h->stream);
+    hipError_t e = XY_LAUNCH(xyk::launch_init(h->state, L, precision, (uint32_t)(seed & 0xffffffffu),
+                                              (uint32_t)(seed >> 32), start == XY_HOT, h->stream));
+    if (e == hipSuccess) e = XY_LAUNCH(xyk::launch_zero_u64(h->w.counter, 4, h->stream));
     if (e != hipSuccess) {
         h->magic = 0;
         delete h;
@@ -251,7 +275,7 @@ int xy_attach(xy_lattice** out, uint64_t seed, int32_t L, double beta, double de
     if (rc != XY_OK) return rc;
     xy_lattice* h = *out;
     h->sweep = sweep;
-    hipError_t e = xyk::launch_zero_u64(h->w.counter, 4, h->stream);
+    hipError_t e = XY_LAUNCH(xyk::launch_zero_u64(h->w.counter, 4, h->stream));
     if (e != hipSuccess) {
         h->magic = 0;
         delete h;
@@ -261,21 +285,37 @@ int xy_attach(xy_lattice** out, uint64_t seed, int32_t L, double beta, double de
     return XY_OK;
 }
 
+// One sweep in place by two half-sweep launches.  A failure of the first launch
+// leaves the state and counter as they were; a failure of the second leaves the
+// red half-sweep done, which is then finished so that state and counter agree.
 static int stream_sweep(xy_lattice* h, bool measured, xy_obs* rec, uint8_t* dbg_acc, float* dbg_dE)
 {
     xyk::SweepArgs a = args_of(h);
     unsigned long long* cnt = measured ? h->w.counter : nullptr;
-    hipError_t e = xyk::launch_half_sweep(a, 0, cnt, dbg_acc, dbg_dE, h->stream);
-    if (e == hipSuccess) e = xyk::launch_half_sweep(a, 1, cnt, dbg_acc, dbg_dE, h->stream);
+    hipError_t e = XY_LAUNCH(xyk::launch_half_sweep(a, 0, cnt, dbg_acc, dbg_dE, h->stream));
     if (e != hipSuccess) return hip_fail(e, "half-sweep launch");
+    e = XY_LAUNCH(xyk::launch_half_sweep(a, 1, cnt, dbg_acc, dbg_dE, h->stream));
+    if (e != hipSuccess) {
+        // finish the sweep; its record is lost, so its accepts are dropped too
+        const int rc = hip_fail(e, "half-sweep launch");
+        if (xyk::launch_half_sweep(a, 1, cnt, dbg_acc, dbg_dE, h->stream) == hipSuccess) h->sweep += 1;
+        if (cnt) (void)xyk::launch_zero_u64(h->w.counter, 4, h->stream);
+        return rc;
+    }
     h->sweep += 1;
     if (measured) {
         int np = 0;
-        e = xyk::launch_measure(h->state, h->L, h->precision, h->w.partials, h->w.max_partials, &np, h->stream);
+        e = XY_LAUNCH(xyk::launch_measure(h->state, h->L, h->precision, h->w.partials, h->w.max_partials, &np,
+                                          h->stream));
         if (e == hipSuccess)
-            e = xyk::launch_finalize(h->w.partials, np, h->w.counter, rec, h->sweep, h->stream, h->w.chunks,
-                                     h->w.arrive);
-        if (e != hipSuccess) return hip_fail(e, "measure launch");
+            e = XY_LAUNCH(xyk::launch_finalize(h->w.partials, np, h->w.counter, rec, h->sweep, h->stream,
+                                               h->w.chunks, h->w.arrive));
+        if (e != hipSuccess) {
+            // the record is lost; its accepts must not leak into the next one
+            const int rc = hip_fail(e, "measure launch");
+            (void)xyk::launch_zero_u64(h->w.counter, 4, h->stream);
+            return rc;
+        }
     }
     return XY_OK;
 }
@@ -304,8 +344,9 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
         for (int64_t done = 0; done < n_sweeps;) {
             const int64_t m = std::min<int64_t>(cap, n_sweeps - done);
             xyk::SweepArgs a = args_of(h);
-            hipError_t e = xyk::launch_resident(a, (int)m, meas ? measure_every : 0,
-                                                meas ? obs_dev + done / measure_every : nullptr, h->stream);
+            hipError_t e = XY_LAUNCH(xyk::launch_resident(a, (int)m, meas ? measure_every : 0,
+                                                          meas ? obs_dev + done / measure_every : nullptr,
+                                                          h->stream));
             if (e != hipSuccess) return hip_fail(e, "resident sweep launch");
             h->sweep += (uint64_t)m;
             done += m;
@@ -315,7 +356,10 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
 
     // Fused schedule: an even number of ping-pong passes (state -> pingpong ->
     // state ...), so the angles end in the caller's buffer; the remaining sweeps
-    // run in place with the streaming schedule (same trajectory).
+    // run in place with the streaming schedule (same trajectory).  If a launch
+    // fails after an odd number of passes, the latest angles are copied back from
+    // the ping-pong buffer, so the state and the counter (the sweeps enqueued)
+    // always agree and the handle stays usable.
     const bool strip = h->plan.kind == XY_PLAN_STRIP;
     const int m = strip ? 1 : h->plan.sweeps_per_pass;
     int64_t passes = n_sweeps / m;
@@ -323,6 +367,14 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
     const int nrec = strip ? xyk::strip_records(h->L, h->plan.tile_x, h->plan.tile_y)
                            : xyk::fused_records(h->L, h->plan.tile_x, h->plan.tile_y, m);
     int64_t j = 0;  // sweeps done in this call
+    int64_t done_passes = 0;
+    auto fail = [&](hipError_t e, const char* what) {
+        const int rc = hip_fail(e, what);
+        if (done_passes & 1)
+            (void)hipMemcpyAsync(h->state, h->w.pingpong, xyk::state_bytes(h->L, h->precision),
+                                 hipMemcpyDeviceToDevice, h->stream);
+        return rc;
+    };
     for (int64_t q = 0; q < passes; ++q) {
         xyk::SweepArgs a = args_of(h);
         a.src = (q & 1) ? h->w.pingpong : h->state;
@@ -330,18 +382,25 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
         unsigned mask = 0;
         for (int js = 0; js < m; ++js)
             if (measured(j + js + 1)) mask |= 1u << js;
-        hipError_t e = strip ? xyk::launch_strip(a, h->plan.tile_x, h->plan.tile_y, mask != 0, h->w.partials,
-                                                 h->stream)
-                             : xyk::launch_fused(a, h->plan.tile_x, h->plan.tile_y, m, mask, h->w.partials, h->stream);
-        if (e != hipSuccess) return hip_fail(e, "fused sweep launch");
-        for (int js = 0; js < m; ++js) {
-            if (!(mask & (1u << js))) continue;
-            e = xyk::launch_finalize(h->w.partials + (size_t)js * nrec * 8, nrec, nullptr,
-                                     rec_of(j + js + 1), h->sweep + js + 1, h->stream, h->w.chunks, h->w.arrive);
-            if (e != hipSuccess) return hip_fail(e, "finalize launch");
-        }
+        const bool timing = h->tn < h->tcap;
+        if (timing) (void)hipEventRecord(h->tev[2 * h->tn], h->stream);
+        hipError_t e = XY_LAUNCH(strip ? xyk::launch_strip(a, h->plan.tile_x, h->plan.tile_y, mask != 0,
+                                                           h->w.partials, h->stream)
+                                       : xyk::launch_fused(a, h->plan.tile_x, h->plan.tile_y, m, mask,
+                                                           h->w.partials, h->stream));
+        if (e != hipSuccess) return fail(e, "fused sweep launch");
+        if (timing) (void)hipEventRecord(h->tev[2 * h->tn++ + 1], h->stream);
+        done_passes = q + 1;
+        const uint64_t s0 = h->sweep;
         h->sweep += m;
         j += m;
+        for (int js = 0; js < m; ++js) {
+            if (!(mask & (1u << js))) continue;
+            e = XY_LAUNCH(xyk::launch_finalize(h->w.partials + (size_t)js * nrec * 8, nrec, nullptr,
+                                               rec_of(j - m + js + 1), s0 + js + 1, h->stream, h->w.chunks,
+                                               h->w.arrive));
+            if (e != hipSuccess) return fail(e, "finalize launch");
+        }
     }
     for (; j < n_sweeps; ++j) {
         int rc = stream_sweep(h, measured(j + 1), measured(j + 1) ? rec_of(j + 1) : nullptr, nullptr, nullptr);
@@ -355,9 +414,11 @@ int xy_measure(xy_lattice* h, xy_obs* obs_dev)
     if (!live(h)) return XY_ESTATE;
     if (!obs_dev) return XY_ESTATE;
     int np = 0;
-    hipError_t e = xyk::launch_measure(h->state, h->L, h->precision, h->w.partials, h->w.max_partials, &np, h->stream);
+    hipError_t e = XY_LAUNCH(
+        xyk::launch_measure(h->state, h->L, h->precision, h->w.partials, h->w.max_partials, &np, h->stream));
     if (e == hipSuccess)
-        e = xyk::launch_finalize(h->w.partials, np, nullptr, obs_dev, h->sweep, h->stream, h->w.chunks, h->w.arrive);
+        e = XY_LAUNCH(xyk::launch_finalize(h->w.partials, np, nullptr, obs_dev, h->sweep, h->stream, h->w.chunks,
+                                           h->w.arrive));
     if (e != hipSuccess) return hip_fail(e, "measure launch");
     return XY_OK;
 }
@@ -380,9 +441,9 @@ int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_wo
     const xyk::HmcWork w = xyk::hmc_carve(hmc_work, h->L);
     const uint32_t k0 = (uint32_t)(h->seed & 0xffffffffu), k1 = (uint32_t)(h->seed >> 32);
     for (int64_t j = 0; j < n_traj; ++j) {
-        hipError_t e = xyk::launch_hmc_trajectory((float*)h->state, (float*)h->w.pingpong, w, h->L, h->beta, eps,
-                                                  n_md, h->hmc_steps, (uint32_t)h->sweep, k0, k1,
-                                                  obs_dev ? obs_dev + j : nullptr, h->stream);
+        hipError_t e = XY_LAUNCH(xyk::launch_hmc_trajectory((float*)h->state, (float*)h->w.pingpong, w, h->L,
+                                                            h->beta, eps, n_md, h->hmc_steps, (uint32_t)h->sweep,
+                                                            k0, k1, obs_dev ? obs_dev + j : nullptr, h->stream));
         if (e != hipSuccess) return hip_fail(e, "hmc trajectory launch");
         h->sweep += 1;
     }
@@ -454,11 +515,63 @@ int xy_get_plan(const xy_lattice* h, xy_plan* plan)
     return XY_OK;
 }
 
+static void drop_timer(xy_lattice* h)
+{
+    if (h->tev) {
+        for (int i = 0; i < 2 * h->tcap; ++i)
+            if (h->tev[i]) (void)hipEventDestroy(h->tev[i]);
+        delete[] h->tev;
+    }
+    h->tev = nullptr;
+    h->tcap = h->tn = 0;
+}
+
 int xy_free(xy_lattice* h)
 {
     if (!live(h)) return XY_ESTATE;
+    drop_timer(h);
     h->magic = 0;
     delete h;
+    return XY_OK;
+}
+
+int xy_kernel_timer(xy_lattice* h, int32_t capacity)
+{
+    if (!live(h)) return XY_ESTATE;
+    if (capacity < 0) return XY_EINVAL;
+    drop_timer(h);
+    if (capacity == 0) return XY_OK;
+    h->tev = new (std::nothrow) hipEvent_t[2 * (size_t)capacity]();
+    if (!h->tev) return XY_ENOMEM;
+    h->tcap = capacity;
+    for (int i = 0; i < 2 * capacity; ++i) {
+        hipError_t e = hipEventCreate(&h->tev[i]);
+        if (e != hipSuccess) {
+            h->tev[i] = nullptr;
+            drop_timer(h);
+            return hip_fail(e, "xy_kernel_timer: hipEventCreate");
+        }
+    }
+    return XY_OK;
+}
+
+int xy_kernel_timer_read(xy_lattice* h, double* total_ms, int64_t* launches)
+{
+    if (!live(h) || !total_ms || !launches) return XY_ESTATE;
+    double t = 0.0;
+    if (h->tn > 0) {
+        hipError_t e = hipEventSynchronize(h->tev[2 * h->tn - 1]);
+        if (e != hipSuccess) return hip_fail(e, "xy_kernel_timer_read: hipEventSynchronize");
+        for (int i = 0; i < h->tn; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, h->tev[2 * i], h->tev[2 * i + 1]);
+            if (e != hipSuccess) return hip_fail(e, "xy_kernel_timer_read: hipEventElapsedTime");
+            t += ms;
+        }
+    }
+    *total_ms = t;
+    *launches = h->tn;
+    h->tn = 0;
     return XY_OK;
 }
 
@@ -524,7 +637,7 @@ int xy_autotune(xy_lattice* h, int32_t sweeps_per_trial, const char* cache_path,
     if (best) *best = best_p;
     if (cache_path) {
         const double gupd = (double)h->L * h->L * sweeps_per_trial / (best_t * 1e-3) / 1e9;
-        if (!cache_store(cache_path, h->L, h->precision, best_p, gupd)) return XY_EINVAL;
+        if (!cache_store(cache_path, h->L, h->precision, best_p, gupd)) return XY_EIO;
     }
     return XY_OK;
 }
@@ -547,10 +660,18 @@ const char* xy_strerror(int code)
     case XY_ESTATE: return "invalid or freed handle / missing pointer";
     case XY_ENOMEM: return "host allocation failed";
     case XY_EBARRIER: return "batch barrier wait exceeded its spin limit";
+    case XY_EIO: return "file could not be written";
     default: return "unknown error";
     }
 }
 
 const char* xy_last_hip_error(void) { return g_hip_err; }
+
+int xy_test_inject_failure(int32_t after)
+{
+    if (after < -1) return XY_EINVAL;
+    g_inject_countdown.store(after, std::memory_order_relaxed);
+    return XY_OK;
+}
 
 }  // extern "C"

@@ -22,7 +22,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libxyhip.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "xy.h")
 
-XY_OK, XY_EINVAL, XY_ESIZE, XY_ERANGE, XY_EHIP, XY_ESTATE, XY_ENOMEM, XY_EBARRIER = 0, -1, -2, -3, -4, -5, -6, -7
+XY_OK, XY_EINVAL, XY_ESIZE, XY_ERANGE, XY_EHIP, XY_ESTATE, XY_ENOMEM, XY_EBARRIER, XY_EIO = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
 XY_FP32, XY_FP16 = 0, 1
 XY_HOT, XY_COLD = 0, 1
 XY_PLAN_AUTO, XY_PLAN_STREAM, XY_PLAN_FUSED, XY_PLAN_STRIP, XY_PLAN_RESIDENT = 0, 1, 2, 3, 4
@@ -114,6 +115,10 @@ def _load():
         "xy_quad_get_tile": [vp, P(i32), P(i32)],
         "xy_quad_free": [vp],
         "xy_hmc": [vp, i64, i32, dbl, vp, sz, vp],
+        "xy_batch_set_spin_limit": [vp, ctypes.c_uint32],
+        "xy_test_inject_failure": [i32],
+        "xy_kernel_timer": [vp, i32],
+        "xy_kernel_timer_read": [vp, P(dbl), P(i64)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -138,6 +143,11 @@ def header_functions():
     with open(HEADER) as f:
         text = f.read()
     return sorted(set(re.findall(r"^(?:int|const char\*)\s+(xy_\w+)\s*\(", text, flags=re.M)))
+
+
+def xy_test_inject_failure(after: int):
+    """Test support: the (after + 1)-th launch point from now fails with XY_EHIP."""
+    check(_lib.xy_test_inject_failure(int(after)), "xy_test_inject_failure")
 
 
 def check(rc: int, what: str):
@@ -195,6 +205,19 @@ def _nbytes(t):
     return t.numel() * t.element_size()
 
 
+def _check_out(out, nbytes: int, device, what: str, dtype=None):
+    """The C ABI writes `nbytes` of records through `out` with no length argument:
+    refuse a tensor that is not a contiguous float64 device tensor of at least that
+    size on the lattice's device, before any device write can run past its end."""
+    import torch
+    dtype = dtype or torch.float64
+    if out.dtype != dtype or not out.is_contiguous() or out.device != torch.device(device):
+        raise ValueError("%s: out must be a contiguous %s tensor on %s (got %s, %s, contiguous=%s)"
+                         % (what, dtype, device, out.dtype, out.device, out.is_contiguous()))
+    if _nbytes(out) < nbytes:
+        raise ValueError("%s: out holds %d bytes, the call writes %d" % (what, _nbytes(out), nbytes))
+
+
 class Lattice:
     """One L x L lattice: angles and workspace in torch device tensors, sweeps in HIP.
 
@@ -241,6 +264,8 @@ class Lattice:
         nrec = n // measure_every if measure_every > 0 else 0
         if nrec and out is None:
             out = torch.empty((nrec, 8), dtype=torch.float64, device=self.state.device)
+        if nrec:
+            _check_out(out, nrec * 64, self.state.device, "xy_sweep")
         rc = _lib.xy_sweep(self.h, int(n), int(measure_every), _ptr(out) if nrec else None)
         check(rc, "xy_sweep")
         return out
@@ -263,6 +288,8 @@ class Lattice:
             self.hmc_work = torch.empty((xy_hmc_work_bytes(self.L),), dtype=torch.uint8, device=self.state.device)
         if out is None:
             out = torch.empty((max(int(n_traj), 1), 9), dtype=torch.float64, device=self.state.device)
+        if n_traj > 0:
+            _check_out(out, int(n_traj) * 72, self.state.device, "xy_hmc")
         rc = _lib.xy_hmc(self.h, int(n_traj), int(n_md), float(eps), _ptr(self.hmc_work), _nbytes(self.hmc_work),
                          _ptr(out) if n_traj > 0 else None)
         check(rc, "xy_hmc")
@@ -272,6 +299,7 @@ class Lattice:
         import torch
         if out is None:
             out = torch.empty((1, 8), dtype=torch.float64, device=self.state.device)
+        _check_out(out, 64, self.state.device, "xy_measure")
         check(_lib.xy_measure(self.h, _ptr(out)), "xy_measure")
         return out
 
@@ -304,6 +332,16 @@ class Lattice:
         p = xy_plan()
         check(_lib.xy_get_plan(self.h, ctypes.byref(p)), "xy_get_plan")
         return p.as_tuple()
+
+    def kernel_timer(self, capacity: int):
+        """Time the next `capacity` tiled sweep launches with HIP events (0: off)."""
+        check(_lib.xy_kernel_timer(self.h, int(capacity)), "xy_kernel_timer")
+
+    def kernel_timer_read(self):
+        """(total ms, launches) of the launches timed since the last read."""
+        t, n = ctypes.c_double(), ctypes.c_int64()
+        check(_lib.xy_kernel_timer_read(self.h, ctypes.byref(t), ctypes.byref(n)), "xy_kernel_timer_read")
+        return t.value, n.value
 
     def autotune(self, sweeps_per_trial: int = 4, cache_path=None):
         p = xy_plan()
@@ -350,6 +388,9 @@ class Batch:
             out = torch.empty((max(int(n_rounds), 1), n, 8), dtype=torch.float64, device=self.state.device)
         if rungs is None:
             rungs = torch.empty((max(int(n_rounds), 1), n), dtype=torch.int32, device=self.state.device)
+        if n_rounds > 0:
+            _check_out(out, int(n_rounds) * n * 64, self.state.device, "xy_batch_tempering")
+            _check_out(rungs, int(n_rounds) * n * 4, self.state.device, "xy_batch_tempering", torch.int32)
         check(_lib.xy_batch_tempering(self.h, int(n_rounds), int(sweeps_per_round), int(pt_seed), _ptr(out),
                                       _ptr(rungs)), "xy_batch_tempering")
         return out[: int(n_rounds)], rungs[: int(n_rounds)]
@@ -369,6 +410,8 @@ class Batch:
         nrec = n // measure_every if measure_every > 0 else 0
         if nrec and out is None:
             out = torch.empty((len(self.Ls), nrec, 8), dtype=torch.float64, device=self.state.device)
+        if nrec:
+            _check_out(out, len(self.Ls) * nrec * 64, self.state.device, "xy_batch_sweep")
         check(_lib.xy_batch_sweep(self.h, int(n), int(measure_every), _ptr(out) if nrec else None),
               "xy_batch_sweep")
         return out
@@ -382,6 +425,10 @@ class Batch:
     def status(self):
         """Synchronise and raise if any persistent launch hit a barrier spin limit."""
         check(_lib.xy_batch_status(self.h), "xy_batch_status")
+
+    def set_spin_limit(self, polls: int):
+        """Test support: polls before a persistent barrier wait gives up."""
+        check(_lib.xy_batch_set_spin_limit(self.h, int(polls)), "xy_batch_set_spin_limit")
 
     @property
     def tile(self):
@@ -448,6 +495,8 @@ class Quad:
         nrec = n // measure_every if measure_every > 0 else 0
         if nrec and out is None:
             out = torch.empty((nrec, 4, 8), dtype=torch.float64, device=self.state.device)
+        if nrec:
+            _check_out(out, nrec * 4 * 64, self.state.device, "xy_quad_sweep")
         check(_lib.xy_quad_sweep(self.h, int(n), int(measure_every), _ptr(out) if nrec else None), "xy_quad_sweep")
         return out
 

@@ -208,3 +208,33 @@ def test_steps_per_pass_settings():
     assert L_.xy_hmc_set_steps_per_pass(lat64.h, 0) == xy.XY_EINVAL
     assert L_.xy_hmc_set_steps_per_pass(lat64.h, 9) == xy.XY_EINVAL
     assert L_.xy_hmc_set_steps_per_pass(None, 2) == xy.XY_ESTATE
+
+
+def test_trajectory_at_high_seed_and_counter(orc):
+    """A 64-bit seed and trajectory counters 2^32 - 4 and 2^32 - 3 (resumed
+    through xy_attach): the momenta and accept numbers come from the top of the
+    Philox counter range with both key words in use; dH, decision and observables
+    against the oracle, as in the low-counter trajectories."""
+    L, seed, beta, eps, n = 32, 0x9E3779B97F4A7C15, 1.0, 0.1, 10
+    t0 = 2 ** 32 - 4
+    phi = orc.hot_start(seed, L, "f32")
+    start = xy.Lattice(L, seed=seed, beta=beta)
+    np.testing.assert_array_equal(natural(start.state), phi)
+    lat = xy.Lattice(L, seed=seed, beta=beta, state=start.state.clone(), sweep=t0)
+    rec = xy.hmc_records(lat.hmc(2, n, eps))
+    for t in range(2):
+        acc, dH, _ = orc.hmc_trajectory(seed, phi, beta, eps, n, t0 + t)
+        assert abs(float(rec["dH"][t]) - dH) < 1e-4 + 1e-5 * abs(dH), (t, float(rec["dH"][t]), dH)
+        u = orc.hmc_accept_uniform(seed, t0 + t)
+        if abs(math.exp(-dH) - u) < DECISION_EXEMPT:
+            return
+        assert bool(rec["accepted"][t]) == acc
+        assert int(rec["traj"][t]) == t0 + t + 1
+    assert np.max(turn_dist(natural(lat.state), phi)) < 1e-5
+    m = orc.measure(natural(lat.state))
+    for name, ref in zip(["cx", "cy", "ix", "iy", "mx", "my"], m):
+        assert abs(float(rec[name][1]) - ref) <= obs_tol(ref, L * L), name
+    assert lat.sweep_count == t0 + 2
+    with pytest.raises(xy.XYError) as ei:
+        lat.hmc(1, n, eps)
+    assert ei.value.code == xy.XY_ERANGE

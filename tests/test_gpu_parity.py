@@ -68,15 +68,16 @@ def check_record(rec, m_ref, acc_ref, N, sweep_ref):
         assert abs(float(rec[name]) - ref) <= obs_tol(ref, N), (name, float(rec[name]), ref)
 
 
-def follow(orc, lat, seed, beta, delta, n_calls, per_call, prec="fp32"):
-    """Advance device and oracle together, `per_call` sweeps per xy_sweep call,
-    comparing the stored state after every call and every measured record until
-    the first allowed divergence.  Returns the sweep index where it happened (or None)."""
+def follow(orc, lat, seed, beta, delta, n_calls, per_call, prec="fp32", s0=0):
+    """Advance device and oracle together from the hot start of `seed` and sweep
+    counter s0, `per_call` sweeps per xy_sweep call, comparing the stored state
+    after every call and every measured record until the first allowed
+    divergence.  Returns the sweep index where it happened (or None)."""
     L = lat.L
     N = L * L
     th = orc.hot_start(seed, L, OPREC[prec])
     np.testing.assert_array_equal(dev_natural(lat), th)
-    s = 0
+    s = s0
     for _ in range(n_calls):
         obs = lat.sweep(per_call, 1)
         recs = xy.records(obs)
@@ -249,11 +250,15 @@ def _light_cone_value(orc, seed, L, beta, delta, x, y, s, memo, prec="f32"):
     return v
 
 
-@pytest.mark.parametrize("L,beta,delta,plan", [(4096, 1.12, 1.0, (2, 256, 16, 1)), (16384, 1.0, 1.2, (2, 128, 32, 1)),
-                                                (16384, 1.0, 1.2, (3, 256, 64, 1)),
-                                                (16384, 1.0, 1.2, (3, 256, 128, 1))])
+FULL_SIZE_CASES = [(4096, 1.12, 1.0, (2, 256, 16, 1))] + \
+    [(16384, 1.0, 1.2, p) for p in [STREAM] + fused_plans(16384) + strip_plans(16384)]
+
+
+@pytest.mark.parametrize("L,beta,delta,plan", FULL_SIZE_CASES)
 def test_full_size_sampled_sites(orc, L, beta, delta, plan):
-    """At the benchmark sizes, with the plans the benchmark's autotuner picks among:
+    """At the benchmark sizes, with every plan the autotuner picks among at
+    L = 16384 (streaming, every fused tile, every strip segment, the XCD band
+    remap of the 512-wide strips included):
     two sweeps on the device, then 1500 sampled sites (edges included) against the
     oracle's site-by-site evaluation of their light cones; the two FP64 records
     against a float64 recomputation from the device state."""
@@ -589,3 +594,36 @@ def test_resident_long_call_and_records():
         np.testing.assert_allclose(ra[f], rb[f], rtol=0, atol=1e-7 * 32 * 32)
     r2 = xy.records(a.sweep(14, 7))
     assert list(r2["sweep"]) == [1007, 1014]
+
+
+# ------------------------------------------------- edges of the random stream
+
+SEED_HI = 0x9E3779B97F4A7C15          # key word 1 = seed >> 32 is non-zero
+S_HI = 2 ** 32 - 40                    # sweep counters up to 2^32 - 2, the last one allowed
+
+EDGE_PLANS = [(64, STREAM), (256, (2, 128, 32, 1)), (256, (2, 64, 32, 2)), (256, (2, 256, 16, 1)),
+              (256, (3, 128, 32, 1)), (512, (3, 512, 64, 1)), (32, RESIDENT)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("L,plan", EDGE_PLANS)
+def test_high_seed_and_counter_trajectory(orc, L, plan, prec):
+    """A seed of 64 bits (the key's high word in use) and sweep counters from
+    2^32 - 40 to 2^32 - 2 (Philox counter word 0 near its top; the device adds
+    round constants to both key words): the hot start, then 38 sweeps resumed
+    through xy_attach at the high counter, state and every record against the
+    oracle on every plan, FP32 and FP16 storage.  One more sweep would pass the
+    32-bit counter: XY_ERANGE, with the handle unchanged."""
+    start = xy.Lattice(L, seed=SEED_HI, precision=prec)
+    np.testing.assert_array_equal(dev_natural(start), orc.hot_start(SEED_HI, L, OPREC[prec]))
+    lat = xy.Lattice(L, seed=SEED_HI, beta=1.0, delta=1.0, precision=prec, state=start.state.clone(), sweep=S_HI,
+                     plan=plan)
+    assert lat.sweep_count == S_HI
+    div = follow(orc, lat, SEED_HI, 1.0, 1.0, 19, 2, prec, s0=S_HI)
+    if div is None:
+        assert lat.sweep_count == 2 ** 32 - 2
+        before = lat.state.clone()
+        with pytest.raises(xy.XYError) as ei:
+            lat.sweep(1)
+        assert ei.value.code == xy.XY_ERANGE
+        assert torch.equal(lat.state, before) and lat.sweep_count == 2 ** 32 - 2

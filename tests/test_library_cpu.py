@@ -109,7 +109,7 @@ def test_batch_validation_codes():
 
 
 def test_strerror_covers_codes():
-    for c in [0, -1, -2, -3, -4, -5, -6, -7]:
+    for c in [0, -1, -2, -3, -4, -5, -6, -7, -8]:
         assert L_.xy_strerror(c)
     assert L_.xy_strerror(-99) == b"unknown error"
 
@@ -154,3 +154,20 @@ def test_hmc_validation_without_gpu():
     s = ctypes.c_size_t()
     assert L_.xy_hmc_work_bytes(5, ctypes.byref(s)) == xy.XY_EINVAL
     assert L_.xy_hmc(None, 1, 1, 0.1, None, 0, None) == xy.XY_ESTATE
+
+
+def test_injected_failure_reported_before_any_device_work():
+    """An armed injected failure makes the next launch point fail with XY_EHIP and
+    a message that names the injection; nothing reaches the HIP runtime, so this
+    holds with or without a GPU.  The hook then disarms itself."""
+    assert L_.xy_test_inject_failure(-2) == xy.XY_EINVAL
+    assert L_.xy_test_inject_failure(0) == xy.XY_OK
+    rc, h = _init()
+    assert rc == xy.XY_EHIP
+    assert not h.value
+    assert L_.xy_last_hip_error().endswith(b"[injected]")
+    assert L_.xy_test_inject_failure(-1) == xy.XY_OK
+
+
+def test_strerror_io_code():
+    assert L_.xy_strerror(xy.XY_EIO) == b"file could not be written"
