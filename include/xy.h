@@ -401,6 +401,30 @@ int xy_batch_status(xy_batch* b);
 int xy_batch_set_spin_limit(xy_batch* b, uint32_t polls);
 int xy_batch_free(xy_batch* b);
 
+/* ------------------------------------------------ allocation-free entry point
+ * For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same as xy_attach(seed,
+ * L, beta, delta, precision, sweep, ...) followed by xy_sweep(n_sweeps,
+ * measure_every, obs_dev) and freeing the handle, with the same trajectory and
+ * records bit for bit, but with no caller workspace and no handle: the
+ * workspace is a fixed device array of XY_NOALLOC_SCRATCH_BYTES inside the
+ * library, one per device, held from module load until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree or host heap) and reads no file;
+ * it runs the default plan.  It enqueues its work on hip_stream and returns.
+ * state_dev (xy_state_bytes bytes, caller-owned) holds the angles in and out;
+ * obs_dev as in xy_sweep.  Every call on one device shares that device's array
+ * (the counters in it are cleared at the start of each call): calls that overlap
+ * in time on one device, from two streams or threads, race and give wrong
+ * results.  XY_ESIZE: the workspace of (L, precision) exceeds the array (FP32:
+ * L > 2432; FP16: L > 3342) or state_len is too small; XY_ERANGE: sweep +
+ * n_sweeps would pass 2^32 - 1; XY_EINVAL / XY_ESTATE as xy_attach and xy_sweep;
+ * XY_EHIP: the device address of the array could not be found or a launch
+ * failed. */
+#define XY_NOALLOC_SCRATCH_BYTES (24u << 20)
+int xy_sweep_noalloc(uint64_t seed, int32_t L, double beta, double delta, int32_t precision,
+                     uint64_t sweep, int64_t n_sweeps, int32_t measure_every, void* state_dev,
+                     size_t state_len, xy_obs* obs_dev, void* hip_stream);
+
 const char* xy_strerror(int code);
 /* Name of the last failing HIP call and its error string (thread-local). */
 const char* xy_last_hip_error(void);

@@ -649,6 +649,47 @@ int xy_tuned_plan(const char* cache_path, int32_t L, int32_t precision, xy_plan*
     return cache_lookup(cache_path, L, precision, plan) ? XY_OK : XY_EINVAL;
 }
 
+}  // extern "C"
+
+int xyr::sweep_on_work(uint64_t seed, int32_t L, double beta, double delta, int32_t precision, uint64_t sweep,
+                       int64_t n_sweeps, int32_t measure_every, void* state_dev, size_t state_len, void* work,
+                       size_t work_len, xy_obs* obs_dev, hipStream_t stream)
+{
+    if (!valid_L(L) || !valid_beta_delta(beta, delta) || (precision != XY_FP32 && precision != XY_FP16) ||
+        n_sweeps < 0 || measure_every < 0)
+        return XY_EINVAL;
+    if (!state_dev || !work) return XY_ESTATE;
+    if (state_len < xyk::state_bytes(L, precision) || work_len < xyk::work_bytes(L, precision)) return XY_ESIZE;
+    if (sweep >= 0xffffffffull || sweep + (uint64_t)n_sweeps >= 0xffffffffull) return XY_ERANGE;
+    xy_lattice h;
+    h.magic = kMagic;
+    h.seed = seed;
+    h.L = L;
+    h.precision = precision;
+    h.beta = beta;
+    h.delta = delta;
+    h.state = state_dev;
+    h.state_len = state_len;
+    h.work = work;
+    h.work_len = work_len;
+    h.stream = stream;
+    h.sweep = sweep;
+    h.hmc_steps = 5;
+    h.tev = nullptr;
+    h.tcap = h.tn = 0;
+    h.w = xyk::carve(work, L, precision);
+    h.plan = default_plan(L);
+    // the workspace keeps the previous call's contents: the accept and arrival
+    // counters must start at zero (a kernel, so the call may be graph-captured)
+    hipError_t e = XY_LAUNCH(xyk::launch_zero_u64(h.w.counter, 4, stream));
+    if (e != hipSuccess) return hip_fail(e, "zero counters");
+    const int rc = xy_sweep(&h, n_sweeps, measure_every, obs_dev);
+    h.magic = 0;
+    return rc;
+}
+
+extern "C" {
+
 const char* xy_strerror(int code)
 {
     switch (code) {

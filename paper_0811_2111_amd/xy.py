@@ -117,6 +117,7 @@ def _load():
         "xy_hmc": [vp, i64, i32, dbl, vp, sz, vp],
         "xy_batch_set_spin_limit": [vp, ctypes.c_uint32],
         "xy_test_inject_failure": [i32],
+        "xy_sweep_noalloc": [u64, i32, dbl, dbl, i32, u64, i64, i32, vp, sz, vp, vp],
         "xy_kernel_timer": [vp, i32],
         "xy_kernel_timer_read": [vp, P(dbl), P(i64)],
     }
@@ -143,6 +144,28 @@ def header_functions():
     with open(HEADER) as f:
         text = f.read()
     return sorted(set(re.findall(r"^(?:int|const char\*)\s+(xy_\w+)\s*\(", text, flags=re.M)))
+
+
+def xy_sweep_noalloc(seed: int, L: int, beta: float, delta: float, precision, sweep: int, n_sweeps: int,
+                     measure_every: int, state, out=None, stream=None):
+    """Allocation-free sweeps of the angles in `state` (a contiguous (2, L, L/2)
+    device tensor), starting at sweep counter `sweep`; the library's fixed device
+    array serves as the workspace.  `out`: None, or a float64 device tensor for the
+    records (allocated here if None and records are asked for -- pass one to keep
+    the call allocation-free)."""
+    import torch
+    prec = _PREC[precision]
+    nrec = n_sweeps // measure_every if measure_every > 0 else 0
+    if nrec and out is None:
+        out = torch.empty((nrec, 8), dtype=torch.float64, device=state.device)
+    if nrec:
+        _check_out(out, nrec * 64, state.device, "xy_sweep_noalloc")
+    if not state.is_contiguous():
+        raise ValueError("xy_sweep_noalloc: state must be contiguous")
+    check(_lib.xy_sweep_noalloc(int(seed), int(L), float(beta), float(delta), prec, int(sweep), int(n_sweeps),
+                                int(measure_every), _ptr(state), _nbytes(state), _ptr(out) if nrec else None,
+                                _stream_handle(stream)), "xy_sweep_noalloc")
+    return out
 
 
 def xy_test_inject_failure(after: int):
