@@ -1,19 +1,27 @@
 #!/usr/bin/env python
 """Benchmark: checkerboard Metropolis sweeps of the 2-d XY model on one MI355X.
 
-Workload (default): one L = 4096 lattice (16.8 M sites, FP32 angles), beta = 1.12,
-delta = 1.0, hot start from seed 1; W warm-up steps (thermalisation) then K timed
-steps; one step = 10 sweeps plus one FP64 record of the energy, magnetisation and
-helicity sums (measured every 10 sweeps).  Defaults W = 100, K = 1000 reproduce the
-configuration's 10^3 thermalisation + 10^4 measured sweeps.
+Workload (default): the HBM-streaming lattice, L = 16384 (268 M sites, 1 GiB of
+FP32 angles), beta = 1.0, delta = 1.2, hot start from seed 1, every observable
+(FP64 energy, helicity and magnetisation sums) recorded after every sweep.  One
+step = 25 sweeps with their 25 records; W warm-up steps, then K timed steps
+(defaults W = 4, K = 20: the configuration's 500 sweeps), the plan picked by the
+library's autotuner on a scratch lattice of the same size.
 
 Prints one JSON line.  `value` is site-updates per second (Gupd/s) of the timed
-region, inputs resident in HBM.  `roofline` covers the dominant kernel (the fused
-LDS-tiled sweep), timed with HIP events on the stream it runs on.  `cpu_baseline`
-is the FP64 C oracle on a bounded sample of the same workload on one host core.
-`extra` holds the other configurations of the metric: the HBM-streaming L = 16384
-lattice, the batched 96-lattice temperature scan against per-lattice launches,
-and the FP16-storage variant.
+region, inputs resident in HBM.  `roofline` covers the dominant kernel (the
+sweep kernel of the chosen plan, measured sweeps): its launches in the timed
+region are bracketed by HIP events on the stream they run on (the library's
+kernel timer), and achieved = 8 algorithmic bytes per site-update (read and
+write each FP32 angle once) x L^2 / average launch duration, against the 8 TB/s
+HBM3E peak; the device-to-device copy rate measured in the same run is given
+beside it.  `traffic` is the counter-measured HBM bytes per launch from the
+committed profile, while the kernel sources still hash as profiled.
+`cpu_baseline` is the FP64 C oracle on one sweep of the same lattice on one host
+core.  `extra` holds the other configurations of the metric: the MALL-resident
+L = 4096 lattice with its ALU roofline, the batched 96-lattice temperature scan
+against per-lattice launches, tempering, FP16 storage, four replicas per texel
+and HMC.
 """
 from __future__ import annotations
 
@@ -50,47 +58,89 @@ ALG_SLOTS_PER_UPDATE = 76.0
 ALG_BYTES_FUSED = 8.0                    # bytes per site-update of one fused sweep: read 4 + write 4 (FP32)
 ALG_BYTES_STREAM = 12.0                  # two half-sweep passes: read both colours, write one, per half
 ALG_BYTES_HMC_STEP = 16.0                # one leap-frog step: read and write the angle and the momentum
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_fused_traffic.json")
-PLAN_NAMES = {1: "stream", 2: "fused", 3: "strip"}
+PLAN_NAMES = {1: "stream", 2: "fused", 3: "strip", 4: "resident"}
 BATCH_SCHEDULES = {0: "persistent", 1: "per-sweep launches", 2: "per-sweep launches, 256x16 tiles where L allows"}
 KERNEL_NAMES = {1: "k_half_sweep", 2: "k_fused (LDS-tiled fused red+black sweep)",
                 3: "k_strip (strip segment, rows streamed through LDS rings)"}
-KERNEL_SOURCES = ["xy_device.hpp", "xy_tile1.hpp", "xy_fused.hip"]
+# Counter profiles (FETCH_SIZE / WRITE_SIZE per launch) of the tiled sweep kernels,
+# valid while the kernel's sources hash as they did when the counters were taken.
+TRAFFIC_FILES = {2: os.path.join(ROOT, "profiles", "k_fused_traffic.json"),
+                 3: os.path.join(ROOT, "profiles", "k_strip_traffic.json")}
+KERNEL_SOURCES = {2: ["xy_device.hpp", "xy_tile1.hpp", "xy_fused.hip"],
+                  3: ["xy_device.hpp", "xy_tile1.hpp", "xy_strip.hpp", "xy_strip.hip"]}
+TRAFFIC_FILE = TRAFFIC_FILES[2]           # the fused kernel's file (kept for its CPU test)
 
 
-def kernel_sources_hash() -> str:
+def kernel_sources_hash(kind: int = 2) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
+    for name in KERNEL_SOURCES[kind]:
         with open(os.path.join(ROOT, "paper_0811_2111_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic(L, plan):
-    """HBM bytes per launch of k_fused from the committed counter profile, if it was
-    taken on the current kernel sources for this lattice and tile; else None."""
+def measured_traffic(L, plan, measured=False):
+    """HBM bytes per launch of the plan's sweep kernel (measured or unmeasured
+    sweep) from the committed counter profile, if it was taken on the current
+    kernel sources for this lattice and tile; else None."""
+    kind = plan[0]
+    path = TRAFFIC_FILE if kind == 2 else TRAFFIC_FILES.get(kind)
+    if path is None:
+        return None
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sources_sha256") != kernel_sources_hash():
+    if t.get("kernel_sources_sha256") != kernel_sources_hash(kind):
         return None
-    if plan[0] != 2:                         # the counters were taken on the fused tile kernel
-        return None
-    e = t.get("entries", {}).get("%d/%d,%d,%d" % (L, plan[1], plan[2], plan[3]))
+    key = "%d/%d,%d,%d" % (L, plan[1], plan[2], plan[3]) + ("/meas" if measured else "")
+    e = t.get("entries", {}).get(key)
+    if e is None and not measured and kind == 2:
+        e = t.get("entries", {}).get("%d/%d,%d,%d" % (L, plan[1], plan[2], plan[3]))
     return None if e is None else e.get("bytes_per_launch")
+
+
+def host_cpu():
+    """Host CPU of this run: logical CPUs usable by this process and the model name."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return n, model
+
+
+def copy_rate_gbs(stream, nbytes=1 << 30, reps=10):
+    """Device-to-device copy of nbytes (read + write bytes per second): the HBM
+    rate a plain streaming kernel reaches on this device."""
+    import torch
+    a = torch.ones((nbytes // 4,), dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = timed(lambda: [b.copy_(a) for _ in range(reps)], stream)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes * reps / (ms * 1e-3) / 1e9
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--no-extra", action="store_true", help="skip the L=16384, batched and FP16 legs")
+    ap.add_argument("--steps", type=int, default=20, help="timed steps of 25 sweeps (default: 500 sweeps)")
+    ap.add_argument("--warmup", type=int, default=4, help="untimed steps of 25 sweeps before the timed ones")
+    ap.add_argument("--no-extra", action="store_true", help="skip the L=4096, batched, FP16, quad and HMC legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps of the L=4096 sample")
+    ap.add_argument("--cpu-sweeps", type=int, default=1, help="oracle sweeps of the L=16384 sample")
     ap.add_argument("--kernel-only", action="store_true",
                     help="only the main workload's sweeps (for profiler runs)")
     ap.add_argument("--plan", type=str, default=None,
@@ -98,7 +148,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc", "quad", "fp16", "tempering", "small"],
-                    default="l4096",
+                    default="l16384",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
     ap.add_argument("--schedule", type=int, default=None,
                     help="with --kernel-only --workload batch: batch schedule (0 persistent, 1 per-sweep, "
@@ -118,6 +168,9 @@ def timed(fn, stream):
     return e0.elapsed_time(e1)            # ms
 
 
+SWEEPS_PER_STEP = 25
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -130,11 +183,11 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
-    if args.kernel_only and args.workload != "l4096":
+    if args.kernel_only and args.workload != "l16384":
         profile_leg(args, stream)
         return
-    cfg = workloads.SINGLE_4096
-    L, me = cfg["L"], cfg["measure_every"]
+    cfg = workloads.SINGLE_16384
+    L, me, sps = cfg["L"], cfg["measure_every"], SWEEPS_PER_STEP
     N = L * L
     # the plan (schedule and tile shape) is picked by the library's autotuner on a
     # scratch lattice of the same size; it does not change the trajectory
@@ -142,53 +195,73 @@ def main():
         tuned = tuple(int(v) for v in args.plan.split(","))
     else:
         scratch = xy.Lattice(L, seed=cfg["seed"] + 1000, beta=cfg["beta"], delta=cfg["delta"])
-        tuned = scratch.autotune(20)
+        tuned = scratch.autotune(8)
         del scratch
+        torch.cuda.empty_cache()
     lat = xy.Lattice(L, seed=cfg["seed"], beta=cfg["beta"], delta=cfg["delta"], plan=tuned)
     plan = lat.plan
+    tiled = plan[0] in (xy.XY_PLAN_FUSED, xy.XY_PLAN_STRIP)
     if args.calib_copy:
         a = torch.ones((64 << 20,), dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    obs_w = torch.empty((max(args.warmup, 1), 8), dtype=torch.float64, device="cuda")
-    obs_t = torch.empty((max(args.steps, 1), 8), dtype=torch.float64, device="cuda")
+    copy_gbs = None if args.kernel_only else copy_rate_gbs(stream)
+    obs_w = torch.empty((max(args.warmup * sps, 1), 8), dtype=torch.float64, device="cuda")
+    obs_t = torch.empty((max(args.steps * sps, 1), 8), dtype=torch.float64, device="cuda")
+    # warm-up steps right before the timed ones bring the clocks up after the host
+    # work above; the library's kernel timer brackets every sweep launch of the
+    # timed region with HIP events on the lattice's stream
+    torch.cuda.synchronize()
     if args.warmup:
-        lat.sweep(me * args.warmup, me, out=obs_w)
-    ms = timed(lambda: lat.sweep(me * args.steps, me, out=obs_t), stream)
-    updates = float(N) * me * args.steps
+        lat.sweep(sps * args.warmup, me, out=obs_w)
+    torch.cuda.synchronize()
+    if tiled:
+        lat.kernel_timer(args.steps * sps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.sweep(sps * args.steps, me, out=obs_t)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    k_ms, k_n = lat.kernel_timer_read() if tiled else (0.0, 0)
+    lat.kernel_timer(0)
+    updates = float(N) * sps * args.steps
     gupd = updates / (ms * 1e-3) / 1e9
-    rec = xy.records(obs_t[: args.steps])
+    rec = xy.records(obs_t[: args.steps * sps])
     e_mean = float(-(rec["cx"] + rec["cy"]).mean() / N)
     acc_rate = float(rec["n_accept"].mean() / N)
+    ups = float(rec["cx"].size)
 
-    # dominant kernel: average duration of one fused or strip launch (no measurement),
-    # events on the stream; the streaming plan launches two half-sweeps per sweep
-    # Events on the library's stream bracket each call of 20 sweeps (20 launches
-    # back to back for the tiled plans), so a pause of the host between calls is
-    # not counted; the per-launch average is the sum over 30 calls / launches.
-    # 200 untimed sweeps are queued right before the first event: after the host
-    # work above the GPU has been idle, and its clock takes a few milliseconds to
-    # come back up.
-    nrep, per_call = 30, 20
-    tiled = plan[0] in (xy.XY_PLAN_FUSED, xy.XY_PLAN_STRIP)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nrep)]
-    torch.cuda.synchronize()
-    lat.sweep(plan[3] * 200)
-    for e0, e1 in ev:
-        e0.record(stream)
-        lat.sweep(plan[3] * per_call)
-        e1.record(stream)
-    torch.cuda.synchronize()
-    ms_k = sum(e0.elapsed_time(e1) for e0, e1 in ev)
-    launches = nrep * per_call if tiled else nrep * per_call * plan[3] * 2
-    per_launch_ms = ms_k / launches
-    sweeps_per_launch = plan[3] if tiled else 0.5
-    upd_per_launch = N * sweeps_per_launch
-    alg_bytes = (ALG_BYTES_FUSED if tiled else ALG_BYTES_STREAM / 2) * upd_per_launch
+    # dominant kernel: the measured sweep launch of the chosen plan
+    if k_n:
+        per_launch_ms = k_ms / k_n
+        upd_per_launch = N * plan[3]
+        alg_bytes = ALG_BYTES_FUSED * N          # one read and one write of every angle per launch
+    else:                                        # streaming plan: no timer; whole sweeps
+        per_launch_ms = ms / (sps * args.steps)
+        upd_per_launch = N
+        alg_bytes = ALG_BYTES_STREAM * N
     achieved_gbs = alg_bytes / (per_launch_ms * 1e-3) / 1e9
-    gupd_kernel = upd_per_launch / (per_launch_ms * 1e-3) / 1e9
+    roofline = {
+        "kernel": KERNEL_NAMES.get(plan[0], "sweep") + ", measured sweep",
+        "bound": "hbm",
+        "achieved": round(achieved_gbs, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(L, plan, measured=True),
+        "alg_bytes_per_update": ALG_BYTES_FUSED if k_n else ALG_BYTES_STREAM,
+        "alg_bytes_per_launch": alg_bytes,
+        "avg_launch_ms": round(per_launch_ms, 5),
+        "launches_timed": k_n,
+        "kernel_gupd_s": round(upd_per_launch / (per_launch_ms * 1e-3) / 1e9, 2),
+    }
+    if copy_gbs is not None:
+        roofline["device_copy_GBs"] = round(copy_gbs, 1)
+        roofline["frac_of_device_copy"] = round(achieved_gbs / copy_gbs, 4)
     out = {
         "metric": "site-updates/sec (Gupd/s) at 1 MI355X; % HBM roofline; batched vs per-lattice speedup",
         "value": round(gupd, 3),
@@ -202,37 +275,83 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (hot start from Philox seed 1)",
-        "config": {"workload": "XY checkerboard Metropolis, L=4096 single lattice, beta=1.12, delta=1.0, "
-                               "10 sweeps + FP64 E/M/helicity record per step",
-                   "L": L, "beta": cfg["beta"], "delta": cfg["delta"], "sweeps_per_step": me,
+        "config": {"workload": "XY checkerboard Metropolis, L=16384 single lattice (HBM-streaming), beta=1.0, "
+                               "delta=1.2, FP64 E/helicity/M record every sweep; step = 25 sweeps",
+                   "L": L, "beta": cfg["beta"], "delta": cfg["delta"], "sweeps_per_step": sps,
+                   "measure_every": me,
                    "plan": {"kind": PLAN_NAMES[plan[0]], "tile_x": plan[1], "tile_y": plan[2],
                             "sweeps_per_pass": plan[3]},
                    "parallelism": "single GPU"},
-        "roofline": {
-            "kernel": KERNEL_NAMES[plan[0]],
-            "bound": "alu",
-            "achieved": round(ALG_SLOTS_PER_UPDATE * upd_per_launch / (per_launch_ms * 1e-3) / 1e12, 2),
-            "peak": round(VALU_PEAK_TSLOTS, 2),
-            "unit": "T VALU-slot/s",
-            "frac": round(ALG_SLOTS_PER_UPDATE * upd_per_launch / (per_launch_ms * 1e-3) / 1e12 / VALU_PEAK_TSLOTS, 4),
-            "traffic": measured_traffic(L, plan),
-            "alg_slots_per_update": ALG_SLOTS_PER_UPDATE,
-            "avg_launch_ms": round(per_launch_ms, 5),
-            "kernel_gupd_s": round(gupd_kernel, 2),
-            "hbm": {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
-                    "alg_bytes_per_update": ALG_BYTES_FUSED if tiled else ALG_BYTES_STREAM},
-        },
-        "observables": {"E_per_site": round(e_mean, 6), "accept_rate": round(acc_rate, 4)},
+        "roofline": roofline,
+        "observables": {"E_per_site": round(e_mean, 6), "accept_rate": round(acc_rate, 4),
+                        "records": int(ups)},
     }
 
     if not args.kernel_only and not args.no_extra:
-        out["extra"] = extra_legs(stream, lat)
+        del lat, obs_w, obs_t
+        torch.cuda.empty_cache()
+        out["extra"] = extra_legs(stream, args)
 
     if not args.kernel_only and not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sweeps)
 
     print(json.dumps(out), flush=True)
+
+
+def l4096_leg(stream, steps=1000, warmup=100):
+    """The MALL-resident L = 4096 lattice (beta = 1.12, delta = 1.0, a record every
+    10 sweeps): Gupd/s, and the dominant (unmeasured fused) launch against the ALU
+    and HBM peaks."""
+    import torch
+
+    from paper_0811_2111_amd import workloads, xy
+    cfg = workloads.SINGLE_4096
+    L, me = cfg["L"], cfg["measure_every"]
+    N = L * L
+    scratch = xy.Lattice(L, seed=cfg["seed"] + 1000, beta=cfg["beta"], delta=cfg["delta"])
+    tuned = scratch.autotune(20)
+    del scratch
+    lat = xy.Lattice(L, seed=cfg["seed"], beta=cfg["beta"], delta=cfg["delta"], plan=tuned)
+    plan = lat.plan
+    obs_w = torch.empty((warmup, 8), dtype=torch.float64, device="cuda")
+    obs_t = torch.empty((steps, 8), dtype=torch.float64, device="cuda")
+    lat.sweep(me * warmup, me, out=obs_w)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.sweep(me * steps, me, out=obs_t)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    gupd = float(N) * me * steps / (ms * 1e-3) / 1e9
+    res = {"gupd_s": round(gupd, 2), "sweeps": me * steps, "ms": round(ms, 2), "plan": list(plan),
+           "thermalisation_sweeps": me * warmup}
+    tiled = plan[0] in (xy.XY_PLAN_FUSED, xy.XY_PLAN_STRIP)
+    if tiled:
+        # unmeasured launches (9 of every 10 sweeps) timed by the library's kernel
+        # timer, after 200 untimed sweeps queued right before
+        lat.sweep(plan[3] * 200)
+        lat.kernel_timer(600)
+        lat.sweep(plan[3] * 600)
+        k_ms, k_n = lat.kernel_timer_read()
+        lat.kernel_timer(0)
+        per_launch_ms = k_ms / k_n
+        upd = N * plan[3]
+        slots = ALG_SLOTS_PER_UPDATE * upd / (per_launch_ms * 1e-3) / 1e12
+        gbs = ALG_BYTES_FUSED * N / (per_launch_ms * 1e-3) / 1e9
+        res["roofline_alu"] = {"kernel": KERNEL_NAMES[plan[0]] + ", unmeasured sweep", "bound": "alu",
+                               "achieved": round(slots, 2), "peak": round(VALU_PEAK_TSLOTS, 2),
+                               "unit": "T VALU-slot/s", "frac": round(slots / VALU_PEAK_TSLOTS, 4),
+                               "alg_slots_per_update": ALG_SLOTS_PER_UPDATE,
+                               "avg_launch_ms": round(per_launch_ms, 5), "launches_timed": k_n,
+                               "kernel_gupd_s": round(upd / (per_launch_ms * 1e-3) / 1e9, 2),
+                               "traffic": measured_traffic(L, plan),
+                               "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                       "alg_bytes_per_update": ALG_BYTES_FUSED}}
+    del lat, obs_w, obs_t
+    torch.cuda.empty_cache()
+    return res
 
 
 def profile_leg(args, stream):
@@ -246,15 +365,16 @@ def profile_leg(args, stream):
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    if args.workload == "l16384":
-        c4 = workloads.SINGLE_16384
+    if args.workload == "l4096":
+        c2 = workloads.SINGLE_4096
         plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
-        lat = xy.Lattice(c4["L"], seed=c4["seed"], beta=c4["beta"], delta=c4["delta"], plan=plan)
+        lat = xy.Lattice(c2["L"], seed=c2["seed"], beta=c2["beta"], delta=c2["delta"], plan=plan)
+        me = c2["measure_every"]
         obs = torch.empty((max(args.steps, 1), 8), dtype=torch.float64, device="cuda")
-        lat.sweep(args.warmup, 1, out=obs[: max(args.warmup, 1)])
-        ms = timed(lambda: lat.sweep(args.steps, c4["measure_every"], out=obs[: args.steps]), stream)
-        print(json.dumps({"workload": "L16384", "sweeps": args.steps, "ms": ms,
-                          "gupd_s": float(c4["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}))
+        lat.sweep(me * args.warmup, me, out=obs[: max(args.warmup, 1)])
+        ms = timed(lambda: lat.sweep(me * args.steps, me, out=obs[: args.steps]), stream)
+        print(json.dumps({"workload": "L4096", "sweeps": me * args.steps, "ms": ms, "plan": list(lat.plan),
+                          "gupd_s": float(c2["L"]) ** 2 * me * args.steps / (ms * 1e-3) / 1e9}))
     elif args.workload == "hmc":
         hc = workloads.HMC_16384
         lat = xy.Lattice(hc["L"], seed=hc["seed"], beta=hc["beta"])
@@ -321,28 +441,14 @@ def profile_leg(args, stream):
                           "gupd_s": float(sites) * args.steps / (ms * 1e-3) / 1e9}))
 
 
-def extra_legs(stream, main_lat=None):
+def extra_legs(stream, args=None):
     import torch
 
     from paper_0811_2111_amd import workloads, xy
     ex = {}
-    # HBM-streaming lattice
-    c4 = workloads.SINGLE_16384
-    L = c4["L"]
-    scratch = xy.Lattice(L, seed=c4["seed"] + 1000, beta=c4["beta"], delta=c4["delta"])
-    tuned = scratch.autotune(8)
-    del scratch
-    lat = xy.Lattice(L, seed=c4["seed"], beta=c4["beta"], delta=c4["delta"], plan=tuned)
-    obs = torch.empty((c4["sweeps"], 8), dtype=torch.float64, device="cuda")
-    lat.sweep(4, 1, out=obs[:4])
-    ms = timed(lambda: lat.sweep(c4["sweeps"], c4["measure_every"], out=obs), stream)
-    g = float(L) * L * c4["sweeps"] / (ms * 1e-3) / 1e9
-    ex["L16384_hbm_streaming"] = {
-        "gupd_s": round(g, 2), "sweeps": c4["sweeps"], "ms": round(ms, 2), "plan": list(lat.plan),
-        "alg_GBps_8B": round(g * 8.0, 1), "frac_hbm_8B": round(g * 8.0 / HBM_PEAK_GBS, 4),
-        "effective_frac_12B": round(g * 12.0 / HBM_PEAK_GBS, 4)}
-    del lat, obs
-    torch.cuda.empty_cache()
+    # the MALL-resident single lattice (ALU-bound) with its roofline
+    ex["L4096_mall_resident"] = l4096_leg(stream)
+    main_plan = tuple(ex["L4096_mall_resident"]["plan"])
 
     # batched temperature scan vs per-lattice launches
     sc = workloads.temperature_scan()
@@ -422,7 +528,7 @@ def extra_legs(stream, main_lat=None):
     ms_q = timed(lambda: qd.sweep(qc["sweeps"], qc["measure_every"], out=qobs), stream)
     tile_q = qd.tile
     del qd, qobs
-    singles = [xy.Lattice(qc["L"], seed=s_, beta=b_, delta=qc["delta"], plan=tuple(main_lat.plan) if main_lat is not None else None)
+    singles = [xy.Lattice(qc["L"], seed=s_, beta=b_, delta=qc["delta"], plan=main_plan)
                for s_, b_ in zip(qc["seeds"], qc["betas"])]
     for lt in singles:
         lt.sweep(10, 10)
@@ -468,14 +574,19 @@ def extra_legs(stream, main_lat=None):
 
 
 def cpu_baseline(cfg, sweeps):
+    """The FP64 C oracle as it stands (single-threaded) on `sweeps` sweeps of the
+    same lattice from its hot start; only the sweeps are timed."""
     import oracle
     L = cfg["L"]
     th = oracle.hot_start(cfg["seed"], L, "f32")
     t0 = time.perf_counter()
     oracle.run(cfg["seed"], th, cfg["beta"], cfg["delta"], sweeps, 0, prec="f32")
     dt = time.perf_counter() - t0
+    n, model = host_cpu()
     return {"value": round(float(L) * L * sweeps / dt / 1e9, 6), "unit": "Gupd/s", "cores": 1, "kind": "oracle",
-            "sample": "%d sweeps of the L=%d lattice from its hot start (%.1f s on one core)" % (sweeps, L, dt)}
+            "sample": "%d sweep(s) of the L=%d lattice (beta=%g, delta=%g) from its hot start, %.1f s on one core"
+                      % (sweeps, L, cfg["beta"], cfg["delta"], dt),
+            "host_cpus": n, "cpu_model": model}
 
 
 if __name__ == "__main__":
