@@ -187,6 +187,7 @@ struct StripWalk {
                 acc += aa + ab;
                 bio<T>::st2(rd, (unsigned)(g.y0 - 1 + rel) * Hh + col, ta, tb);
             }
+            if constexpr (MEAS) pin_sums(acc);
         }
         __syncthreads();
 
@@ -207,6 +208,7 @@ struct StripWalk {
             if constexpr (MEAS) {
                 meas_acc(m, ca, sa, n.la, n.ra, n.ua, n.da);
                 meas_acc(m, cb, sb, n.lb, n.rb, n.ub, n.db);
+                pin_sums(m, acc);
             }
         }
         ub = pb[C];   // already consumed above, so no wait

@@ -166,6 +166,17 @@ __device__ __forceinline__ void meas_acc(MeasAcc& m, float cb, float sb, float2 
     m.my = __fadd_rn(__fadd_rn(m.my, sb), r.y);
 }
 
+// Running sums of a measured sweep, made to exist in registers at this point.
+// Without it the compiler sinks the bond arithmetic of a step past the step
+// boundary, keeping that step's neighbour (cos, sin) live across the next
+// step's updates: the measured strip kernel then needs 133 VGPRs (three waves
+// per SIMD) instead of 84 (five).
+__device__ __forceinline__ void pin_sums(int& acc) { asm volatile("" : "+v"(acc)); }
+__device__ __forceinline__ void pin_sums(MeasAcc& m, int& acc)
+{
+    asm volatile("" : "+v"(m.cx), "+v"(m.cy), "+v"(m.ix), "+v"(m.iy), "+v"(m.mx), "+v"(m.my), "+v"(acc));
+}
+
 // Per-thread geometry shared by both phases.
 //
 // Work items are pairs of a core half-row.  A pass of the workgroup covers RP
