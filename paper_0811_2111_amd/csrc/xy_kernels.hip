@@ -9,6 +9,8 @@
 // y * P + j)) and their middle horizontal neighbour.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "xy_device.hpp"
 #include "xy_launch.hpp"
 
@@ -118,12 +120,15 @@ k_half_sweep(T* __restrict__ st, int L, int col, uint32_t sweep, uint32_t k0, ui
              unsigned long long* __restrict__ counter, uint8_t* __restrict__ dbg_acc,
              float* __restrict__ dbg_dE)
 {
+    __shared__ unsigned long long wacc[4];
     const int Hh = L >> 1;
     const int P = (Hh + 1) >> 1;
     const int j = blockIdx.x * 64 + threadIdx.x;
-    const int y = blockIdx.y * 4 + threadIdx.y;
     int acc = 0;
-    if (j < P && y < L) {
+    // rows in a grid-stride loop: the grid stays a few thousand blocks, and so does
+    // the number of accept-counter atomics (one per block)
+    for (int y = blockIdx.y * 4 + threadIdx.y; y < L; y += gridDim.y * 4) {
+        if (j >= P) continue;
         const int o = (col + y) & 1;
         T* own = st + ((size_t)col * L + y) * Hh;
         const T* oth = st + ((size_t)(1 - col) * L + y) * Hh;
@@ -173,7 +178,12 @@ k_half_sweep(T* __restrict__ st, int L, int col, uint32_t sweep, uint32_t k0, ui
     }
     if (counter) {
         const unsigned long long w = wave_sum_u64((unsigned long long)acc);
-        if ((threadIdx.x & 63) == 0 && w) atomicAdd(counter, w);
+        if ((threadIdx.x & 63) == 0) wacc[threadIdx.y] = w;
+        __syncthreads();
+        if (threadIdx.x == 0 && threadIdx.y == 0) {
+            const unsigned long long t = (wacc[0] + wacc[1]) + (wacc[2] + wacc[3]);
+            if (t) atomicAdd(counter, t);
+        }
     }
 }
 
@@ -181,7 +191,10 @@ hipError_t launch_half_sweep(const SweepArgs& a, int colour, unsigned long long*
                              float* dbg_dE, hipStream_t s)
 {
     const int P = ((a.L >> 1) + 1) >> 1;
-    dim3 grid((P + 63) / 64, (a.L + 3) / 4), block(64, 4);
+    // about 8192 blocks at most: the row loop covers the rest
+    const int gx = (P + 63) / 64;
+    const int gy = std::max(1, std::min((a.L + 3) / 4, 8192 / gx));
+    dim3 grid(gx, gy), block(64, 4);
     const Params p{a.delta, a.nbl2e};
     if (a.precision == XY_FP16)
         hipLaunchKernelGGL(k_half_sweep<__half>, grid, block, 0, s, (__half*)a.dst, a.L, colour, a.sweep,

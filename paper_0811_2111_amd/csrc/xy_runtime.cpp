@@ -354,16 +354,17 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
         return XY_OK;
     }
 
-    // Fused schedule: an even number of ping-pong passes (state -> pingpong ->
-    // state ...), so the angles end in the caller's buffer; the remaining sweeps
-    // run in place with the streaming schedule (same trajectory).  If a launch
-    // fails after an odd number of passes, the latest angles are copied back from
-    // the ping-pong buffer, so the state and the counter (the sweeps enqueued)
-    // always agree and the handle stays usable.
+    // Tiled schedules: ping-pong passes (state -> pingpong -> state ...); after an
+    // odd number of passes the angles are copied back from the ping-pong buffer
+    // (one device copy, far cheaper than a streaming sweep at large L), so they
+    // end in the caller's buffer; sweeps left over by a two-sweep plan run in
+    // place with the streaming schedule (same trajectory).  If a launch fails after
+    // an odd number of passes, the latest angles are copied back likewise, so the
+    // state and the counter (the sweeps enqueued) always agree and the handle
+    // stays usable.
     const bool strip = h->plan.kind == XY_PLAN_STRIP;
     const int m = strip ? 1 : h->plan.sweeps_per_pass;
-    int64_t passes = n_sweeps / m;
-    passes -= passes & 1;
+    const int64_t passes = n_sweeps / m;
     const int nrec = strip ? xyk::strip_records(h->L, h->plan.tile_x, h->plan.tile_y)
                            : xyk::fused_records(h->L, h->plan.tile_x, h->plan.tile_y, m);
     int64_t j = 0;  // sweeps done in this call
@@ -401,6 +402,12 @@ int xy_sweep(xy_lattice* h, int64_t n_sweeps, int32_t measure_every, xy_obs* obs
                                                h->w.arrive));
             if (e != hipSuccess) return fail(e, "finalize launch");
         }
+    }
+    if (done_passes & 1) {
+        hipError_t e = XY_LAUNCH(hipMemcpyAsync(h->state, h->w.pingpong, xyk::state_bytes(h->L, h->precision),
+                                                hipMemcpyDeviceToDevice, h->stream));
+        if (e != hipSuccess) return fail(e, "copy back");
+        done_passes = 0;
     }
     for (; j < n_sweeps; ++j) {
         int rc = stream_sweep(h, measured(j + 1), measured(j + 1) ? rec_of(j + 1) : nullptr, nullptr, nullptr);
