@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0                    # MI355X HBM3E
 VALU_PEAK_TSLOTS = 256 * 128 * 2.4e9 / 1e12
 # Algorithmic VALU slots of one site update of a sweep that reads the angles once,
 # with the issue costs measured on MI355X relative to v_add_f32
-# (paper_0811_2111_amd/probes/issue_cost.hip: v_mad_u64_u32 2.76, v_sin/v_cos 3.42,
+# (throughput microbenchmark, profiles/valu_issue_costs.md: v_mad_u64_u32 2.76, v_sin/v_cos 3.42,
 # v_exp 3.50, v_bitop3_b32 1.72, v_fma/v_fmaak 1.14, v_fract 1.06, others 1) and the
 # instruction counts of the compiled update:
 #   half a Philox4x32-10 call (16.5 v_mad_u64_u32, 13 v_bitop3, 3 v_xor per call)   35.5

@@ -46,8 +46,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB)
+        # XY_ORACLE_LIB names another build of the same sources (the sanitizer test's)
+        path = os.environ.get("XY_ORACLE_LIB") or build()
+        L = ctypes.CDLL(path)
         u32p = ctypes.POINTER(ctypes.c_uint32)
         dp = ctypes.POINTER(ctypes.c_double)
         u8p = ctypes.POINTER(ctypes.c_uint8)

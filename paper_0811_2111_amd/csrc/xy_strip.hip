@@ -68,8 +68,7 @@ static hipError_t run_strip_k(const SweepArgs& a, double* partials, hipStream_t 
     X(256, 256)            \
     X(512, 64)             \
     X(512, 128)            \
-    X(512, 256)            \
-    X(512, 512)
+    X(512, 256)
 
 bool strip_supported(int L, int tile_x, int tile_y)
 {

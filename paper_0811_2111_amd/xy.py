@@ -62,6 +62,9 @@ class XYError(RuntimeError):
 
 
 def _load():
+    global LIB_PATH
+    # XY_LIB names another build of the same sources (the sanitizer test's host-only build)
+    LIB_PATH = os.environ.get("XY_LIB") or LIB_PATH
     if not os.path.exists(LIB_PATH):
         raise ImportError("libxyhip.so is not built (%s); run python -m paper_0811_2111_amd.build" % LIB_PATH)
     # torch first: its bundled HIP runtime carries the soname libamdhip64.so.7, so

@@ -3,7 +3,7 @@ device against FP64 storage in the oracle).
 
 Not collected by pytest (a long measurement, run by hand on an MI355X):
 
-    python tests/precision_replicas.py --out results.json [--replicas 16 --sweeps 4000 --discard 1000]
+    python tests/precision_replicas.py [--replicas 16 --sweeps 4000 --discard 1000]   # writes tests/results/precision_replicas_L256.json
 
 For each beta, R replicas of an L x L lattice (seeds seed0 .. seed0 + R - 1, hot
 start) run `sweeps` sweeps; each replica's means of e, |m| and the helicity
@@ -71,7 +71,7 @@ def summary(samples):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--out", default=os.path.join(HERE, "results", "precision_replicas_L256.json"))
     ap.add_argument("--L", type=int, default=256)
     ap.add_argument("--replicas", type=int, default=16)
     ap.add_argument("--sweeps", type=int, default=4000)

@@ -2,7 +2,7 @@
 
 Not collected by pytest (a long measurement, run by hand on an MI355X):
 
-    python tests/precision_study.py --out results.json [--sweeps 20000 --discard 2000]
+    python tests/precision_study.py [--sweeps 20000 --discard 2000]   # writes tests/results/precision_study_L8192.json
 
 * device, L = 8192, beta in {0.9, 1.0, 1.1}: FP32 and FP16 storage from the same
   seed and Philox stream, records every 10 sweeps after `discard` sweeps;
@@ -83,7 +83,7 @@ def bias(a, b):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--out", default=os.path.join(HERE, "results", "precision_study_L8192.json"))
     ap.add_argument("--sweeps", type=int, default=20000)
     ap.add_argument("--discard", type=int, default=2000)
     ap.add_argument("--oracle-sweeps", type=int, default=20000)
