@@ -545,6 +545,38 @@ def extra_legs(stream, args=None):
                         "four_single_lattices_gupd_s": round(upd / (ms_s * 1e-3) / 1e9, 2),
                         "sweeps": qc["sweeps"], "betas": qc["betas"]}
 
+    # batched HMC over the temperature scan (one accept per lattice) against the
+    # same trajectories run lattice by lattice
+    hb = workloads.HMC_SCAN
+    sc = workloads.temperature_scan()
+    sites = sum(L * L for L in sc["Ls"])
+    bh = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+    bh.sweep(hb["therm"])
+    bh.hmc(1, hb["n_md"], hb["eps"])
+    hout = torch.empty((len(sc["Ls"]), hb["traj"], 9), dtype=torch.float64, device="cuda")
+    ms_bh = timed(lambda: bh.hmc(hb["traj"], hb["n_md"], hb["eps"], out=hout), stream)
+    rbh = xy.hmc_records(hout)
+    del bh
+    torch.cuda.empty_cache()
+    singles = [xy.Lattice(L, seed=s_, beta=b_, delta=1.0) for L, s_, b_ in zip(sc["Ls"], sc["seeds"], sc["betas"])]
+    for lt in singles:
+        lt.sweep(hb["therm"])
+        lt.hmc(1, hb["n_md"], hb["eps"])
+    ntr = hb["traj_per_lattice_timed"]
+
+    def hmc_singles():
+        for lt in singles:
+            lt.hmc(ntr, hb["n_md"], hb["eps"])
+    ms_sh = timed(hmc_singles, stream)
+    del singles
+    torch.cuda.empty_cache()
+    g_bh = float(sites) * hb["n_md"] * hb["traj"] / (ms_bh * 1e-3) / 1e9
+    g_sh = float(sites) * hb["n_md"] * ntr / (ms_sh * 1e-3) / 1e9
+    ex["hmc_batch_scan_96"] = {"g_site_steps_s": round(g_bh, 2), "trajectories": hb["traj"], "n_md": hb["n_md"],
+                               "eps": hb["eps"], "ms": round(ms_bh, 2),
+                               "accept_rate": round(float(rbh["accepted"].mean()), 3),
+                               "per_lattice_g_site_steps_s": round(g_sh, 2), "speedup": round(g_bh / g_sh, 2)}
+
     # hybrid Monte Carlo trajectories (the paper's update)
     for name, hc in (("hmc_L4096", workloads.HMC_4096), ("hmc_L16384", workloads.HMC_16384)):
         lt = xy.Lattice(hc["L"], seed=hc["seed"], beta=hc["beta"])

@@ -301,6 +301,31 @@ int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_wo
 int xy_hmc_set_steps_per_pass(xy_lattice* h, int32_t steps);
 int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
 
+/* Batched hybrid Monte Carlo: n_traj trajectories of every lattice of an FP32
+ * batch, the paper's update (section 1.2; see xy_hmc) applied to the replicas at
+ * several temperatures of section 3.2 with one Metropolis accept per replica
+ * (the per-replica acceptance vector of section 3.2), decided on the device from
+ * that lattice's own FP64 dH.  Lattice i runs at its current beta with its own
+ * seed; trajectory t of the call uses counter word 0 = the batch's sweep counter,
+ * which advances by one per trajectory (shared with sweeps, as for a single
+ * lattice), so every lattice follows bit for bit the trajectory that xy_hmc
+ * gives a single lattice with the same seed, beta, counter, n_md, eps and leap-
+ * frog steps per pass.  One trajectory of all lattices is captured once into a
+ * HIP graph (lattices spread over four concurrent branches) and replayed.
+ * hmc_work: caller-owned device memory of xy_batch_hmc_work_bytes bytes (per
+ * lattice: momenta, second momenta, saved angles, partial records; then one
+ * staging record per lattice); the batch workspace's ping-pong area holds the
+ * second copy of the angles.  obs_dev: NULL, or device memory for n * n_traj
+ * records, lattice-major (trajectory r of lattice i at obs_dev[i * n_traj + r]).
+ * XY_EINVAL: FP16 batch, n_traj < 0, n_md < 1 or a bad eps; XY_ESIZE: hmc_len too
+ * small; XY_ERANGE: the counter would pass 2^32 - 1. */
+int xy_batch_hmc_work_bytes(const xy_batch* b, size_t* bytes);
+int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
+                 xy_hmc_obs* obs_dev);
+/* Leap-frog steps per pass of xy_batch_hmc (1 .. 8, default 5), as
+ * xy_hmc_set_steps_per_pass.  XY_EINVAL otherwise. */
+int xy_batch_hmc_set_steps_per_pass(xy_batch* b, int32_t steps);
+
 /* Profiling support: time the tiled sweep kernel launches (XY_PLAN_FUSED and
  * XY_PLAN_STRIP; one launch per pass) of the handle's next calls with HIP events
  * recorded on its stream right before and after each launch, for up to

@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -68,7 +70,8 @@ struct Ctrl {
     uint32_t sweep0;      // absolute sweep index of the next pass (advanced by k_batch_advance)
     uint32_t timed_out;   // set if a barrier wait gave up (sticky: the batch's results are void)
     uint32_t spin_limit;  // polls before a barrier wait gives up
-    uint32_t pad[61];
+    uint32_t hmc_round;   // index of the next HMC trajectory within an xy_batch_hmc call
+    uint32_t pad[60];
 };
 
 // Default spin limit of one barrier wait: 2^27 polls with s_sleep 2 (~128
@@ -234,6 +237,26 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
 
 __global__ void k_batch_advance(Ctrl* ctrl, uint32_t n) { ctrl->sweep0 += n; }
 
+// Batched HMC: the trajectory's records of all lattices from the staging area to
+// obs[i * n_traj + r] (r = trajectory within the call), then the sweep counter
+// (the trajectory index every lattice's next trajectory reads) advances by one.
+__global__ void k_bhmc_finish(const xy_hmc_obs* __restrict__ staging, xy_hmc_obs* __restrict__ obs, int n,
+                              int n_traj, Ctrl* __restrict__ ctrl)
+{
+    __shared__ uint32_t r;
+    if (threadIdx.x == 0) r = ctrl->hmc_round;
+    __syncthreads();
+    if (obs)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) obs[(size_t)i * n_traj + r] = staging[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ctrl->hmc_round = r + 1u;
+        ctrl->sweep0 += 1u;
+    }
+}
+
+__global__ void k_bhmc_start(Ctrl* ctrl) { ctrl->hmc_round = 0u; }
+
 // LDS of a per-pass kernel: the larger of the two tile programs it may run, then
 // the workgroup's reduction slots.
 template <int TX, int TY, bool WIDE>
@@ -389,6 +412,8 @@ struct Shape {
 // the small ones exist so that any batch of L % 4 == 0 lattices can run.
 static const Shape kShapes[] = {{64, 32}, {64, 16}, {32, 16}, {16, 16}, {8, 8}, {4, 4}};
 static constexpr int kNT = 256;
+// Streams a batched HMC trajectory forks into (lattices run side by side).
+static constexpr int kHmcStreams = 4;
 // Longest per-sweep launch sequence captured in one graph (longer calls replay it).
 static constexpr int kMaxGraphPasses = 16384;
 
@@ -535,6 +560,18 @@ struct xy_batch {
     int g_nrec;
     int g_grid;
     int g_sched;
+    // batched HMC: extra capture streams, join events and the cached graph of one
+    // trajectory of every lattice (key: n_md, eps, steps per pass, workspace, records on/off)
+    hipStream_t hs[kHmcStreams];
+    hipEvent_t hev[kHmcStreams];
+    hipGraph_t hgraph;
+    hipGraphExec_t hexec;
+    int32_t h_nmd, h_steps;
+    double h_eps;
+    void* h_work;
+    xy_hmc_obs* h_obs;
+    int64_t h_ntraj;
+    int32_t hmc_steps;     // leap-frog steps per pass of xy_batch_hmc
 };
 
 static bool blive(const xy_batch* b) { return b && b->magic == kBatchMagic; }
@@ -542,9 +579,22 @@ static bool blive(const xy_batch* b) { return b && b->magic == kBatchMagic; }
 static void drop_graph(xy_batch* b);
 
 // Graph, streams and events of a batch, then the handle itself.
+static void drop_hmc_graph(xy_batch* b)
+{
+    if (b->hexec) (void)hipGraphExecDestroy(b->hexec);
+    if (b->hgraph) (void)hipGraphDestroy(b->hgraph);
+    b->hexec = nullptr;
+    b->hgraph = nullptr;
+}
+
 static void release(xy_batch* b)
 {
     drop_graph(b);
+    drop_hmc_graph(b);
+    for (int k = 0; k < kHmcStreams; ++k) {
+        if (b->hs[k]) (void)hipStreamDestroy(b->hs[k]);
+        if (b->hev[k]) (void)hipEventDestroy(b->hev[k]);
+    }
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->cap2) (void)hipStreamDestroy(b->cap2);
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
@@ -793,6 +843,19 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->g_obs = nullptr;
     b->g_grid = 0;
     b->g_sched = -1;
+    for (int k = 0; k < kHmcStreams; ++k) {
+        b->hs[k] = nullptr;
+        b->hev[k] = nullptr;
+    }
+    b->hgraph = nullptr;
+    b->hexec = nullptr;
+    b->h_nmd = -1;
+    b->h_steps = -1;
+    b->h_eps = 0.0;
+    b->h_work = nullptr;
+    b->h_obs = nullptr;
+    b->h_ntraj = -1;
+    b->hmc_steps = 5;
     b->sched = XY_BATCH_PASSES_WIDE;
     auto fail = [&](int code) {
         release(b);
@@ -1062,6 +1125,125 @@ int xy_batch_get_params(const xy_batch* b, double* beta, double* delta)
         if (beta) beta[i] = b->beta[i];
         if (delta) delta[i] = b->delta[i];
     }
+    return XY_OK;
+}
+
+// ------------------------------------------------------------- batched HMC
+// Workspace of lattice i at offset off[i] (its HMC areas sized for its L), then
+// the trajectory's records of all lattices (staging).
+static size_t bhmc_layout(const xy_batch* b, std::vector<size_t>* off, size_t* staging)
+{
+    size_t t = 0;
+    if (off) off->resize(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        if (off) (*off)[i] = t;
+        t += align256(xyk::hmc_work_bytes_compact(b->L[i]));
+    }
+    if (staging) *staging = t;
+    return t + align256((size_t)b->n * sizeof(xy_hmc_obs));
+}
+
+int xy_batch_hmc_work_bytes(const xy_batch* b, size_t* bytes)
+{
+    if (!blive(b) || !bytes) return XY_ESTATE;
+    *bytes = bhmc_layout(b, nullptr, nullptr);
+    return XY_OK;
+}
+
+int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
+                 xy_hmc_obs* obs_dev)
+{
+    if (!blive(b)) return XY_ESTATE;
+    if (b->precision != XY_FP32 || n_traj < 0 || n_md < 1 || !std::isfinite(eps) || !(eps > 0.0)) return XY_EINVAL;
+    if (!hmc_work) return XY_ESTATE;
+    std::vector<size_t> off;
+    size_t staging = 0;
+    if (hmc_len < bhmc_layout(b, &off, &staging)) return XY_ESIZE;
+    if (b->sweep + (uint64_t)n_traj >= 0xffffffffull || n_traj > INT32_MAX) return XY_ERANGE;
+    if (n_traj == 0) return XY_OK;
+    hipError_t e;
+    for (int k = 1; k < kHmcStreams; ++k) {
+        if (!b->hs[k] && (e = hipStreamCreateWithFlags(&b->hs[k], hipStreamNonBlocking)) != hipSuccess) {
+            b->hs[k] = nullptr;
+            return xyr::hip_fail(e, "xy_batch_hmc: hipStreamCreate");
+        }
+        if (!b->hev[k] && (e = hipEventCreateWithFlags(&b->hev[k], hipEventDisableTiming)) != hipSuccess) {
+            b->hev[k] = nullptr;
+            return xyr::hip_fail(e, "xy_batch_hmc: hipEventCreate");
+        }
+    }
+    Ctrl* ctrl = (Ctrl*)(b->work + b->lo.ctrl_off);
+    char* hw = (char*)hmc_work;
+    xy_hmc_obs* stage = (xy_hmc_obs*)(hw + staging);
+    if (!b->hexec || b->h_nmd != n_md || b->h_eps != eps || b->h_steps != b->hmc_steps || b->h_work != hmc_work ||
+        b->h_obs != obs_dev || b->h_ntraj != n_traj) {
+        // one trajectory of every lattice, the lattices spread over kHmcStreams
+        // branches (greedy by L^2), captured once and replayed per trajectory; the
+        // kernels read the trajectory index from the batch's device counter
+        drop_hmc_graph(b);
+        if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return xyr::hip_fail(e, "xy_batch_hmc: hipStreamBeginCapture");
+        hipError_t le = hipEventRecord(b->ev_fork, b->cap);
+        for (int k = 1; k < kHmcStreams && le == hipSuccess; ++k) le = hipStreamWaitEvent(b->hs[k], b->ev_fork, 0);
+        double load[kHmcStreams] = {0.0};
+        const size_t eb = sizeof(float);
+        for (int i = 0; i < b->n && le == hipSuccess; ++i) {
+            int k = 0;
+            for (int q = 1; q < kHmcStreams; ++q)
+                if (load[q] < load[k]) k = q;
+            load[k] += (double)b->L[i] * b->L[i];
+            hipStream_t sk = k == 0 ? b->cap : b->hs[k];
+            const LatDesc& d = b->desc[i];
+            float* st = (float*)(b->state + (size_t)d.off * eb);
+            float* pp = (float*)(b->work + b->lo.pp_off + (size_t)d.off * eb);
+            const xyk::HmcWork w = xyk::hmc_carve_compact(hw + off[i], b->L[i]);
+            le = xyk::launch_hmc_trajectory(st, pp, w, b->L[i], b->beta[i], eps, n_md, b->hmc_steps, 0u, d.key0,
+                                            d.key1, stage + i, sk, &ctrl->sweep0);
+        }
+        for (int k = 1; k < kHmcStreams && le == hipSuccess; ++k) {
+            le = hipEventRecord(b->hev[k], b->hs[k]);
+            if (le == hipSuccess) le = hipStreamWaitEvent(b->cap, b->hev[k], 0);
+        }
+        if (le == hipSuccess) {
+            hipLaunchKernelGGL(k_bhmc_finish, dim3(1), dim3(kNT), 0, b->cap, (const xy_hmc_obs*)stage, obs_dev, b->n,
+                               (int)n_traj, ctrl);
+            le = hipGetLastError();
+        }
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap, &g);
+        if (le != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return xyr::hip_fail(le, "xy_batch_hmc: launch (capture)");
+        }
+        if (e != hipSuccess) return xyr::hip_fail(e, "xy_batch_hmc: hipStreamEndCapture");
+        b->hgraph = g;
+        if ((e = hipGraphInstantiate(&b->hexec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            b->hexec = nullptr;
+            drop_hmc_graph(b);
+            return xyr::hip_fail(e, "xy_batch_hmc: hipGraphInstantiate");
+        }
+        b->h_nmd = n_md;
+        b->h_eps = eps;
+        b->h_steps = b->hmc_steps;
+        b->h_work = hmc_work;
+        b->h_obs = obs_dev;
+        b->h_ntraj = n_traj;
+    }
+    hipLaunchKernelGGL(k_bhmc_start, dim3(1), dim3(1), 0, b->stream, ctrl);
+    if ((e = hipGetLastError()) != hipSuccess) return xyr::hip_fail(e, "xy_batch_hmc: launch");
+    for (int64_t t = 0; t < n_traj; ++t) {
+        if ((e = XY_LAUNCH(hipGraphLaunch(b->hexec, b->stream))) != hipSuccess)
+            return xyr::hip_fail(e, "xy_batch_hmc: hipGraphLaunch");
+        b->sweep += 1;
+    }
+    return XY_OK;
+}
+
+int xy_batch_hmc_set_steps_per_pass(xy_batch* b, int32_t steps)
+{
+    if (!blive(b)) return XY_ESTATE;
+    if (steps < 1 || steps > 8) return XY_EINVAL;
+    b->hmc_steps = steps;
     return XY_OK;
 }
 

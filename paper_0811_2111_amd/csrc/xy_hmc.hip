@@ -117,8 +117,10 @@ __device__ __forceinline__ unsigned xcd_band(unsigned b, unsigned nb)
 // Momenta, saved angles and the partial records of H_old.
 __global__ void __launch_bounds__(kThreads)
 k_hmc_begin(const float* __restrict__ st, float* __restrict__ p, float* __restrict__ saved, int L, uint32_t traj,
-            uint32_t k0, uint32_t k1, int cols, int rb, double* __restrict__ rec)
+            const uint32_t* __restrict__ traj_dev, uint32_t k0, uint32_t k1, int cols, int rb,
+            double* __restrict__ rec)
 {
+    if (traj_dev) traj = *traj_dev;
     const int Hh = L >> 1, P = (Hh + 1) >> 1;
     const unsigned t = xcd_band(blockIdx.x, gridDim.x);
     const int col = (int)(t % (unsigned)cols);
@@ -467,13 +469,15 @@ k_hmc_end(const float* __restrict__ st, float* __restrict__ copy, const float* _
     write_record(v, rec, t);
 }
 
-// Begin and end of a trajectory for L % 4 == 0, by pairs: a thread takes the
-// entries 2j, 2j+1 of colour c in a run of consecutive rows; the other plane's
-// pair j of the rows above, at and below a row are kept in registers as a
-// rolling window, so each row loads one new other-plane pair and one edge entry
-// (2j-1 or 2j+2) and computes 2.5 sines and cosines per site instead of 5.
-// 1-D grid of cols2 = 2 ceil(J/256) column blocks (colour interleaved) times rb
-// row blocks, remapped by xcd_band; one partial record per wave.
+// Begin and end of a trajectory for L % 4 == 0, by pairs: a thread takes pair j
+// (entries 2j, 2j+1) of both colours in a run of consecutive rows.  Each plane's
+// pair j of the rows above, at and below a row sits in registers as a rolling
+// window with its (cos, sin): a row loads one new pair of each plane and one edge
+// entry of each (2j-1 or 2j+2), so every angle is read from memory once (a thread
+// per colour would read each plane twice, once as its own colour and once as the
+// other's neighbours) and a site costs 1.5 sines and cosines.
+// 1-D grid of cols2 = ceil(J/256) column blocks times rb row blocks, remapped by
+// xcd_band; one partial record per wave.
 struct PairCS {
     float c0, s0, c1, s1;
 };
@@ -504,46 +508,69 @@ __device__ __forceinline__ void pair_nb(const PairCS& own, const PairCS& u, cons
 template <bool BEGIN>
 __global__ void __launch_bounds__(kThreads)
 k_hmc_ends2(const float* __restrict__ st, float* __restrict__ p, float* __restrict__ copy, int L, uint32_t traj,
-            uint32_t k0, uint32_t k1, float nbeta_kick, int cols, int rb, double* __restrict__ rec)
+            const uint32_t* __restrict__ traj_dev, uint32_t k0, uint32_t k1, float nbeta_kick, int cols, int rb,
+            double* __restrict__ rec)
 {
+    if (BEGIN && traj_dev) traj = *traj_dev;
     const int Hh = L >> 1, J = Hh >> 1;
     const unsigned t = xcd_band(blockIdx.x, gridDim.x);
     const int col = (int)(t % (unsigned)cols);
-    const int c = col & 1;
-    const int j = (col >> 1) * kThreads + threadIdx.x;
+    const int j = col * kThreads + threadIdx.x;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     const int R = (L + rb - 1) / rb, y0 = (int)(t / (unsigned)cols) * R, y1 = y0 + R < L ? y0 + R : L;
     if (j < J && y0 < y1) {
-        const float* own = st + (size_t)c * L * Hh;
-        const float* oth = st + (size_t)(1 - c) * L * Hh;
-        PairCS u = pair_cs(((const float2*)(oth + (size_t)wrapi(y0 - 1, L) * Hh))[j]);
-        PairCS h = pair_cs(((const float2*)(oth + (size_t)y0 * Hh))[j]);
+        const float* pl0 = st;
+        const float* pl1 = st + (size_t)L * Hh;
+        const float2* r0 = (const float2*)pl0;
+        const float2* r1 = (const float2*)pl1;
+        // windows: plane c rows y-1 (u), y (h) with angles, y+1 loaded per row
+        float2 t0 = r0[(size_t)y0 * J + j], t1 = r1[(size_t)y0 * J + j];
+        PairCS u0 = pair_cs(r0[(size_t)wrapi(y0 - 1, L) * J + j]), u1 = pair_cs(r1[(size_t)wrapi(y0 - 1, L) * J + j]);
+        PairCS h0 = pair_cs(t0), h1 = pair_cs(t1);
+        const int kl = wrapi(2 * j - 1, Hh), kr = wrapi(2 * j + 2, Hh);
         for (int y = y0; y < y1; ++y) {
-            const int o = (c + y) & 1;
-            const size_t row = ((size_t)c * L + y) * Hh;
-            const float2 th = ((const float2*)(own + (size_t)y * Hh))[j];
-            const PairCS d = pair_cs(((const float2*)(oth + (size_t)wrapi(y + 1, L) * Hh))[j]);
-            float se, ce;
-            sincos_turn(oth[(size_t)y * Hh + (o ? wrapi(2 * j + 2, Hh) : wrapi(2 * j - 1, Hh))], se, ce);
-            Nb na, nb;
-            pair_nb(pair_cs(th), u, h, d, ce, se, o, na, nb);
-            float pa, pb;
+            const int yd = wrapi(y + 1, L);
+            const float2 n0 = r0[(size_t)yd * J + j], n1 = r1[(size_t)yd * J + j];
+            const PairCS d0 = pair_cs(n0), d1 = pair_cs(n1);
+            const int o = y & 1;                  // red rows: o = y & 1; black rows: 1 - o
+            // edge entries: the red pair reads plane 1 at 2j+2 (o) or 2j-1; the black pair plane 0 the other way
+            float se1, ce1, se0, ce0;
+            sincos_turn(pl1[(size_t)y * Hh + (o ? kr : kl)], se1, ce1);
+            sincos_turn(pl0[(size_t)y * Hh + (o ? kl : kr)], se0, ce0);
+            Nb na0, nb0, na1, nb1;
+            pair_nb(h0, u1, h1, d1, ce1, se1, o, na0, nb0);
+            pair_nb(h1, u0, h0, d0, ce0, se0, 1 - o, na1, nb1);
+            const size_t row0 = (size_t)y * Hh, row1 = ((size_t)L + y) * Hh;
+            float pa0, pb0, pa1, pb1;
             if constexpr (BEGIN) {
-                ((float2*)(copy + row))[j] = th;       // saved angles
-                const u32x4 r = philox10(traj, (uint32_t)c, 2u, (uint32_t)y * (uint32_t)J + (uint32_t)j, k0, k1);
-                pa = box_muller(r.x, r.y);
-                pb = box_muller(r.z, r.w);
-                ((float2*)(p + row))[j] = make_float2(pa, pb);
+                ((float2*)(copy + row0))[j] = t0;      // saved angles
+                ((float2*)(copy + row1))[j] = t1;
+                const u32x4 q0 = philox10(traj, 0u, 2u, (uint32_t)y * (uint32_t)J + (uint32_t)j, k0, k1);
+                const u32x4 q1 = philox10(traj, 1u, 2u, (uint32_t)y * (uint32_t)J + (uint32_t)j, k0, k1);
+                pa0 = box_muller(q0.x, q0.y);
+                pb0 = box_muller(q0.z, q0.w);
+                pa1 = box_muller(q1.x, q1.y);
+                pb1 = box_muller(q1.z, q1.w);
+                ((float2*)(p + row0))[j] = make_float2(pa0, pb0);
+                ((float2*)(p + row1))[j] = make_float2(pa1, pb1);
             } else {
-                if (copy) ((float2*)(copy + row))[j] = th;
-                const float2 pv = ((const float2*)(p + row))[j];
-                pa = __fmaf_rn(nbeta_kick, sin_sum(na), pv.x);
-                pb = __fmaf_rn(nbeta_kick, sin_sum(nb), pv.y);
+                if (copy) {
+                    ((float2*)(copy + row0))[j] = t0;
+                    ((float2*)(copy + row1))[j] = t1;
+                }
+                const float2 pv0 = ((const float2*)(p + row0))[j], pv1 = ((const float2*)(p + row1))[j];
+                pa0 = __fmaf_rn(nbeta_kick, sin_sum(na0), pv0.x);
+                pb0 = __fmaf_rn(nbeta_kick, sin_sum(nb0), pv0.y);
+                pa1 = __fmaf_rn(nbeta_kick, sin_sum(na1), pv1.x);
+                pb1 = __fmaf_rn(nbeta_kick, sin_sum(nb1), pv1.y);
             }
-            accumulate(v, na, c, __fmul_rn(0.5f, __fmul_rn(pa, pa)));
-            accumulate(v, nb, c, __fmul_rn(0.5f, __fmul_rn(pb, pb)));
-            u = h;
-            h = d;
+            accumulate(v, na0, 0, __fmul_rn(0.5f, __fmul_rn(pa0, pa0)));
+            accumulate(v, nb0, 0, __fmul_rn(0.5f, __fmul_rn(pb0, pb0)));
+            accumulate(v, na1, 1, __fmul_rn(0.5f, __fmul_rn(pa1, pa1)));
+            accumulate(v, nb1, 1, __fmul_rn(0.5f, __fmul_rn(pb1, pb1)));
+            u0 = h0; u1 = h1;
+            h0 = d0; h1 = d1;
+            t0 = n0; t1 = n1;
         }
     }
     write_record(v, rec, t);              // every lane reaches the wave sums
@@ -573,8 +600,10 @@ __device__ void sum_records(const double* __restrict__ rec, int nrec, double out
 // record sets.
 __global__ void __launch_bounds__(kThreads)
 k_hmc_decide(const double* __restrict__ rec_old, const double* __restrict__ rec_new, int nrec, double beta,
-             uint32_t traj, uint32_t k0, uint32_t k1, unsigned* __restrict__ flag, xy_hmc_obs* __restrict__ obs)
+             uint32_t traj, const uint32_t* __restrict__ traj_dev, uint32_t k0, uint32_t k1,
+             unsigned* __restrict__ flag, xy_hmc_obs* __restrict__ obs)
 {
+    if (traj_dev) traj = *traj_dev;
     __shared__ double red[4 * 7];
     double o[7], n[7];
     sum_records(rec_old, nrec, o, red);
@@ -620,10 +649,18 @@ static int hmc_row_blocks(int L)
 }
 
 static bool hmc_pairs(int L) { return L % 4 == 0; }
-static int hmc_cols2(int L) { return 2 * (((L >> 2) + kThreads - 1) / kThreads); }
+static int hmc_cols2(int L) { return ((L >> 2) + kThreads - 1) / kThreads; }
+// Row blocks of the pair kernels: runs of up to 32 rows per thread (each run
+// reads the plane rows just above and below it once more, so short runs cost
+// traffic), but at least about 2048 workgroups while L allows, and at most one
+// record per wave within the record buffer.
 static int hmc_row_blocks2(int L)
 {
-    int gy = kHmcMaxRecords / (hmc_cols2(L) * (kThreads / 64));
+    const int cols = hmc_cols2(L);
+    int gy = (2048 + cols - 1) / cols;
+    if (gy < L / 32) gy = L / 32;
+    const int cap = kHmcMaxRecords / (cols * (kThreads / 64));
+    if (gy > cap) gy = cap;
     if (gy > L) gy = L;
     return gy < 1 ? 1 : gy;
 }
@@ -663,11 +700,43 @@ HmcWork hmc_carve(void* work, int L)
     return w;
 }
 
+// The same areas with the record arrays sized for this L only (batches).
+size_t hmc_work_bytes_compact(int L)
+{
+    const size_t n = (size_t)L * (size_t)L;
+    const size_t nrec = (size_t)hmc_records(L), nch = (nrec + 255) / 256;
+    return 256 + 3 * n * sizeof(float) + 2 * (nrec + nch) * 8 * sizeof(double);
+}
+
+HmcWork hmc_carve_compact(void* work, int L)
+{
+    HmcWork w;
+    char* b = (char*)work;
+    const size_t n = (size_t)L * (size_t)L;
+    const size_t nrec = (size_t)hmc_records(L), nch = (nrec + 255) / 256;
+    w.flag = (unsigned*)b;
+    b += 256;
+    w.p = (float*)b;
+    b += n * sizeof(float);
+    w.saved = (float*)b;
+    b += n * sizeof(float);
+    w.p2 = (float*)b;
+    b += n * sizeof(float);
+    w.rec_old = (double*)b;
+    b += nrec * 8 * sizeof(double);
+    w.rec_new = (double*)b;
+    b += nrec * 8 * sizeof(double);
+    w.chunk_old = (double*)b;
+    b += nch * 8 * sizeof(double);
+    w.chunk_new = (double*)b;
+    return w;
+}
+
 bool hmc_multi_supported(int L) { return L >= kMultiTile && L % kMultiTile == 0; }
 
 hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w, int L, double beta, double eps,
                                  int n_md, int steps_per_pass, uint32_t traj, uint32_t k0, uint32_t k1,
-                                 xy_hmc_obs* obs, hipStream_t s)
+                                 xy_hmc_obs* obs, hipStream_t s, const uint32_t* traj_dev)
 {
     const bool pairs2 = hmc_pairs(L);
     const int cols = pairs2 ? hmc_cols2(L) : hmc_cols(L), rb = pairs2 ? hmc_row_blocks2(L) : hmc_row_blocks(L);
@@ -676,10 +745,11 @@ hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w
     const int nchunk = (nrec + 255) / 256;
     const float drift = (float)(eps / (2.0 * 3.14159265358979323846));
     if (pairs2)
-        hipLaunchKernelGGL(k_hmc_ends2<true>, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, 0.0f, cols, rb,
-                           w.rec_old);
+        hipLaunchKernelGGL(k_hmc_ends2<true>, grec, block, 0, s, state, w.p, w.saved, L, traj, traj_dev, k0, k1, 0.0f,
+                           cols, rb, w.rec_old);
     else
-        hipLaunchKernelGGL(k_hmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, k0, k1, cols, rb, w.rec_old);
+        hipLaunchKernelGGL(k_hmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, traj_dev, k0, k1, cols, rb,
+                           w.rec_old);
     float* src = state;
     float* dst = pingpong;
     float* p = w.p;
@@ -715,16 +785,16 @@ hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w
         }
     }
     if (pairs2)
-        hipLaunchKernelGGL(k_hmc_ends2<false>, grec, block, 0, s, src, p, src == state ? nullptr : state, L, traj, k0,
-                           k1, kick_half, cols, rb, w.rec_new);
+        hipLaunchKernelGGL(k_hmc_ends2<false>, grec, block, 0, s, src, p, src == state ? nullptr : state, L, traj,
+                           traj_dev, k0, k1, kick_half, cols, rb, w.rec_new);
     else
         hipLaunchKernelGGL(k_hmc_end, grec, block, 0, s, src, src == state ? nullptr : state, p, L, kick_half, cols,
                            rb, w.rec_new);
     hipError_t e = launch_reduce_chunks(w.rec_old, nrec, w.chunk_old, s);
     if (e == hipSuccess) e = launch_reduce_chunks(w.rec_new, nrec, w.chunk_new, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_hmc_decide, dim3(1), block, 0, s, w.chunk_old, w.chunk_new, nchunk, beta, traj, k0, k1,
-                       w.flag, obs);
+    hipLaunchKernelGGL(k_hmc_decide, dim3(1), block, 0, s, w.chunk_old, w.chunk_new, nchunk, beta, traj, traj_dev,
+                       k0, k1, w.flag, obs);
     const size_t n = (size_t)L * (size_t)L;
     const unsigned nb = (unsigned)((n + kThreads * 8 - 1) / (kThreads * 8));
     hipLaunchKernelGGL(k_hmc_restore, dim3(nb < 4096 ? nb : 4096), block, 0, s, w.flag, w.saved, state, n);

@@ -99,9 +99,14 @@ int hmc_records(int L);
 // `pingpong` a second state-sized buffer; record to obs if not NULL.
 // steps_per_pass > 1 (and L % 32 == 0): leap-frog steps in passes of up to
 // min(steps_per_pass, 8) steps (temporal blocking); else one step per launch.
+// traj_dev != NULL: the trajectory index is read from device memory when the
+// kernels run (graph replays), instead of `traj`.
 hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w, int L, double beta, double eps,
                                  int n_md, int steps_per_pass, uint32_t traj, uint32_t k0, uint32_t k1,
-                                 xy_hmc_obs* obs, hipStream_t s);
+                                 xy_hmc_obs* obs, hipStream_t s, const uint32_t* traj_dev = nullptr);
+// Workspace of one lattice with record arrays sized for its L only (batches).
+size_t hmc_work_bytes_compact(int L);
+HmcWork hmc_carve_compact(void* work, int L);
 bool hmc_multi_supported(int L);
 bool fused_supported(int L, int tile_x, int tile_y, int m);
 

@@ -122,6 +122,9 @@ def _load():
         "xy_test_inject_failure": [i32],
         "xy_sweep_noalloc": [u64, i32, dbl, dbl, i32, u64, i64, i32, vp, sz, vp, vp],
         "xy_kernel_timer": [vp, i32],
+        "xy_batch_hmc_work_bytes": [vp, P(sz)],
+        "xy_batch_hmc": [vp, i64, i32, dbl, vp, sz, vp],
+        "xy_batch_hmc_set_steps_per_pass": [vp, i32],
         "xy_kernel_timer_read": [vp, P(dbl), P(i64)],
     }
     for name, args in sig.items():
@@ -420,6 +423,26 @@ class Batch:
         check(_lib.xy_batch_tempering(self.h, int(n_rounds), int(sweeps_per_round), int(pt_seed), _ptr(out),
                                       _ptr(rungs)), "xy_batch_tempering")
         return out[: int(n_rounds)], rungs[: int(n_rounds)]
+
+    def hmc(self, n_traj: int, n_md: int, eps: float, out=None):
+        """n_traj HMC trajectories of every lattice (one accept per lattice); returns
+        a device tensor (n, n_traj, 9) of xy_hmc_obs records (see hmc_records)."""
+        import torch
+        n = len(self.Ls)
+        if getattr(self, "hmc_work", None) is None:
+            b = ctypes.c_size_t()
+            check(_lib.xy_batch_hmc_work_bytes(self.h, ctypes.byref(b)), "xy_batch_hmc_work_bytes")
+            self.hmc_work = torch.empty((b.value,), dtype=torch.uint8, device=self.state.device)
+        if out is None:
+            out = torch.empty((n, max(int(n_traj), 1), 9), dtype=torch.float64, device=self.state.device)
+        if n_traj > 0:
+            _check_out(out, n * int(n_traj) * 72, self.state.device, "xy_batch_hmc")
+        check(_lib.xy_batch_hmc(self.h, int(n_traj), int(n_md), float(eps), _ptr(self.hmc_work),
+                                _nbytes(self.hmc_work), _ptr(out) if n_traj > 0 else None), "xy_batch_hmc")
+        return out[:, : int(n_traj)] if out.dim() == 3 else out
+
+    def set_hmc_steps_per_pass(self, steps: int):
+        check(_lib.xy_batch_hmc_set_steps_per_pass(self.h, int(steps)), "xy_batch_hmc_set_steps_per_pass")
 
     def params(self):
         n = len(self.Ls)

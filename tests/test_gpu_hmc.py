@@ -238,3 +238,62 @@ def test_trajectory_at_high_seed_and_counter(orc):
     with pytest.raises(xy.XYError) as ei:
         lat.hmc(1, n, eps)
     assert ei.value.code == xy.XY_ERANGE
+
+
+def test_batch_hmc_matches_single_lattices():
+    """xy_batch_hmc on a batch of uneven L (64 x 64 and 32 x 32 multi-step tiles,
+    one-step kernels for L % 32 != 0) at different beta: every lattice's angles and
+    every trajectory record bit for bit those of xy_hmc on a single lattice with
+    the same seed, after the same Metropolis sweeps (shared counter)."""
+    Ls = [64, 36, 128, 32, 96]
+    seeds = [21, 22, 23, 24, 25]
+    betas = [0.9, 1.0, 1.1, 1.2, 0.8]
+    b = xy.Batch(Ls, seeds, betas, [1.0] * len(Ls))
+    b.sweep(3)
+    brec = xy.hmc_records(b.hmc(4, 10, 0.1))
+    assert brec.shape == (len(Ls), 4)
+    assert b.sweep_count == 7
+    b.sweep(2)
+    brec2 = xy.hmc_records(b.hmc(2, 6, 0.12))       # another (n_md, eps): a new graph
+    torch.cuda.synchronize()
+    for i, L in enumerate(Ls):
+        lat = xy.Lattice(L, seed=seeds[i], beta=betas[i], delta=1.0)
+        lat.sweep(3)
+        srec = xy.hmc_records(lat.hmc(4, 10, 0.1))
+        lat.sweep(2)
+        srec2 = xy.hmc_records(lat.hmc(2, 6, 0.12))
+        torch.cuda.synchronize()
+        assert srec.tobytes() == brec[i].tobytes(), (L, srec, brec[i])
+        assert srec2.tobytes() == brec2[i].tobytes(), L
+        assert torch.equal(b.lattice_state(i), lat.state), L
+        assert 0 < int(brec["accepted"][i].sum()) <= 4
+
+
+def test_batch_hmc_first_trajectory_matches_oracle(orc):
+    """From the hot start, the first batched trajectory of each lattice against the
+    FP64 oracle: dH within the single-lattice tolerance, same decision outside the
+    exemption band."""
+    Ls, seeds, beta, eps, n = [32, 64], [3, 4], 1.0, 0.1, 10
+    b = xy.Batch(Ls, seeds, [beta, beta], [1.0, 1.0])
+    rec = xy.hmc_records(b.hmc(1, n, eps))
+    for i, L in enumerate(Ls):
+        phi = orc.hot_start(seeds[i], L, "f32")
+        acc, dH, _ = orc.hmc_trajectory(seeds[i], phi, beta, eps, n, 0)
+        tol = 1e-4 * math.sqrt(L * L / 1024.0) + 1e-5 * abs(dH)
+        assert abs(float(rec["dH"][i, 0]) - dH) < tol, (L, float(rec["dH"][i, 0]), dH)
+        u = orc.hmc_accept_uniform(seeds[i], 0)
+        if abs(math.exp(-dH) - u) > DECISION_EXEMPT:
+            assert bool(rec["accepted"][i, 0]) == acc
+
+
+def test_batch_hmc_rejects_fp16_and_bad_args():
+    b = xy.Batch([32, 64], [1, 2], [1.0, 1.0], [1.0, 1.0], precision="fp16")
+    with pytest.raises(xy.XYError) as ei:
+        b.hmc(1, 4, 0.1)
+    assert ei.value.code == xy.XY_EINVAL
+    b = xy.Batch([32, 64], [1, 2], [1.0, 1.0], [1.0, 1.0])
+    for kw in (dict(n_traj=1, n_md=0, eps=0.1), dict(n_traj=1, n_md=4, eps=float("nan")),
+               dict(n_traj=-1, n_md=4, eps=0.1)):
+        with pytest.raises(xy.XYError) as ei:
+            b.hmc(**kw)
+        assert ei.value.code == xy.XY_EINVAL
