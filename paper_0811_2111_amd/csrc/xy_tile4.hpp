@@ -149,10 +149,11 @@ __device__ __forceinline__ void meas_acc4(MeasAcc4& m, const CS4& b, const CS4& 
 
 // Red half-sweep; O = parity of this thread's red rows (left/right neighbours of
 // entry k are the other colour's entries k + O - 1 and k + O).
-template <int TX, int TY, int NT, int O>
+template <int TX, int TY, int NT, int O, bool KEEP>
 __device__ __forceinline__ int tile4_red(const T1Geom& g, Lds4<Tile4<TX, TY, NT>> cs, __amdgpu_buffer_rsrc_t src,
                                          __amdgpu_buffer_rsrc_t dst, uint32_t sweep, const Params4& p, float4 the,
-                                         int e, int e_row, int e_col, int e_red, int e_k)
+                                         int e, int e_row, int e_col, int e_red, int e_k,
+                                         const float4 (&tr)[Tile4<TX, TY, NT>::NQR][2])
 {
     using S = Tile4<TX, TY, NT>;
     constexpr int FULL = TY / S::RP;
@@ -166,7 +167,16 @@ __device__ __forceinline__ int tile4_red(const T1Geom& g, Lds4<Tile4<TX, TY, NT>
         const int y = g.y0 - 1 + row;
         const int yw = g.edge_tile ? wrapi(y, g.L) : y;
         const unsigned at = (unsigned)yw * (unsigned)g.Hh + (unsigned)(g.kb + 2 * g.s);
-        float4 ta = ld4(src, at), tb = ld4(src, at + 1u);     // reloaded (an L2 hit), not kept across barriers
+        // KEEP: the angles the fill loaded, kept in registers across the barrier;
+        // else reloaded (an L2 hit), so no angles stay live across it
+        float4 ta, tb;
+        if constexpr (KEEP) {
+            ta = tr[q][0];
+            tb = tr[q][1];
+        } else {
+            ta = ld4(src, at);
+            tb = ld4(src, at + 1u);
+        }
         u32x4 w[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) w[r] = philox10(sweep, 0u, 0u, (uint32_t)yw * (uint32_t)g.P + jb, p.k0[r], p.k1[r]);
@@ -215,9 +225,10 @@ __device__ __forceinline__ int tile4_red(const T1Geom& g, Lds4<Tile4<TX, TY, NT>
 }
 
 // Black half-sweep of the interior rows; O = parity of this thread's black rows.
-template <int TX, int TY, int NT, int O, bool MEAS>
+template <int TX, int TY, int NT, int O, bool MEAS, bool KEEP>
 __device__ __forceinline__ int tile4_black(const T1Geom& g, Lds4<Tile4<TX, TY, NT>> cs, __amdgpu_buffer_rsrc_t src,
-                                           __amdgpu_buffer_rsrc_t dst, uint32_t sweep, const Params4& p, MeasAcc4& m)
+                                           __amdgpu_buffer_rsrc_t dst, uint32_t sweep, const Params4& p, MeasAcc4& m,
+                                           const float4 (&tb)[Tile4<TX, TY, NT>::NQB][2])
 {
     using S = Tile4<TX, TY, NT>;
     constexpr int FULL = TY / S::RP;
@@ -230,7 +241,14 @@ __device__ __forceinline__ int tile4_black(const T1Geom& g, Lds4<Tile4<TX, TY, N
         if (!(q < FULL || (black_valid<S>(g, q) && row >= 2 && row < TY + 2))) continue;
         const int y = g.y0 - 2 + row;      // interior: never wraps
         const unsigned at = ((unsigned)g.L + (unsigned)y) * (unsigned)g.Hh + (unsigned)(g.kb + 2 * g.s);
-        float4 t0 = ld4(src, at), t1 = ld4(src, at + 1u);
+        float4 t0, t1;
+        if constexpr (KEEP) {
+            t0 = tb[q][0];
+            t1 = tb[q][1];
+        } else {
+            t0 = ld4(src, at);
+            t1 = ld4(src, at + 1u);
+        }
         u32x4 w[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) w[r] = philox10(sweep, 1u, 0u, (uint32_t)y * (uint32_t)g.P + jb, p.k0[r], p.k1[r]);
@@ -283,8 +301,7 @@ __device__ __forceinline__ void tile4_program(const float4* __restrict__ src, fl
     }
     g.edge_tile = (y0 < 2) || (y0 + TY + 2 > L);
 
-    // fill: (cos, sin) of every loaded entry; the angles themselves are loaded
-    // again where they are updated, so no item's angles stay live across barriers
+    // fill: (cos, sin) of every loaded entry
     float4 tr[S::NQR][2], tb[S::NQB][2];
     const unsigned col = (unsigned)(g.kb + 2 * g.s);
 #pragma unroll
@@ -343,18 +360,24 @@ __device__ __forceinline__ void tile4_program(const float4* __restrict__ src, fl
     if (e < S::NEDGE) cs.put((e_red ? 0 : S::RR) + e_row, e_col, sincos4(the));
     __syncthreads();
 
+    // The unmeasured sweep keeps the loaded angles in registers through both
+    // phases: the tile's LDS already limits a CU to three workgroups, i.e. three
+    // waves per SIMD, so registers up to 168 per lane cost no occupancy, and the
+    // updates then wait on no reload.  The measured sweep, with its sums, has no
+    // registers to spare and reloads them.
+    constexpr bool KEEP = !MEAS;
     MeasAcc4 m;
     int acc = 0;
     const bool red_odd = __builtin_amdgcn_readfirstlane((y0 + g.rt) & 1) != 0;
     if (red_odd)
-        acc += tile4_red<TX, TY, NT, 1>(g, cs, rs, rd, sweep, p, the, e, e_row, e_col, e_red, e_k);
+        acc += tile4_red<TX, TY, NT, 1, KEEP>(g, cs, rs, rd, sweep, p, the, e, e_row, e_col, e_red, e_k, tr);
     else
-        acc += tile4_red<TX, TY, NT, 0>(g, cs, rs, rd, sweep, p, the, e, e_row, e_col, e_red, e_k);
+        acc += tile4_red<TX, TY, NT, 0, KEEP>(g, cs, rs, rd, sweep, p, the, e, e_row, e_col, e_red, e_k, tr);
     __syncthreads();
     if (red_odd)
-        acc += tile4_black<TX, TY, NT, 0, MEAS>(g, cs, rs, rd, sweep, p, m);
+        acc += tile4_black<TX, TY, NT, 0, MEAS, KEEP>(g, cs, rs, rd, sweep, p, m, tb);
     else
-        acc += tile4_black<TX, TY, NT, 1, MEAS>(g, cs, rs, rd, sweep, p, m);
+        acc += tile4_black<TX, TY, NT, 1, MEAS, KEEP>(g, cs, rs, rd, sweep, p, m, tb);
     if constexpr (MEAS) {
         const int lane = tid & 63, wv = tid >> 6;
 #pragma unroll
