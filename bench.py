@@ -55,6 +55,11 @@ VALU_PEAK_TSLOTS = 256 * 128 * 2.4e9 / 1e12
 #   acceptance (mul, exp2, compare)                                                 5.5
 #   three selects                                                                   3
 ALG_SLOTS_PER_UPDATE = 76.0
+# A measured sweep adds the bond and magnetisation sums at every black site (half
+# the updates): 8 fma for the four bond cosines and sines (the left + right and
+# up + down sums are the update's own), 4 subtractions, 4 additions for Mx, My:
+# 8 x 1.14 + 8 = 17.1 slots per black site, 8.56 per update.
+ALG_SLOTS_MEAS_PER_UPDATE = 8.56
 ALG_BYTES_FUSED = 8.0                    # bytes per site-update of one fused sweep: read 4 + write 4 (FP32)
 ALG_BYTES_STREAM = 12.0                  # two half-sweep passes: read both colours, write one, per half
 ALG_BYTES_HMC_STEP = 16.0                # one leap-frog step: read and write the angle and the momentum
@@ -262,6 +267,12 @@ def main():
     if copy_gbs is not None:
         roofline["device_copy_GBs"] = round(copy_gbs, 1)
         roofline["frac_of_device_copy"] = round(achieved_gbs / copy_gbs, 4)
+    # the same launch against the VALU issue rate (the measured sweep's update and
+    # record arithmetic; peak 78.6 T slots/s)
+    slots = (ALG_SLOTS_PER_UPDATE + ALG_SLOTS_MEAS_PER_UPDATE) * upd_per_launch / (per_launch_ms * 1e-3) / 1e12
+    roofline["alu"] = {"achieved": round(slots, 2), "peak": round(VALU_PEAK_TSLOTS, 2), "unit": "T VALU-slot/s",
+                       "frac": round(slots / VALU_PEAK_TSLOTS, 4),
+                       "alg_slots_per_update": ALG_SLOTS_PER_UPDATE + ALG_SLOTS_MEAS_PER_UPDATE}
     out = {
         "metric": "site-updates/sec (Gupd/s) at 1 MI355X; % HBM roofline; batched vs per-lattice speedup",
         "value": round(gupd, 3),
