@@ -571,7 +571,10 @@ struct xy_batch {
     void* h_work;
     xy_hmc_obs* h_obs;
     int64_t h_ntraj;
+    uint64_t h_pgen;
     int32_t hmc_steps;     // leap-frog steps per pass of xy_batch_hmc
+    void* hdesc;           // device copy of the batched-stage descriptors and block offsets
+    uint64_t pgen;         // bumped whenever a lattice's beta or delta changes
 };
 
 static bool blive(const xy_batch* b) { return b && b->magic == kBatchMagic; }
@@ -583,8 +586,10 @@ static void drop_hmc_graph(xy_batch* b)
 {
     if (b->hexec) (void)hipGraphExecDestroy(b->hexec);
     if (b->hgraph) (void)hipGraphDestroy(b->hgraph);
+    if (b->hdesc) (void)hipFree(b->hdesc);
     b->hexec = nullptr;
     b->hgraph = nullptr;
+    b->hdesc = nullptr;
 }
 
 static void release(xy_batch* b)
@@ -855,7 +860,10 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->h_work = nullptr;
     b->h_obs = nullptr;
     b->h_ntraj = -1;
+    b->h_pgen = ~0ull;
     b->hmc_steps = 5;
+    b->hdesc = nullptr;
+    b->pgen = 0;
     b->sched = XY_BATCH_PASSES_WIDE;
     auto fail = [&](int code) {
         release(b);
@@ -1115,6 +1123,7 @@ int xy_batch_tempering(xy_batch* b, int64_t n_rounds, int32_t sweeps_per_round, 
         b->beta[member[k]] = rbeta[k];
         b->delta[member[k]] = rdelta[k];
     }
+    b->pgen += 1;        // graphs that hold a lattice's beta are out of date
     return XY_OK;
 }
 
@@ -1176,18 +1185,78 @@ int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hm
     char* hw = (char*)hmc_work;
     xy_hmc_obs* stage = (xy_hmc_obs*)(hw + staging);
     if (!b->hexec || b->h_nmd != n_md || b->h_eps != eps || b->h_steps != b->hmc_steps || b->h_work != hmc_work ||
-        b->h_obs != obs_dev || b->h_ntraj != n_traj) {
-        // one trajectory of every lattice, the lattices spread over kHmcStreams
-        // branches (greedy by L^2), captured once and replayed per trajectory; the
-        // kernels read the trajectory index from the batch's device counter
+        b->h_obs != obs_dev || b->h_ntraj != n_traj || b->h_pgen != b->pgen) {
+        // one trajectory of every lattice, captured once and replayed per
+        // trajectory; the kernels read the trajectory index from the batch's device
+        // counter.  Lattices with L % 64 == 0 (with passes of several steps) go
+        // through the batched stages, one launch per stage for all of them; the
+        // others are spread over kHmcStreams branches (greedy by L^2) with their
+        // own single-lattice launches.
+        if ((e = hipStreamSynchronize(b->stream)) != hipSuccess)     // a replay may still read the descriptors
+            return xyr::hip_fail(e, "xy_batch_hmc: hipStreamSynchronize");
         drop_hmc_graph(b);
-        if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-            return xyr::hip_fail(e, "xy_batch_hmc: hipStreamBeginCapture");
-        hipError_t le = hipEventRecord(b->ev_fork, b->cap);
-        for (int k = 1; k < kHmcStreams && le == hipSuccess; ++k) le = hipStreamWaitEvent(b->hs[k], b->ev_fork, 0);
+        std::vector<int> fast;
+        if (b->hmc_steps > 1)
+            for (int i = 0; i < b->n; ++i)
+                if (xyk::hmc_batch_supported(b->L[i])) fast.push_back(i);
+        const int nf = (int)fast.size();
+        uint32_t totals[3] = {0, 0, 0};
+        xyk::BhLat* d_desc = nullptr;
+        uint32_t* d_start = nullptr;
+        std::vector<char> isfast(b->n, 0);
         double load[kHmcStreams] = {0.0};
         const size_t eb = sizeof(float);
+        if (nf > 0) {
+            std::vector<xyk::BhLat> hd(nf);
+            std::vector<uint32_t> hs(3 * (size_t)(nf + 1));
+            for (int f = 0; f < nf; ++f) {
+                const int i = fast[f];
+                isfast[i] = 1;
+                const LatDesc& ld = b->desc[i];
+                xyk::BhLat& q = hd[f];
+                q.st = (float*)(b->state + (size_t)ld.off * eb);
+                q.pp = (float*)(b->work + b->lo.pp_off + (size_t)ld.off * eb);
+                q.w = xyk::hmc_carve_compact(hw + off[i], b->L[i]);
+                q.obs = stage + i;
+                q.k0 = ld.key0;
+                q.k1 = ld.key1;
+                xyk::hmc_batch_describe(q, b->L[i], b->beta[i], eps);
+                uint32_t nb[3];
+                xyk::hmc_batch_blocks(b->L[i], nb);
+                for (int g = 0; g < 3; ++g) {
+                    hs[(size_t)g * (nf + 1) + f] = totals[g];
+                    if ((uint64_t)totals[g] + nb[g] > 0x7fffffffull) return XY_ESIZE;
+                    totals[g] += nb[g];
+                }
+                load[0] += (double)b->L[i] * b->L[i];
+            }
+            for (int g = 0; g < 3; ++g) hs[(size_t)g * (nf + 1) + nf] = totals[g];
+            const size_t db = align256(sizeof(xyk::BhLat) * (size_t)nf);
+            if ((e = hipMalloc(&b->hdesc, db + hs.size() * sizeof(uint32_t))) != hipSuccess) {
+                b->hdesc = nullptr;
+                return xyr::hip_fail(e, "xy_batch_hmc: hipMalloc");
+            }
+            d_desc = (xyk::BhLat*)b->hdesc;
+            d_start = (uint32_t*)((char*)b->hdesc + db);
+            if ((e = hipMemcpy(d_desc, hd.data(), sizeof(xyk::BhLat) * (size_t)nf, hipMemcpyHostToDevice)) !=
+                    hipSuccess ||
+                (e = hipMemcpy(d_start, hs.data(), hs.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) !=
+                    hipSuccess) {
+                drop_hmc_graph(b);
+                return xyr::hip_fail(e, "xy_batch_hmc: descriptor copy");
+            }
+        }
+        if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+            drop_hmc_graph(b);
+            return xyr::hip_fail(e, "xy_batch_hmc: hipStreamBeginCapture");
+        }
+        hipError_t le = hipEventRecord(b->ev_fork, b->cap);
+        for (int k = 1; k < kHmcStreams && le == hipSuccess; ++k) le = hipStreamWaitEvent(b->hs[k], b->ev_fork, 0);
+        if (le == hipSuccess && nf > 0)
+            le = xyk::launch_hmc_batch_trajectory(d_desc, d_start, nf, totals, eps, n_md, b->hmc_steps,
+                                                  &ctrl->sweep0, b->cap);
         for (int i = 0; i < b->n && le == hipSuccess; ++i) {
+            if (isfast[i]) continue;
             int k = 0;
             for (int q = 1; q < kHmcStreams; ++q)
                 if (load[q] < load[k]) k = q;
@@ -1213,9 +1282,13 @@ int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hm
         e = hipStreamEndCapture(b->cap, &g);
         if (le != hipSuccess) {
             if (g) (void)hipGraphDestroy(g);
+            drop_hmc_graph(b);
             return xyr::hip_fail(le, "xy_batch_hmc: launch (capture)");
         }
-        if (e != hipSuccess) return xyr::hip_fail(e, "xy_batch_hmc: hipStreamEndCapture");
+        if (e != hipSuccess) {
+            drop_hmc_graph(b);
+            return xyr::hip_fail(e, "xy_batch_hmc: hipStreamEndCapture");
+        }
         b->hgraph = g;
         if ((e = hipGraphInstantiate(&b->hexec, g, nullptr, nullptr, 0)) != hipSuccess) {
             b->hexec = nullptr;
@@ -1228,6 +1301,7 @@ int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hm
         b->h_work = hmc_work;
         b->h_obs = obs_dev;
         b->h_ntraj = n_traj;
+        b->h_pgen = b->pgen;
     }
     hipLaunchKernelGGL(k_bhmc_start, dim3(1), dim3(1), 0, b->stream, ctrl);
     if ((e = hipGetLastError()) != hipSuccess) return xyr::hip_fail(e, "xy_batch_hmc: launch");

@@ -21,6 +21,7 @@
 
 #include "xy_device.hpp"
 #include "xy_launch.hpp"
+#include "xy_reduce.hpp"
 
 using namespace xyd;
 
@@ -325,15 +326,15 @@ k_hmc_multi(const float* __restrict__ src, float* __restrict__ dst, const float*
 // so that 64 x 64 tiles keep two workgroups of 1024 threads on a CU.  The grown
 // tile is 1.27 times the tile at T = 64, K = 4 (1.56 at T = 32), so less of the
 // work goes to the halo.  Per site the arithmetic is that of k_hmc_step.
+// The pass on tile b (after the XCD remap) of one lattice; cs: the LDS buffer(s),
+// (SINGLE ? 1 : 2) (T + 2K)^2 float2.
 template <int K, int T, int NT, bool SINGLE>
-__global__ void __launch_bounds__(NT)
-k_hmc_multi_g(const float* __restrict__ src, float* __restrict__ dst, const float* __restrict__ psrc,
-              float* __restrict__ pdst, int L, float kick0, float kick, float drift)
+__device__ __forceinline__ void multi_g_body(const float* __restrict__ src, float* __restrict__ dst,
+                                             const float* __restrict__ psrc, float* __restrict__ pdst, int L,
+                                             float kick0, float kick, float drift, int b, float2* cs)
 {
     constexpr int E = T + 2 * K, NE = E * E, M = (NE + NT - 1) / NT;
-    __shared__ float2 cs[SINGLE ? 1 : 2][NE];
     const int Hh = L >> 1, nt = L / T;
-    const int b = (int)xcd_band(blockIdx.x, gridDim.x);
     const int ty = b / nt, tx = b - ty * nt;
     const int x0 = tx * T - K, y0 = ty * T - K;
     float th[M], pm[M];
@@ -355,14 +356,14 @@ k_hmc_multi_g(const float* __restrict__ src, float* __restrict__ dst, const floa
         if (i < NE) {
             float sn, cn;
             sincos_turn(th[m], sn, cn);
-            cs[0][i] = make_float2(cn, sn);
+            cs[i] = make_float2(cn, sn);
         }
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-        const float2* cur = cs[SINGLE ? 0 : (q & 1)];
-        float2* nxt = cs[SINGLE ? 0 : ((q + 1) & 1)];
+        const float2* cur = cs + (SINGLE ? 0 : (q & 1)) * NE;
+        float2* nxt = cs + (SINGLE ? 0 : ((q + 1) & 1)) * NE;
         const float kq = q == 0 ? kick0 : kick;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -408,6 +409,17 @@ k_hmc_multi_g(const float* __restrict__ src, float* __restrict__ dst, const floa
             }
         }
     }
+}
+
+template <int K, int T, int NT, bool SINGLE>
+__global__ void __launch_bounds__(NT)
+k_hmc_multi_g(const float* __restrict__ src, float* __restrict__ dst, const float* __restrict__ psrc,
+              float* __restrict__ pdst, int L, float kick0, float kick, float drift)
+{
+    constexpr int NE = (T + 2 * K) * (T + 2 * K);
+    __shared__ float2 cs[(SINGLE ? 1 : 2) * NE];
+    multi_g_body<K, T, NT, SINGLE>(src, dst, psrc, pdst, L, kick0, kick, drift,
+                                   (int)xcd_band(blockIdx.x, gridDim.x), cs);
 }
 
 constexpr int kMaxStepsPerPass = 8;
@@ -505,15 +517,13 @@ __device__ __forceinline__ void pair_nb(const PairCS& own, const PairCS& u, cons
     na.cd = d.c0; na.sd = d.s0; nb.cd = d.c1; nb.sd = d.s1;
 }
 
+// The pass on record block t (after the XCD remap) of one lattice.
 template <bool BEGIN>
-__global__ void __launch_bounds__(kThreads)
-k_hmc_ends2(const float* __restrict__ st, float* __restrict__ p, float* __restrict__ copy, int L, uint32_t traj,
-            const uint32_t* __restrict__ traj_dev, uint32_t k0, uint32_t k1, float nbeta_kick, int cols, int rb,
-            double* __restrict__ rec)
+__device__ __forceinline__ void ends2_body(const float* __restrict__ st, float* __restrict__ p,
+                                           float* __restrict__ copy, int L, uint32_t traj, uint32_t k0, uint32_t k1,
+                                           float nbeta_kick, int cols, int rb, double* __restrict__ rec, unsigned t)
 {
-    if (BEGIN && traj_dev) traj = *traj_dev;
     const int Hh = L >> 1, J = Hh >> 1;
-    const unsigned t = xcd_band(blockIdx.x, gridDim.x);
     const int col = (int)(t % (unsigned)cols);
     const int j = col * kThreads + threadIdx.x;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
@@ -576,6 +586,16 @@ k_hmc_ends2(const float* __restrict__ st, float* __restrict__ p, float* __restri
     write_record(v, rec, t);              // every lane reaches the wave sums
 }
 
+template <bool BEGIN>
+__global__ void __launch_bounds__(kThreads)
+k_hmc_ends2(const float* __restrict__ st, float* __restrict__ p, float* __restrict__ copy, int L, uint32_t traj,
+            const uint32_t* __restrict__ traj_dev, uint32_t k0, uint32_t k1, float nbeta_kick, int cols, int rb,
+            double* __restrict__ rec)
+{
+    if (BEGIN && traj_dev) traj = *traj_dev;
+    ends2_body<BEGIN>(st, p, copy, L, traj, k0, k1, nbeta_kick, cols, rb, rec, xcd_band(blockIdx.x, gridDim.x));
+}
+
 // Sum of one set of records in a fixed order (thread t: records t, t + 256, ...,
 // then the wave sums and the four waves in order); thread 0 gets the totals.
 __device__ void sum_records(const double* __restrict__ rec, int nrec, double out[7], double* red)
@@ -596,6 +616,29 @@ __device__ void sum_records(const double* __restrict__ rec, int nrec, double out
     __syncthreads();
 }
 
+// dH = H_new - H_old from the two sums (slot 6 = sum p^2/2, slots 0, 1 = the bond
+// cosines, H = K + beta E with E = -(Cx + Cy)); accept iff u < exp(-dH), u from
+// Philox (traj, 0, 3, 0).
+__device__ __forceinline__ void decide_core(const double o[7], const double n[7], double beta, uint32_t traj,
+                                            uint32_t k0, uint32_t k1, unsigned* __restrict__ flag,
+                                            xy_hmc_obs* __restrict__ obs)
+{
+    const double h_old = o[6] - beta * (o[0] + o[1]);
+    const double h_new = n[6] - beta * (n[0] + n[1]);
+    const double dH = h_new - h_old;
+    const u32x4 r = philox10(traj, 0u, 3u, 0u, k0, k1);
+    const double u = (double)u01(r.x);           // exact in FP32
+    const unsigned acc = u < exp(-dH) ? 1u : 0u;
+    *flag = acc;
+    if (obs) {
+        const double* s = acc ? n : o;
+        obs->traj = (uint64_t)traj + 1u;
+        obs->accepted = acc;
+        obs->dH = dH;
+        obs->cx = s[0]; obs->cy = s[1]; obs->ix = s[2]; obs->iy = s[3]; obs->mx = s[4]; obs->my = s[5];
+    }
+}
+
 // Metropolis step of the trajectory: one workgroup, on the chunk sums of the two
 // record sets.
 __global__ void __launch_bounds__(kThreads)
@@ -608,22 +651,7 @@ k_hmc_decide(const double* __restrict__ rec_old, const double* __restrict__ rec_
     double o[7], n[7];
     sum_records(rec_old, nrec, o, red);
     sum_records(rec_new, nrec, n, red);
-    if (threadIdx.x == 0) {
-        const double h_old = o[6] - beta * (o[0] + o[1]);
-        const double h_new = n[6] - beta * (n[0] + n[1]);
-        const double dH = h_new - h_old;
-        const u32x4 r = philox10(traj, 0u, 3u, 0u, k0, k1);
-        const double u = (double)u01(r.x);           // exact in FP32
-        const unsigned acc = u < exp(-dH) ? 1u : 0u;
-        *flag = acc;
-        if (obs) {
-            const double* s = acc ? n : o;
-            obs->traj = (uint64_t)traj + 1u;
-            obs->accepted = acc;
-            obs->dH = dH;
-            obs->cx = s[0]; obs->cy = s[1]; obs->ix = s[2]; obs->iy = s[3]; obs->mx = s[4]; obs->my = s[5];
-        }
-    }
+    if (threadIdx.x == 0) decide_core(o, n, beta, traj, k0, k1, flag, obs);
 }
 
 // Rejected trajectory: the saved angles back into the state.
@@ -633,6 +661,140 @@ k_hmc_restore(const unsigned* __restrict__ flag, const float* __restrict__ saved
     if (*flag) return;
     for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kThreads)
         st[i] = saved[i];
+}
+
+// ---------------------------------------------------------------- batches
+// One launch per stage over all lattices of a batch.  A stage's grid is the
+// lattices' single-lattice grids one after another, each padded to a multiple of
+// 8 workgroups (so that each lattice's first workgroup goes to XCD 0 and the XCD
+// remap gives it the same bands as alone); a workgroup finds its lattice by
+// bisection over the stage's block offsets and runs the single-lattice pass on
+// its local index.
+
+// Lattice i with start[i] <= blk < start[i + 1].
+__device__ __forceinline__ int bh_find(const uint32_t* __restrict__ start, int n, uint32_t blk)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Trajectory ends: BEGIN draws the momenta, saves the angles and writes the H_old
+// records; else the final half kick from the angles and momenta the leap-frog
+// passes left in the second buffers (parity odd, angles also copied back into the
+// state) or the first, and the H_new records.
+template <bool BEGIN>
+__global__ void __launch_bounds__(kThreads)
+k_bhmc_ends(const BhLat* __restrict__ d, const uint32_t* __restrict__ start, int n,
+            const uint32_t* __restrict__ traj_dev, int parity)
+{
+    const int i = bh_find(start, n, blockIdx.x);
+    const BhLat& q = d[i];
+    const unsigned nb = (unsigned)(q.cols * q.rb), lb = blockIdx.x - start[i];
+    if (lb >= nb) return;
+    const unsigned t = xcd_band(lb, nb);
+    if constexpr (BEGIN)
+        ends2_body<true>(q.st, q.w.p, q.w.saved, q.L, *traj_dev, q.k0, q.k1, 0.0f, q.cols, q.rb, q.w.rec_old, t);
+    else
+        ends2_body<false>(parity ? q.pp : q.st, parity ? q.w.p2 : q.w.p, parity ? q.st : nullptr, q.L, 0u, q.k0,
+                          q.k1, q.kick_half, q.cols, q.rb, q.w.rec_new, t);
+}
+
+// K leap-frog steps of every lattice on 64 x 64 tiles; parity odd: the angles and
+// momenta are read from the second buffers and written to the first.
+template <int K>
+__global__ void __launch_bounds__(kWideThreads)
+k_bhmc_multi(const BhLat* __restrict__ d, const uint32_t* __restrict__ start, int n, int parity, int first,
+             float drift)
+{
+    constexpr int NE = (kWideTile + 2 * K) * (kWideTile + 2 * K);
+    __shared__ float2 cs[NE];
+    const int i = bh_find(start, n, blockIdx.x);
+    const BhLat& q = d[i];
+    const int nt = q.L / kWideTile;
+    const unsigned nb = (unsigned)(nt * nt), lb = blockIdx.x - start[i];
+    if (lb >= nb) return;
+    multi_g_body<K, kWideTile, kWideThreads, true>(parity ? q.pp : q.st, parity ? q.st : q.pp,
+                                                   parity ? q.w.p2 : q.w.p, parity ? q.w.p : q.w.p2, q.L,
+                                                   first ? q.kick_half : q.kick_full, q.kick_full, drift,
+                                                   (int)xcd_band(lb, nb), cs);
+}
+
+// One lattice's records summed as the single-lattice trajectory sums them: chunks
+// of 256 records as k_reduce_chunks forms them (into ch, LDS), then the chunk sums
+// as k_hmc_decide forms them.  Thread 0 gets the totals.
+__device__ void bh_sum(const double* __restrict__ rec, int nrec, double* ch, double out[7], double* red)
+{
+    const int nch = (nrec + 255) / 256;
+    for (int c = 0; c < nch; ++c) {
+        const int i = c * 256 + threadIdx.x;
+        double v[7] = {0, 0, 0, 0, 0, 0, 0};
+        if (i < nrec) {
+            const double* r = rec + (size_t)i * 8;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) v[k] = r[k];
+        }
+        block_sum7_256(v, red);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) ch[c * 8 + k] = v[k];
+            ch[c * 8 + 7] = 0.0;
+        }
+        __syncthreads();
+    }
+    sum_records(ch, nch, out, red);
+}
+
+// Metropolis step of every lattice: workgroup i on lattice i.
+__global__ void __launch_bounds__(kThreads)
+k_bhmc_decide(const BhLat* __restrict__ d, const uint32_t* __restrict__ traj_dev)
+{
+    __shared__ double red[4 * 7];
+    __shared__ double ch[kHmcMaxChunks * 8];
+    const BhLat& q = d[blockIdx.x];
+    double o[7], nn[7];
+    bh_sum(q.w.rec_old, q.nrec, ch, o, red);
+    bh_sum(q.w.rec_new, q.nrec, ch, nn, red);
+    if (threadIdx.x == 0) decide_core(o, nn, q.beta, *traj_dev, q.k0, q.k1, q.w.flag, q.obs);
+}
+
+// Rejected trajectories: the saved angles back into the state.
+__global__ void __launch_bounds__(kThreads)
+k_bhmc_restore(const BhLat* __restrict__ d, const uint32_t* __restrict__ start, int n)
+{
+    const int i = bh_find(start, n, blockIdx.x);
+    const BhLat& q = d[i];
+    if (*q.w.flag) return;
+    const size_t ns = (size_t)q.L * (size_t)q.L;
+    const size_t stride = (size_t)(start[i + 1] - start[i]) * kThreads;
+    for (size_t j = (size_t)(blockIdx.x - start[i]) * kThreads + threadIdx.x; j < ns; j += stride)
+        q.st[j] = q.w.saved[j];
+}
+
+template <int K>
+static void launch_bmulti(uint32_t nb, hipStream_t s, const BhLat* d, const uint32_t* start, int n, int parity,
+                          int first, float drift)
+{
+    hipLaunchKernelGGL(k_bhmc_multi<K>, dim3(nb), dim3(kWideThreads), 0, s, d, start, n, parity, first, drift);
+}
+
+static void launch_bmulti_k(int k, uint32_t nb, hipStream_t s, const BhLat* d, const uint32_t* start, int n,
+                            int parity, int first, float drift)
+{
+    switch (k) {
+    case 1: launch_bmulti<1>(nb, s, d, start, n, parity, first, drift); break;
+    case 2: launch_bmulti<2>(nb, s, d, start, n, parity, first, drift); break;
+    case 3: launch_bmulti<3>(nb, s, d, start, n, parity, first, drift); break;
+    case 4: launch_bmulti<4>(nb, s, d, start, n, parity, first, drift); break;
+    case 5: launch_bmulti<5>(nb, s, d, start, n, parity, first, drift); break;
+    case 6: launch_bmulti<6>(nb, s, d, start, n, parity, first, drift); break;
+    case 7: launch_bmulti<7>(nb, s, d, start, n, parity, first, drift); break;
+    default: launch_bmulti<8>(nb, s, d, start, n, parity, first, drift); break;
+    }
 }
 
 }  // namespace
@@ -798,6 +960,55 @@ hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w
     const size_t n = (size_t)L * (size_t)L;
     const unsigned nb = (unsigned)((n + kThreads * 8 - 1) / (kThreads * 8));
     hipLaunchKernelGGL(k_hmc_restore, dim3(nb < 4096 ? nb : 4096), block, 0, s, w.flag, w.saved, state, n);
+    return hipGetLastError();
+}
+
+bool hmc_batch_supported(int L) { return L >= kWideTile && L % kWideTile == 0; }
+
+void hmc_batch_describe(BhLat& d, int L, double beta, double eps)
+{
+    d.L = L;
+    d.beta = beta;
+    d.cols = hmc_cols2(L);
+    d.rb = hmc_row_blocks2(L);
+    d.nrec = hmc_records(L);
+    d.kick_half = (float)(-beta * 0.5 * eps);
+    d.kick_full = (float)(-beta * eps);
+}
+
+static uint32_t pad8(uint32_t v) { return (v + 7u) & ~7u; }
+
+void hmc_batch_blocks(int L, uint32_t nb[3])
+{
+    nb[0] = pad8((uint32_t)(hmc_cols2(L) * hmc_row_blocks2(L)));
+    nb[1] = pad8((uint32_t)((L / kWideTile) * (L / kWideTile)));
+    const size_t n = (size_t)L * (size_t)L;
+    const size_t r = (n + kThreads * 8 - 1) / (kThreads * 8);
+    nb[2] = pad8((uint32_t)(r < 4096 ? r : 4096));
+}
+
+hipError_t launch_hmc_batch_trajectory(const BhLat* d, const uint32_t* start, int n, const uint32_t totals[3],
+                                       double eps, int n_md, int steps_per_pass, const uint32_t* traj_dev,
+                                       hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const uint32_t* s_ends = start;
+    const uint32_t* s_pass = start + (n + 1);
+    const uint32_t* s_rest = start + 2 * (n + 1);
+    const float drift = (float)(eps / (2.0 * 3.14159265358979323846));
+    const dim3 block(kThreads);
+    hipLaunchKernelGGL(k_bhmc_ends<true>, dim3(totals[0]), block, 0, s, d, s_ends, n, traj_dev, 0);
+    const int kmax = steps_per_pass < kMaxStepsPerPass ? steps_per_pass : kMaxStepsPerPass;
+    int parity = 0;
+    for (int q = 0; q < n_md;) {
+        const int k = n_md - q < kmax ? n_md - q : kmax;
+        launch_bmulti_k(k, totals[1], s, d, s_pass, n, parity, q == 0, drift);
+        parity ^= 1;
+        q += k;
+    }
+    hipLaunchKernelGGL(k_bhmc_ends<false>, dim3(totals[0]), block, 0, s, d, s_ends, n, traj_dev, parity);
+    hipLaunchKernelGGL(k_bhmc_decide, dim3((unsigned)n), block, 0, s, d, traj_dev);
+    hipLaunchKernelGGL(k_bhmc_restore, dim3(totals[2]), block, 0, s, d, s_rest, n);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 
 #include "xy_device.hpp"
 #include "xy_launch.hpp"
+#include "xy_reduce.hpp"
 
 using namespace xyd;
 
@@ -288,20 +289,8 @@ hipError_t launch_measure(const void* st, int L, int precision, double* partials
 // Fixed-order reduction of nparts partial records (8 doubles: six sums, accepts,
 // unused) -> one xy_obs.  Large counts take two levels: k_reduce_chunks sums
 // consecutive chunks of 256 records (thread t takes record t of its chunk, then a
-// fixed tree), k_finalize sums the chunk results.  Both levels are deterministic.
-__device__ __forceinline__ void block_sum7_256(double v[7], double* red /* [4][7] */)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int q = 0; q < 7; ++q) v[q] = wave_sum(v[q]);
-    if (lane == 0)
-#pragma unroll
-        for (int q = 0; q < 7; ++q) red[wid * 7 + q] = v[q];
-    __syncthreads();
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int q = 0; q < 7; ++q) v[q] = (red[q] + red[7 + q]) + (red[14 + q] + red[21 + q]);
-}
+// fixed tree, block_sum7_256), k_finalize sums the chunk results.  Both levels are
+// deterministic.
 
 __global__ void __launch_bounds__(256)
 k_reduce_chunks(const double* __restrict__ partials, int nparts, double* __restrict__ out)

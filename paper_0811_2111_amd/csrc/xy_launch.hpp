@@ -108,6 +108,34 @@ hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w
 size_t hmc_work_bytes_compact(int L);
 HmcWork hmc_carve_compact(void* work, int L);
 bool hmc_multi_supported(int L);
+
+// One trajectory of many lattices, one launch per stage over all of them
+// (batches).  Lattice i's numbers and arithmetic are those of
+// launch_hmc_trajectory on it alone with the same steps per pass (> 1), so each
+// lattice is bit for bit the single-lattice trajectory.
+struct BhLat {
+    float* st;          // the lattice's angles
+    float* pp;          // its second angle buffer
+    HmcWork w;          // its HMC areas (hmc_carve_compact)
+    xy_hmc_obs* obs;    // where its trajectory record goes (may be NULL)
+    double beta;
+    int L, cols, rb, nrec;
+    uint32_t k0, k1;
+    float kick_half, kick_full;   // -beta eps / 2, -beta eps (FP32, as launch_hmc_trajectory forms them)
+};
+// Lattices this path takes: L % 64 == 0 (64 x 64 leap-frog tiles, pair ends).
+bool hmc_batch_supported(int L);
+// Fill the geometry fields of d (cols, rb, nrec, kicks) for lattice L at beta, eps.
+void hmc_batch_describe(BhLat& d, int L, double beta, double eps);
+// Workgroups lattice L takes in each stage grid: [0] ends, [1] leap-frog pass,
+// [2] restore (each a multiple of 8, so that every lattice starts on XCD 0).
+void hmc_batch_blocks(int L, uint32_t nb[3]);
+// d: n descriptors in device memory; start: 3 (n + 1) block offsets in device
+// memory (stage s, lattice i at start[s (n + 1) + i], each stage's total last),
+// totals the three grid sizes; traj_dev: the trajectory index in device memory.
+hipError_t launch_hmc_batch_trajectory(const BhLat* d, const uint32_t* start, int n, const uint32_t totals[3],
+                                       double eps, int n_md, int steps_per_pass, const uint32_t* traj_dev,
+                                       hipStream_t s);
 bool fused_supported(int L, int tile_x, int tile_y, int m);
 
 // Fill n u64 words with zero (kernel, not a memset node: safe inside graphs).

@@ -297,3 +297,60 @@ def test_batch_hmc_rejects_fp16_and_bad_args():
         with pytest.raises(xy.XYError) as ei:
             b.hmc(**kw)
         assert ei.value.code == xy.XY_EINVAL
+
+
+def test_batch_hmc_stages_match_single_lattices():
+    """A batch whose lattices all take the batched stages (L % 64 == 0: one launch
+    per stage for every lattice), with passes of 5, 5 and 2 leap-frog steps and
+    then of 3, 3 and 1: each lattice's angles and records bit for bit those of
+    xy_hmc on the single lattice."""
+    Ls = [64, 192, 128, 64, 256, 320]
+    seeds = [31 + i for i in range(len(Ls))]
+    betas = [0.85, 1.0, 1.15, 1.3, 0.95, 1.05]
+    b = xy.Batch(Ls, seeds, betas, [1.0] * len(Ls))
+    b.sweep(5)
+    brec = xy.hmc_records(b.hmc(3, 12, 0.08))
+    b.set_hmc_steps_per_pass(3)
+    brec2 = xy.hmc_records(b.hmc(2, 7, 0.1))
+    torch.cuda.synchronize()
+    for i, L in enumerate(Ls):
+        lat = xy.Lattice(L, seed=seeds[i], beta=betas[i], delta=1.0)
+        lat.sweep(5)
+        srec = xy.hmc_records(lat.hmc(3, 12, 0.08))
+        srec2 = xy.hmc_records(lat.hmc(2, 7, 0.1))
+        torch.cuda.synchronize()
+        assert srec.tobytes() == brec[i].tobytes(), (L, srec, brec[i])
+        assert srec2.tobytes() == brec2[i].tobytes(), L
+        assert torch.equal(b.lattice_state(i), lat.state), L
+    assert 0 < int(brec["accepted"].sum()) < brec["accepted"].size + 1
+
+
+def test_batch_hmc_follows_tempering_betas():
+    """Tempering moves betas between lattices; a later xy_batch_hmc call with the
+    same arguments as an earlier one must use the new betas: each lattice bit for
+    bit a single lattice attached to its state at its new beta."""
+    Ls = [64, 64, 64, 128, 128, 96]
+    seeds = [51 + i for i in range(len(Ls))]
+    betas = [1.0, 1.004, 1.008, 1.0, 1.003, 1.0]     # close rungs: exchanges are likely
+    b = xy.Batch(Ls, seeds, betas, [1.0] * len(Ls))
+    b.hmc(1, 6, 0.1)                          # the graph of this (n_traj, n_md, eps)
+    moved = False
+    for r in range(8):
+        b.tempering(4, 5, pt_seed=7 + r)
+        nb, _ = b.params()
+        if nb != betas:
+            moved = True
+            break
+    assert moved, "no exchange in 32 rounds"
+    nb, nd = b.params()
+    count = b.sweep_count
+    torch.cuda.synchronize()
+    states = [b.lattice_state(i).clone() for i in range(len(Ls))]
+    brec = xy.hmc_records(b.hmc(1, 6, 0.1))
+    torch.cuda.synchronize()
+    for i, L in enumerate(Ls):
+        lat = xy.Lattice(L, seed=seeds[i], beta=nb[i], delta=nd[i], state=states[i], sweep=count)
+        srec = xy.hmc_records(lat.hmc(1, 6, 0.1))
+        torch.cuda.synchronize()
+        assert srec.tobytes() == brec[i].tobytes(), (i, L, nb[i])
+        assert torch.equal(b.lattice_state(i), lat.state), L
