@@ -311,7 +311,12 @@ int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
  * lattice), so every lattice follows bit for bit the trajectory that xy_hmc
  * gives a single lattice with the same seed, beta, counter, n_md, eps and leap-
  * frog steps per pass.  One trajectory of all lattices is captured once into a
- * HIP graph (lattices spread over four concurrent branches) and replayed.
+ * HIP graph and replayed: with passes of several leap-frog steps, the lattices
+ * with L % 64 == 0 share one launch per stage of the trajectory (ends, passes,
+ * decide, restore); the others run their own launches, spread over four
+ * concurrent branches.  The graph is rebuilt when n_traj, n_md, eps, the steps
+ * per pass, the workspace or obs_dev change, and after xy_batch_tempering has
+ * moved betas between lattices.
  * hmc_work: caller-owned device memory of xy_batch_hmc_work_bytes bytes (per
  * lattice: momenta, second momenta, saved angles, partial records; then one
  * staging record per lattice); the batch workspace's ping-pong area holds the
