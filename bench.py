@@ -152,7 +152,8 @@ def parse():
                     help="fixed plan 'kind,tile_x,tile_y,sweeps_per_pass' instead of autotuning")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc", "quad", "fp16", "tempering", "small"],
+    ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc", "hmc_batch", "quad", "fp16", "tempering",
+                                           "small"],
                     default="l16384",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
     ap.add_argument("--schedule", type=int, default=None,
@@ -393,6 +394,16 @@ def profile_leg(args, stream):
         ms = timed(lambda: lat.hmc(args.steps, hc["n_md"], hc["eps"]), stream)
         print(json.dumps({"workload": "HMC L16384", "trajectories": args.steps, "ms": ms,
                           "g_site_steps_s": float(hc["L"]) ** 2 * hc["n_md"] * args.steps / (ms * 1e-3) / 1e9}))
+    elif args.workload == "hmc_batch":
+        hb = workloads.HMC_SCAN
+        sc = workloads.temperature_scan()
+        bh = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+        bh.sweep(args.warmup)
+        bh.hmc(1, hb["n_md"], hb["eps"])
+        ms = timed(lambda: bh.hmc(args.steps, hb["n_md"], hb["eps"]), stream)
+        sites = sum(L * L for L in sc["Ls"])
+        print(json.dumps({"workload": "batched HMC scan", "trajectories": args.steps, "ms": ms,
+                          "g_site_steps_s": float(sites) * hb["n_md"] * args.steps / (ms * 1e-3) / 1e9}))
     elif args.workload == "quad":
         qc = workloads.QUAD_4096
         qd = xy.Quad(qc["L"], qc["seeds"], qc["betas"], [qc["delta"]] * 4)
