@@ -5,8 +5,11 @@ Each lattice follows the oracle's Metropolis trajectory bit for bit until a
 near-threshold decision (the single-lattice parity rule); the exchange decisions
 use the same Philox uniform and FP64 energies that agree to ~1e-9 relative, so
 the rung assignments agree round by round until either kind of near-threshold
-event.  A round whose accept counts differ marks such an event and ends the
-comparison.
+event.  A round whose accept counts differ ends the comparison, after a check
+that a near-threshold Metropolis decision caused it: the batch is run again to
+the start of that round and each such lattice is swept from its device state,
+one sweep at a time, beside the oracle's diagnostic sweep of the same state;
+they must part, and only at near-threshold sites.
 """
 from __future__ import annotations
 
@@ -15,6 +18,8 @@ import math
 import numpy as np
 import pytest
 import torch
+
+from gpu_helpers import exempt_mask, natural
 
 pytestmark = pytest.mark.gpu
 
@@ -26,9 +31,37 @@ else:  # collected on CPU-only machines; skipped by the marker filter
 SWAP_EXEMPT = 1e-6
 
 
-def compare_ladder(orc, recs, rungs, idx, seeds, L, betas, deltas, pt_seed, ladder, K):
+def assert_near_threshold(orc, remake, r, lattices, seeds, L, K, pt_seed):
+    """Round r's accept counts differ for `lattices`: from each one's device state
+    at the start of round r (the batch run again for r rounds), its K sweeps of
+    the round, device and oracle side by side, must part at a sweep, and only at
+    near-threshold sites (or the black sites next to one)."""
+    b = remake()
+    if r:
+        b.tempering(r, K, pt_seed)
+    beta_now, delta_now = b.params()
+    torch.cuda.synchronize()
+    for i in lattices:
+        lat = xy.Lattice(L, seed=seeds[i], beta=beta_now[i], delta=delta_now[i],
+                         state=b.lattice_state(i).clone(), sweep=r * K)
+        th = natural(lat.state)
+        parted = False
+        for s in range(K):
+            diag = orc.sweep(seeds[i], th, beta_now[i], delta_now[i], r * K + s, prec="f32", diagnostics=True)
+            lat.sweep(1)
+            dev = natural(lat.state)
+            ex = exempt_mask(diag, L)
+            np.testing.assert_array_equal(dev[~ex], th[~ex])
+            if not np.array_equal(dev, th):
+                parted = True
+                break
+        assert parted, ("round %d: accept counts differ with no near-threshold decision" % r, i)
+
+
+def compare_ladder(orc, recs, rungs, idx, seeds, L, betas, deltas, pt_seed, ladder, K, remake=None):
     """Device records/rungs of the lattices idx (one ladder, in rung order at the
-    start) against the oracle; returns the number of rounds compared."""
+    start) against the oracle; returns the number of rounds compared.  remake()
+    builds the batch afresh (for the near-threshold check of a stopping round)."""
     M = len(idx)
     phi = np.ascontiguousarray(np.stack([orc.hot_start(seeds[i], L, "f32") for i in idx]))
     member = np.arange(M, dtype=np.int32)
@@ -39,6 +72,9 @@ def compare_ladder(orc, recs, rungs, idx, seeds, L, betas, deltas, pt_seed, ladd
     for r in range(R):
         acc_d = np.array([int(dev["n_accept"][r, i]) for i in idx])
         if not np.array_equal(acc_d, orec[r, :, 2].astype(np.int64)):
+            assert remake is not None, "round %d: accept counts differ" % r
+            differ = [i for m, i in enumerate(idx) if acc_d[m] != int(orec[r, m, 2])]
+            assert_near_threshold(orc, remake, r, differ, seeds, L, K, pt_seed)
             return r                                       # a near-threshold Metropolis decision
         assert np.array_equal(rg[r, idx], orung[r]), (r, rg[r, idx], orung[r])
         for m, i in enumerate(idx):
@@ -57,11 +93,30 @@ def compare_ladder(orc, recs, rungs, idx, seeds, L, betas, deltas, pt_seed, ladd
 
 def test_single_ladder_matches_oracle(orc):
     L, seeds, betas, deltas = 16, [30, 31, 32, 33], [0.6, 0.8, 1.0, 1.2], [1.0] * 4
-    b = xy.Batch([L] * 4, seeds, betas, deltas)
+    def remake():
+        return xy.Batch([L] * 4, seeds, betas, deltas)
+    b = remake()
     recs, rungs = b.tempering(12, 2, 77)
-    n = compare_ladder(orc, recs, rungs, [0, 1, 2, 3], seeds, L, betas, deltas, 77, 0, 2)
+    n = compare_ladder(orc, recs, rungs, [0, 1, 2, 3], seeds, L, betas, deltas, 77, 0, 2, remake)
     assert n >= 6, n                   # these seeds meet no near-threshold event in 12 rounds
     assert np.any(rungs.cpu().numpy() != np.arange(4))        # some exchange happened
+
+
+def test_stop_without_near_threshold_decision_is_caught(orc):
+    """The stopping-round check itself: an accept count changed by one in the
+    host copy of round 3's records (no near-threshold decision behind it) must be
+    reported, not taken as the end of the comparison."""
+    L, seeds, betas, deltas = 16, [30, 31, 32, 33], [0.6, 0.8, 1.0, 1.2], [1.0] * 4
+
+    def remake():
+        return xy.Batch([L] * 4, seeds, betas, deltas)
+    b = remake()
+    recs, rungs = b.tempering(6, 2, 77)
+    bad = recs.clone()
+    bad.view(torch.int64)[3, 1, 1] += 1    # n_accept (xy_obs word 1, a u64) of lattice 1 in round 3
+    assert compare_ladder(orc, recs, rungs, [0, 1, 2, 3], seeds, L, betas, deltas, 77, 0, 2, remake) >= 4
+    with pytest.raises(AssertionError, match="no near-threshold decision"):
+        compare_ladder(orc, bad, rungs, [0, 1, 2, 3], seeds, L, betas, deltas, 77, 0, 2, remake)
 
 
 def test_equal_temperatures_cycle():
@@ -82,12 +137,14 @@ def test_two_ladders_of_different_L(orc):
     seeds = [50, 51, 52, 53, 54]
     betas = [1.0, 0.9, 0.7, 1.1, 0.8]
     deltas = [1.0, 1.1, 0.9, 1.2, 1.0]
-    b = xy.Batch(Ls, seeds, betas, deltas)
+    def remake():
+        return xy.Batch(Ls, seeds, betas, deltas)
+    b = remake()
     recs, rungs = b.tempering(8, 2, 99)
     for ladder, L in enumerate((16, 32)):
         idx = sorted([i for i in range(5) if Ls[i] == L], key=lambda i: (betas[i], i))
         n = compare_ladder(orc, recs, rungs, idx, seeds, L, [betas[i] for i in idx], [deltas[i] for i in idx], 99,
-                           ladder, 2)
+                           ladder, 2, remake)
         assert n >= 6, (ladder, n)
 
 
