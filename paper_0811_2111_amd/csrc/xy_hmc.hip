@@ -517,18 +517,31 @@ __device__ __forceinline__ void pair_nb(const PairCS& own, const PairCS& u, cons
     na.cd = d.c0; na.sd = d.s0; nb.cd = d.c1; nb.sd = d.s1;
 }
 
-// The pass on record block t (after the XCD remap) of one lattice.
+// Pair columns per run and runs per workgroup of the pair kernels: a lattice
+// narrower than a workgroup (J < 256 pair columns) gives each workgroup
+// 256 / J runs side by side instead of leaving lanes idle.
+__host__ __device__ __forceinline__ int ends_group(int L)
+{
+    const int J = L >> 2;
+    return kThreads / (J < kThreads ? (J > 0 ? J : 1) : kThreads);
+}
+
+// The pass on record block t (after the XCD remap) of one lattice, whose rows
+// are cut into `runs` runs of equal length (the last may be shorter).
 template <bool BEGIN>
 __device__ __forceinline__ void ends2_body(const float* __restrict__ st, float* __restrict__ p,
                                            float* __restrict__ copy, int L, uint32_t traj, uint32_t k0, uint32_t k1,
-                                           float nbeta_kick, int cols, int rb, double* __restrict__ rec, unsigned t)
+                                           float nbeta_kick, int cols, int runs, double* __restrict__ rec, unsigned t)
 {
     const int Hh = L >> 1, J = Hh >> 1;
+    const int G = ends_group(L), JB = kThreads / G;
     const int col = (int)(t % (unsigned)cols);
-    const int j = col * kThreads + threadIdx.x;
+    const int g = (int)threadIdx.x / JB;
+    const int j = col * kThreads + (int)threadIdx.x - g * JB;
+    const int run = (int)(t / (unsigned)cols) * G + g;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
-    const int R = (L + rb - 1) / rb, y0 = (int)(t / (unsigned)cols) * R, y1 = y0 + R < L ? y0 + R : L;
-    if (j < J && y0 < y1) {
+    const int R = (L + runs - 1) / runs, y0 = run * R, y1 = y0 + R < L ? y0 + R : L;
+    if (g < G && j < J && y0 < y1) {
         const float* pl0 = st;
         const float* pl1 = st + (size_t)L * Hh;
         const float2* r0 = (const float2*)pl0;
@@ -694,7 +707,8 @@ k_bhmc_ends(const BhLat* __restrict__ d, const uint32_t* __restrict__ start, int
 {
     const int i = bh_find(start, n, blockIdx.x);
     const BhLat& q = d[i];
-    const unsigned nb = (unsigned)(q.cols * q.rb), lb = blockIdx.x - start[i];
+    const int G = ends_group(q.L);
+    const unsigned nb = (unsigned)(q.cols * ((q.rb + G - 1) / G)), lb = blockIdx.x - start[i];
     if (lb >= nb) return;
     const unsigned t = xcd_band(lb, nb);
     if constexpr (BEGIN)
@@ -812,19 +826,29 @@ static int hmc_row_blocks(int L)
 
 static bool hmc_pairs(int L) { return L % 4 == 0; }
 static int hmc_cols2(int L) { return ((L >> 2) + kThreads - 1) / kThreads; }
-// Row blocks of the pair kernels: runs of up to 32 rows per thread (each run
-// reads the plane rows just above and below it once more, so short runs cost
-// traffic), but at least about 2048 workgroups while L allows, and at most one
-// record per wave within the record buffer.
-static int hmc_row_blocks2(int L)
+// Row runs of the pair kernels.  Each run reads the plane rows just above and
+// below it once more and starts its rolling window with their sines and
+// cosines, so short runs cost traffic and arithmetic.  Lattices of more than one
+// column block (L > 1024): runs of up to 32 rows, but at least about 2048
+// workgroups while L allows, and at most one record per wave within the record
+// buffer.  One column block (L <= 1024, where batches of many lattices supply
+// the parallelism): runs of 8 rows.
+static int hmc_runs2(int L)
 {
     const int cols = hmc_cols2(L);
+    if (cols == 1) return (L + 7) / 8;
     int gy = (2048 + cols - 1) / cols;
     if (gy < L / 32) gy = L / 32;
     const int cap = kHmcMaxRecords / (cols * (kThreads / 64));
     if (gy > cap) gy = cap;
     if (gy > L) gy = L;
     return gy < 1 ? 1 : gy;
+}
+// Workgroups per column block: the runs, ends_group(L) to a workgroup.
+static int hmc_row_blocks2(int L)
+{
+    const int G = ends_group(L);
+    return (hmc_runs2(L) + G - 1) / G;
 }
 
 int hmc_records(int L)
@@ -901,8 +925,9 @@ hipError_t launch_hmc_trajectory(float* state, float* pingpong, const HmcWork& w
                                  xy_hmc_obs* obs, hipStream_t s, const uint32_t* traj_dev)
 {
     const bool pairs2 = hmc_pairs(L);
-    const int cols = pairs2 ? hmc_cols2(L) : hmc_cols(L), rb = pairs2 ? hmc_row_blocks2(L) : hmc_row_blocks(L);
-    const dim3 grec((unsigned)(cols * rb)), gstep(hmc_cols(L), L), block(kThreads);
+    const int cols = pairs2 ? hmc_cols2(L) : hmc_cols(L), rb = pairs2 ? hmc_runs2(L) : hmc_row_blocks(L);
+    const int nbr = pairs2 ? hmc_row_blocks2(L) : rb;     // workgroups per column block
+    const dim3 grec((unsigned)(cols * nbr)), gstep(hmc_cols(L), L), block(kThreads);
     const int nrec = hmc_records(L);
     const int nchunk = (nrec + 255) / 256;
     const float drift = (float)(eps / (2.0 * 3.14159265358979323846));
@@ -970,7 +995,7 @@ void hmc_batch_describe(BhLat& d, int L, double beta, double eps)
     d.L = L;
     d.beta = beta;
     d.cols = hmc_cols2(L);
-    d.rb = hmc_row_blocks2(L);
+    d.rb = hmc_runs2(L);
     d.nrec = hmc_records(L);
     d.kick_half = (float)(-beta * 0.5 * eps);
     d.kick_full = (float)(-beta * eps);

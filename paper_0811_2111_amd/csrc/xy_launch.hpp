@@ -119,7 +119,7 @@ struct BhLat {
     HmcWork w;          // its HMC areas (hmc_carve_compact)
     xy_hmc_obs* obs;    // where its trajectory record goes (may be NULL)
     double beta;
-    int L, cols, rb, nrec;
+    int L, cols, rb, nrec;        // rb: row runs of the pair kernels (hmc_runs2)
     uint32_t k0, k1;
     float kick_half, kick_full;   // -beta eps / 2, -beta eps (FP32, as launch_hmc_trajectory forms them)
 };
