@@ -115,6 +115,16 @@ def test_hot_start_bitwise(orc, L, prec):
     np.testing.assert_array_equal(dev_natural(lat), orc.hot_start(3, L, OPREC[prec]))
 
 
+@pytest.mark.parametrize("seed", [3, 0x9E3779B97F4A7C15])
+def test_hot_start_full_size_bitwise(orc, seed):
+    """The hot start of an L = 4096 lattice, every site against the oracle: the
+    top 23 bits of word X0 or X2 of 8 388 608 Philox4x32-10 calls per seed (counter
+    (0, colour, 1, y P + k/2)), with the key's high word zero and in use."""
+    L = 4096
+    lat = xy.Lattice(L, seed=seed)
+    np.testing.assert_array_equal(dev_natural(lat), orc.hot_start(seed, L, "f32"))
+
+
 def test_cold_start_zero():
     lat = xy.Lattice(64, seed=3, start="cold")
     assert torch.count_nonzero(lat.state).item() == 0
