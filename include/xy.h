@@ -319,8 +319,10 @@ int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
  * moved betas between lattices.
  * hmc_work: caller-owned device memory of xy_batch_hmc_work_bytes bytes (per
  * lattice: momenta, second momenta, saved angles, partial records; then one
- * staging record per lattice); the batch workspace's ping-pong area holds the
- * second copy of the angles.  obs_dev: NULL, or device memory for n * n_traj
+ * staging record per lattice and the batched stages' descriptors, which every
+ * call writes on the stream before its trajectories); the batch workspace's
+ * ping-pong area holds the second copy of the angles.  The library allocates no
+ * device memory here either.  obs_dev: NULL, or device memory for n * n_traj
  * records, lattice-major (trajectory r of lattice i at obs_dev[i * n_traj + r]).
  * XY_EINVAL: FP16 batch, n_traj < 0, n_md < 1 or a bad eps; XY_ESIZE: hmc_len too
  * small; XY_ERANGE: the counter would pass 2^32 - 1. */

@@ -573,7 +573,11 @@ struct xy_batch {
     int64_t h_ntraj;
     uint64_t h_pgen;
     int32_t hmc_steps;     // leap-frog steps per pass of xy_batch_hmc
-    void* hdesc;           // device copy of the batched-stage descriptors and block offsets
+    // batched HMC stages of the cached graph: descriptors and block offsets (host
+    // copies; the graph reads them from the caller's HMC workspace, where every
+    // call writes them again before its replays)
+    std::vector<xyk::BhLat> h_desc;
+    std::vector<uint32_t> h_start;
     uint64_t pgen;         // bumped whenever a lattice's beta or delta changes
 };
 
@@ -586,10 +590,12 @@ static void drop_hmc_graph(xy_batch* b)
 {
     if (b->hexec) (void)hipGraphExecDestroy(b->hexec);
     if (b->hgraph) (void)hipGraphDestroy(b->hgraph);
-    if (b->hdesc) (void)hipFree(b->hdesc);
     b->hexec = nullptr;
     b->hgraph = nullptr;
-    b->hdesc = nullptr;
+    // queued copies read the host descriptors: let them finish before they go
+    if (!b->h_desc.empty()) (void)hipStreamSynchronize(b->stream);
+    b->h_desc.clear();
+    b->h_start.clear();
 }
 
 static void release(xy_batch* b)
@@ -862,7 +868,6 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->h_ntraj = -1;
     b->h_pgen = ~0ull;
     b->hmc_steps = 5;
-    b->hdesc = nullptr;
     b->pgen = 0;
     b->sched = XY_BATCH_PASSES_WIDE;
     auto fail = [&](int code) {
@@ -1139,8 +1144,10 @@ int xy_batch_get_params(const xy_batch* b, double* beta, double* delta)
 
 // ------------------------------------------------------------- batched HMC
 // Workspace of lattice i at offset off[i] (its HMC areas sized for its L), then
-// the trajectory's records of all lattices (staging).
-static size_t bhmc_layout(const xy_batch* b, std::vector<size_t>* off, size_t* staging)
+// the trajectory's records of all lattices (staging), then the batched stages'
+// descriptors (room for every lattice) and their block offsets.
+static size_t bhmc_layout(const xy_batch* b, std::vector<size_t>* off, size_t* staging, size_t* desc = nullptr,
+                          size_t* start = nullptr)
 {
     size_t t = 0;
     if (off) off->resize(b->n);
@@ -1149,7 +1156,11 @@ static size_t bhmc_layout(const xy_batch* b, std::vector<size_t>* off, size_t* s
         t += align256(xyk::hmc_work_bytes_compact(b->L[i]));
     }
     if (staging) *staging = t;
-    return t + align256((size_t)b->n * sizeof(xy_hmc_obs));
+    t += align256((size_t)b->n * sizeof(xy_hmc_obs));
+    if (desc) *desc = t;
+    t += align256((size_t)b->n * sizeof(xyk::BhLat));
+    if (start) *start = t;
+    return t + align256(3 * ((size_t)b->n + 1) * sizeof(uint32_t));
 }
 
 int xy_batch_hmc_work_bytes(const xy_batch* b, size_t* bytes)
@@ -1166,8 +1177,8 @@ int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hm
     if (b->precision != XY_FP32 || n_traj < 0 || n_md < 1 || !std::isfinite(eps) || !(eps > 0.0)) return XY_EINVAL;
     if (!hmc_work) return XY_ESTATE;
     std::vector<size_t> off;
-    size_t staging = 0;
-    if (hmc_len < bhmc_layout(b, &off, &staging)) return XY_ESIZE;
+    size_t staging = 0, desc_off = 0, start_off = 0;
+    if (hmc_len < bhmc_layout(b, &off, &staging, &desc_off, &start_off)) return XY_ESIZE;
     if (b->sweep + (uint64_t)n_traj >= 0xffffffffull || n_traj > INT32_MAX) return XY_ERANGE;
     if (n_traj == 0) return XY_OK;
     hipError_t e;
@@ -1184,6 +1195,8 @@ int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hm
     Ctrl* ctrl = (Ctrl*)(b->work + b->lo.ctrl_off);
     char* hw = (char*)hmc_work;
     xy_hmc_obs* stage = (xy_hmc_obs*)(hw + staging);
+    xyk::BhLat* d_desc = (xyk::BhLat*)(hw + desc_off);
+    uint32_t* d_start = (uint32_t*)(hw + start_off);
     if (!b->hexec || b->h_nmd != n_md || b->h_eps != eps || b->h_steps != b->hmc_steps || b->h_work != hmc_work ||
         b->h_obs != obs_dev || b->h_ntraj != n_traj || b->h_pgen != b->pgen) {
         // one trajectory of every lattice, captured once and replayed per
@@ -1192,7 +1205,7 @@ int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hm
         // through the batched stages, one launch per stage for all of them; the
         // others are spread over kHmcStreams branches (greedy by L^2) with their
         // own single-lattice launches.
-        if ((e = hipStreamSynchronize(b->stream)) != hipSuccess)     // a replay may still read the descriptors
+        if ((e = hipStreamSynchronize(b->stream)) != hipSuccess)     // a copy may still read the host descriptors
             return xyr::hip_fail(e, "xy_batch_hmc: hipStreamSynchronize");
         drop_hmc_graph(b);
         std::vector<int> fast;
@@ -1201,14 +1214,14 @@ int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hm
                 if (xyk::hmc_batch_supported(b->L[i])) fast.push_back(i);
         const int nf = (int)fast.size();
         uint32_t totals[3] = {0, 0, 0};
-        xyk::BhLat* d_desc = nullptr;
-        uint32_t* d_start = nullptr;
         std::vector<char> isfast(b->n, 0);
         double load[kHmcStreams] = {0.0};
         const size_t eb = sizeof(float);
         if (nf > 0) {
-            std::vector<xyk::BhLat> hd(nf);
-            std::vector<uint32_t> hs(3 * (size_t)(nf + 1));
+            std::vector<xyk::BhLat>& hd = b->h_desc;
+            std::vector<uint32_t>& hs = b->h_start;
+            hd.assign(nf, xyk::BhLat{});
+            hs.assign(3 * (size_t)(nf + 1), 0u);
             for (int f = 0; f < nf; ++f) {
                 const int i = fast[f];
                 isfast[i] = 1;
@@ -1225,26 +1238,15 @@ int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hm
                 xyk::hmc_batch_blocks(b->L[i], nb);
                 for (int g = 0; g < 3; ++g) {
                     hs[(size_t)g * (nf + 1) + f] = totals[g];
-                    if ((uint64_t)totals[g] + nb[g] > 0x7fffffffull) return XY_ESIZE;
+                    if ((uint64_t)totals[g] + nb[g] > 0x7fffffffull) {
+                        drop_hmc_graph(b);
+                        return XY_ESIZE;
+                    }
                     totals[g] += nb[g];
                 }
                 load[0] += (double)b->L[i] * b->L[i];
             }
             for (int g = 0; g < 3; ++g) hs[(size_t)g * (nf + 1) + nf] = totals[g];
-            const size_t db = align256(sizeof(xyk::BhLat) * (size_t)nf);
-            if ((e = hipMalloc(&b->hdesc, db + hs.size() * sizeof(uint32_t))) != hipSuccess) {
-                b->hdesc = nullptr;
-                return xyr::hip_fail(e, "xy_batch_hmc: hipMalloc");
-            }
-            d_desc = (xyk::BhLat*)b->hdesc;
-            d_start = (uint32_t*)((char*)b->hdesc + db);
-            if ((e = hipMemcpy(d_desc, hd.data(), sizeof(xyk::BhLat) * (size_t)nf, hipMemcpyHostToDevice)) !=
-                    hipSuccess ||
-                (e = hipMemcpy(d_start, hs.data(), hs.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) !=
-                    hipSuccess) {
-                drop_hmc_graph(b);
-                return xyr::hip_fail(e, "xy_batch_hmc: descriptor copy");
-            }
         }
         if ((e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
             drop_hmc_graph(b);
@@ -1303,6 +1305,14 @@ int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hm
         b->h_ntraj = n_traj;
         b->h_pgen = b->pgen;
     }
+    // the batched stages' descriptors into the caller's workspace, on every call
+    // (the workspace is the caller's between calls), ordered before the replays
+    if (!b->h_desc.empty() &&
+        ((e = hipMemcpyAsync(d_desc, b->h_desc.data(), b->h_desc.size() * sizeof(xyk::BhLat),
+                             hipMemcpyHostToDevice, b->stream)) != hipSuccess ||
+         (e = hipMemcpyAsync(d_start, b->h_start.data(), b->h_start.size() * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, b->stream)) != hipSuccess))
+        return xyr::hip_fail(e, "xy_batch_hmc: descriptor copy");
     hipLaunchKernelGGL(k_bhmc_start, dim3(1), dim3(1), 0, b->stream, ctrl);
     if ((e = hipGetLastError()) != hipSuccess) return xyr::hip_fail(e, "xy_batch_hmc: launch");
     for (int64_t t = 0; t < n_traj; ++t) {

@@ -354,3 +354,23 @@ def test_batch_hmc_follows_tempering_betas():
         torch.cuda.synchronize()
         assert srec.tobytes() == brec[i].tobytes(), (i, L, nb[i])
         assert torch.equal(b.lattice_state(i), lat.state), L
+
+
+def test_batch_hmc_workspace_is_scratch_between_calls():
+    """The HMC workspace belongs to the caller between calls: overwritten after a
+    call (here zero-filled), the next call with the same arguments (the cached
+    graph) writes its stage descriptors again and continues bit for bit as an
+    untouched batch does."""
+    Ls = [64, 128, 96]
+    seeds, betas = [71, 72, 73], [0.9, 1.0, 1.1]
+    a = xy.Batch(Ls, seeds, betas, [1.0] * 3)
+    b = xy.Batch(Ls, seeds, betas, [1.0] * 3)
+    ra = [xy.hmc_records(a.hmc(2, 6, 0.1))]
+    rb = [xy.hmc_records(b.hmc(2, 6, 0.1))]
+    b.hmc_work.zero_()
+    ra.append(xy.hmc_records(a.hmc(2, 6, 0.1)))
+    rb.append(xy.hmc_records(b.hmc(2, 6, 0.1)))
+    torch.cuda.synchronize()
+    for x, y in zip(ra, rb):
+        assert x.tobytes() == y.tobytes()
+    assert torch.equal(a.state, b.state)
