@@ -488,8 +488,9 @@ k_hmc_end(const float* __restrict__ st, float* __restrict__ copy, const float* _
 // entry of each (2j-1 or 2j+2), so every angle is read from memory once (a thread
 // per colour would read each plane twice, once as its own colour and once as the
 // other's neighbours) and a site costs 1.5 sines and cosines.
-// 1-D grid of cols2 = ceil(J/256) column blocks times rb row blocks, remapped by
-// xcd_band; one partial record per wave.
+// 1-D grid of cols2 = ceil(J/256) column blocks times the row blocks, remapped by
+// xcd_band; a row block holds ends_group(L) runs side by side (one unless
+// J < 256); one partial record per wave.
 struct PairCS {
     float c0, s0, c1, s1;
 };
