@@ -258,11 +258,14 @@ k_hmc_multi(const float* __restrict__ src, float* __restrict__ dst, const float*
     const int x0 = tx * T - K, y0 = ty * T - K;
     float th[M], pm[M];
     unsigned off[M];
+    int dep[M];       // distance of the slot's site from the grown tile's edge (-1: no site)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int i = threadIdx.x + m * kThreads;
+        dep[m] = -1;
         if (i < NE) {
             const int ye = i / E, xe = i - ye * E;
+            dep[m] = min(min(xe, E - 1 - xe), min(ye, E - 1 - ye));
             const int x = wrapi(x0 + xe, L), y = wrapi(y0 + ye, L);
             off[m] = (unsigned)((((x + y) & 1) * L + y) * Hh + (x >> 1));
             th[m] = src[off[m]];
@@ -287,21 +290,18 @@ k_hmc_multi(const float* __restrict__ src, float* __restrict__ dst, const float*
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int i = threadIdx.x + m * kThreads;
-            if (i < NE) {
-                const int ye = i / E, xe = i - ye * E;
-                if (xe > q && xe < E - 1 - q && ye > q && ye < E - 1 - q) {
-                    const float2 own = cur[i], l = cur[i - 1], r = cur[i + 1], u = cur[i - E], d = cur[i + E];
-                    Nb n;
-                    n.c = own.x; n.s = own.y;
-                    n.cl = l.x; n.sl = l.y; n.cr = r.x; n.sr = r.y;
-                    n.cu = u.x; n.su = u.y; n.cd = d.x; n.sd = d.y;
-                    pm[m] = __fmaf_rn(kq, sin_sum(n), pm[m]);
-                    th[m] = __builtin_amdgcn_fractf(__fmaf_rn(drift, pm[m], th[m]));
-                    if (q + 1 < K) {
-                        float sn, cn;
-                        sincos_turn(th[m], sn, cn);
-                        nxt[i] = make_float2(cn, sn);
-                    }
+            if (dep[m] > q) {
+                const float2 own = cur[i], l = cur[i - 1], r = cur[i + 1], u = cur[i - E], d = cur[i + E];
+                Nb n;
+                n.c = own.x; n.s = own.y;
+                n.cl = l.x; n.sl = l.y; n.cr = r.x; n.sr = r.y;
+                n.cu = u.x; n.su = u.y; n.cd = d.x; n.sd = d.y;
+                pm[m] = __fmaf_rn(kq, sin_sum(n), pm[m]);
+                th[m] = __builtin_amdgcn_fractf(__fmaf_rn(drift, pm[m], th[m]));
+                if (q + 1 < K) {
+                    float sn, cn;
+                    sincos_turn(th[m], sn, cn);
+                    nxt[i] = make_float2(cn, sn);
                 }
             }
         }
@@ -309,13 +309,9 @@ k_hmc_multi(const float* __restrict__ src, float* __restrict__ dst, const float*
     }
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        const int i = threadIdx.x + m * kThreads;
-        if (i < NE) {
-            const int ye = i / E, xe = i - ye * E;
-            if (xe >= K && xe < E - K && ye >= K && ye < E - K) {
-                dst[off[m]] = th[m];
-                pdst[off[m]] = pm[m];
-            }
+        if (dep[m] >= K) {           // the tile itself
+            dst[off[m]] = th[m];
+            pdst[off[m]] = pm[m];
         }
     }
 }
@@ -339,11 +335,14 @@ __device__ __forceinline__ void multi_g_body(const float* __restrict__ src, floa
     const int x0 = tx * T - K, y0 = ty * T - K;
     float th[M], pm[M];
     unsigned off[M];
+    int dep[M];       // distance of the slot's site from the grown tile's edge (-1: no site)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int i = threadIdx.x + m * NT;
+        dep[m] = -1;
         if (i < NE) {
             const int ye = i / E, xe = i - ye * E;
+            dep[m] = min(min(xe, E - 1 - xe), min(ye, E - 1 - ye));
             const int x = wrapi(x0 + xe, L), y = wrapi(y0 + ye, L);
             off[m] = (unsigned)((((x + y) & 1) * L + y) * Hh + (x >> 1));
             th[m] = src[off[m]];
@@ -368,17 +367,14 @@ __device__ __forceinline__ void multi_g_body(const float* __restrict__ src, floa
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int i = threadIdx.x + m * NT;
-            if (i < NE) {
-                const int ye = i / E, xe = i - ye * E;
-                if (xe > q && xe < E - 1 - q && ye > q && ye < E - 1 - q) {
-                    const float2 own = cur[i], l = cur[i - 1], r = cur[i + 1], u = cur[i - E], d = cur[i + E];
-                    Nb n;
-                    n.c = own.x; n.s = own.y;
-                    n.cl = l.x; n.sl = l.y; n.cr = r.x; n.sr = r.y;
-                    n.cu = u.x; n.su = u.y; n.cd = d.x; n.sd = d.y;
-                    pm[m] = __fmaf_rn(kq, sin_sum(n), pm[m]);
-                    th[m] = __builtin_amdgcn_fractf(__fmaf_rn(drift, pm[m], th[m]));
-                }
+            if (dep[m] > q) {
+                const float2 own = cur[i], l = cur[i - 1], r = cur[i + 1], u = cur[i - E], d = cur[i + E];
+                Nb n;
+                n.c = own.x; n.s = own.y;
+                n.cl = l.x; n.sl = l.y; n.cr = r.x; n.sr = r.y;
+                n.cu = u.x; n.su = u.y; n.cd = d.x; n.sd = d.y;
+                pm[m] = __fmaf_rn(kq, sin_sum(n), pm[m]);
+                th[m] = __builtin_amdgcn_fractf(__fmaf_rn(drift, pm[m], th[m]));
             }
         }
         if (q + 1 < K) {
@@ -386,13 +382,10 @@ __device__ __forceinline__ void multi_g_body(const float* __restrict__ src, floa
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int i = threadIdx.x + m * NT;
-                if (i < NE) {
-                    const int ye = i / E, xe = i - ye * E;
-                    if (xe > q && xe < E - 1 - q && ye > q && ye < E - 1 - q) {
-                        float sn, cn;
-                        sincos_turn(th[m], sn, cn);
-                        nxt[i] = make_float2(cn, sn);
-                    }
+                if (dep[m] > q) {
+                    float sn, cn;
+                    sincos_turn(th[m], sn, cn);
+                    nxt[i] = make_float2(cn, sn);
                 }
             }
             __syncthreads();
@@ -400,13 +393,9 @@ __device__ __forceinline__ void multi_g_body(const float* __restrict__ src, floa
     }
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        const int i = threadIdx.x + m * NT;
-        if (i < NE) {
-            const int ye = i / E, xe = i - ye * E;
-            if (xe >= K && xe < E - K && ye >= K && ye < E - K) {
-                dst[off[m]] = th[m];
-                pdst[off[m]] = pm[m];
-            }
+        if (dep[m] >= K) {           // the tile itself
+            dst[off[m]] = th[m];
+            pdst[off[m]] = pm[m];
         }
     }
 }
