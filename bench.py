@@ -611,11 +611,11 @@ def extra_legs(stream, args=None):
         g_s = steps / (ms_h * 1e-3) / 1e9
         # algorithmic bytes per site of one trajectory: momenta and saved angles
         # (read 4, write 8), ceil(n_md / k) passes of angle + momentum read and
-        # written (16 B each), the final half kick (read 8, plus a copy of 8 when
-        # the pass count is odd)
+        # written (16 B each), the final half kick (read 8, plus the angle written
+        # back into the state, 4, when the pass count is odd)
         k = lt.hmc_steps_per_pass
         passes = -(-hc["n_md"] // k)
-        traj_bytes = 12.0 + ALG_BYTES_HMC_STEP * passes + 8.0 + (8.0 if passes % 2 else 0.0)
+        traj_bytes = 12.0 + ALG_BYTES_HMC_STEP * passes + 8.0 + (4.0 if passes % 2 else 0.0)
         gbs = float(hc["L"]) ** 2 * traj_bytes * hc["traj"] / (ms_h * 1e-3) / 1e9
         ex[name] = {"g_site_steps_s": round(g_s, 2), "trajectories": hc["traj"], "n_md": hc["n_md"],
                     "eps": hc["eps"], "ms": round(ms_h, 2), "accept_rate": round(float(r["accepted"].mean()), 3),

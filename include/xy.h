@@ -291,7 +291,7 @@ int xy_hmc_work_bytes(int32_t L, size_t* bytes);
 int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
            xy_hmc_obs* obs_dev);
 
-/* Leap-frog steps per pass over the lattice (1 .. 8, default 5; XY_EINVAL
+/* Leap-frog steps per pass over the lattice (1 .. 8, default 7; XY_EINVAL
  * otherwise).  With more than one, for L % 32 == 0, a workgroup loads a 64 x 64
  * tile (32 x 32 if L % 64 != 0) grown by that many sites on every side, runs the
  * steps on it (the grown part shrinking by one site per step) and writes the
@@ -329,7 +329,7 @@ int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
 int xy_batch_hmc_work_bytes(const xy_batch* b, size_t* bytes);
 int xy_batch_hmc(xy_batch* b, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
                  xy_hmc_obs* obs_dev);
-/* Leap-frog steps per pass of xy_batch_hmc (1 .. 8, default 5), as
+/* Leap-frog steps per pass of xy_batch_hmc (1 .. 8, default 7), as
  * xy_hmc_set_steps_per_pass.  XY_EINVAL otherwise. */
 int xy_batch_hmc_set_steps_per_pass(xy_batch* b, int32_t steps);
 

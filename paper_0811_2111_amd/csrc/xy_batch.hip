@@ -867,7 +867,7 @@ int xy_batch_init(xy_batch** out, int32_t n, const uint64_t* seeds, const int32_
     b->h_obs = nullptr;
     b->h_ntraj = -1;
     b->h_pgen = ~0ull;
-    b->hmc_steps = 5;
+    b->hmc_steps = 7;
     b->pgen = 0;
     b->sched = XY_BATCH_PASSES_WIDE;
     auto fail = [&](int code) {

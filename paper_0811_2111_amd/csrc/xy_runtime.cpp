@@ -234,7 +234,7 @@ static int make_handle(xy_lattice** out, uint64_t seed, int32_t L, double beta, 
     h->work_len = work_len;
     h->stream = (hipStream_t)hip_stream;
     h->sweep = 0;
-    h->hmc_steps = 5;
+    h->hmc_steps = 7;
     h->tev = nullptr;
     h->tcap = h->tn = 0;
     h->w = xyk::carve(work_dev, L, precision);
@@ -681,7 +681,7 @@ int xyr::sweep_on_work(uint64_t seed, int32_t L, double beta, double delta, int3
     h.work_len = work_len;
     h.stream = stream;
     h.sweep = sweep;
-    h.hmc_steps = 5;
+    h.hmc_steps = 7;
     h.tev = nullptr;
     h.tcap = h.tn = 0;
     h.w = xyk::carve(work, L, precision);

@@ -204,7 +204,7 @@ def test_steps_per_pass_settings():
     lat = xy.Lattice(48, seed=1)
     assert lat.hmc_steps_per_pass == 1                       # 48 % 32 != 0: one step per launch
     lat64 = xy.Lattice(64, seed=1)
-    assert lat64.hmc_steps_per_pass == 5                     # the default
+    assert lat64.hmc_steps_per_pass == 7                     # the default
     assert L_.xy_hmc_set_steps_per_pass(lat64.h, 0) == xy.XY_EINVAL
     assert L_.xy_hmc_set_steps_per_pass(lat64.h, 9) == xy.XY_EINVAL
     assert L_.xy_hmc_set_steps_per_pass(None, 2) == xy.XY_ESTATE
