@@ -152,8 +152,8 @@ def parse():
                     help="fixed plan 'kind,tile_x,tile_y,sweeps_per_pass' instead of autotuning")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["l4096", "l16384", "batch", "hmc", "hmc_batch", "quad", "fp16", "tempering",
-                                           "small"],
+    ap.add_argument("--workload", choices=["l4096", "l4096_tuned", "l16384", "batch", "hmc", "hmc_batch", "quad", "fp16",
+                                           "tempering", "small"],
                     default="l16384",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
     ap.add_argument("--schedule", type=int, default=None,
@@ -377,7 +377,10 @@ def profile_leg(args, stream):
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    if args.workload == "l4096":
+    if args.workload == "l4096_tuned":
+        # the benchmark's L = 4096 leg itself: the autotuner's trials, then the sweeps
+        print(json.dumps({"workload": "L4096 tuned", **l4096_leg(stream, steps=args.steps, warmup=args.warmup)}))
+    elif args.workload == "l4096":
         c2 = workloads.SINGLE_4096
         plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
         lat = xy.Lattice(c2["L"], seed=c2["seed"], beta=c2["beta"], delta=c2["delta"], plan=plan)
