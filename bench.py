@@ -157,7 +157,7 @@ def parse():
                     default="l16384",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
     ap.add_argument("--schedule", type=int, default=None,
-                    help="with --kernel-only --workload batch: batch schedule (0 persistent, 1 per-sweep, "
+                    help="with --kernel-only --workload batch, tempering or small: batch schedule (0 persistent, 1 per-sweep, "
                          "2 per-sweep with wide tiles; default: the library's)")
     return ap.parse_args()
 
@@ -438,6 +438,8 @@ def profile_leg(args, stream):
             del lat
         n = 2048
         b = xy.Batch([pc["L"]] * n, [pc["seed"] + i for i in range(n)], [pc["beta"]] * n, [pc["delta"]] * n)
+        if args.schedule is not None:
+            b.set_schedule(args.schedule)
         b.sweep(args.warmup)
         ms = timed(lambda: b.sweep(args.steps, 10), stream)
         res["batch_2048"] = {"gupd_s": float(pc["L"]) ** 2 * n * args.steps / (ms * 1e-3) / 1e9}
@@ -445,6 +447,8 @@ def profile_leg(args, stream):
     elif args.workload == "tempering":
         sc = workloads.temperature_scan()
         tb = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+        if args.schedule is not None:
+            tb.set_schedule(args.schedule)
         K = sc["measure_every"]
         rounds = max(args.steps // K, 1)
         tb.tempering(max(args.warmup // K, 1), K, 1)

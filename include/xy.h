@@ -70,8 +70,9 @@ extern "C" {
 #define XY_EHIP   (-4)  /* a HIP runtime call failed; xy_last_hip_error() names it */
 #define XY_ESTATE (-5)  /* NULL handle, NULL required pointer, or handle already freed */
 #define XY_ENOMEM (-6)  /* host allocation of a handle failed */
-#define XY_EBARRIER (-7) /* a batch barrier wait hit its spin limit: the GPU did not hold every
-                            workgroup of the persistent launch at once; results are invalid */
+#define XY_EBARRIER (-7) /* a batch barrier wait hit its spin limit (the GPU did not hold every
+                            workgroup of the persistent launch at once), or an XCD with lattices
+                            to sweep ran none of its workgroups; results are invalid */
 #define XY_EIO    (-8)  /* a file (the tune cache) could not be written */
 
 enum { XY_FP32 = 0, XY_FP16 = 1 };
@@ -375,10 +376,12 @@ int xy_tuned_plan(const char* cache_path, int32_t L, int32_t precision, xy_plan*
  * sum_{j<i} L[j]^2 of state_dev, in the single-lattice layout.  A lattice
  * follows exactly the trajectory it would follow alone with the same seed.
  * Three schedules (xy_batch_set_schedule), the same trajectory:
- *   XY_BATCH_PERSISTENT: one persistent kernel per call; every workgroup owns a
- *     contiguous range of the tiles of all lattices and waits, before each pass
- *     over a lattice, for the previous pass of that lattice (per-lattice
- *     counters in device memory);
+ *   XY_BATCH_PERSISTENT: one persistent kernel per call; the lattices are split
+ *     into eight groups of about equal area, one per XCD; the workgroups running
+ *     on an XCD split its group's tiles into contiguous ranges, and each waits,
+ *     before a pass over a lattice, for the previous pass of that lattice (a
+ *     tiles-done counter per lattice in device memory, synchronised within the
+ *     XCD only);
  *   XY_BATCH_PASSES: one launch per sweep over all tiles of all lattices, one
  *     workgroup per tile; the kernel boundary orders the sweeps;
  *   XY_BATCH_PASSES_WIDE (default): the same, with 256 x 16 tiles for every

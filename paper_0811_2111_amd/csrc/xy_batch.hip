@@ -5,15 +5,19 @@
 // performs well only with enough work in flight motivate running a whole
 // temperature scan as one work list: small lattices alone cannot fill 256 CUs.
 //
-// Work list: every lattice is cut into TX x TY tiles; the tiles of all lattices,
-// lattice by lattice, form one list that is split into contiguous ranges, one per
-// workgroup.  The grid never exceeds what the GPU holds at once, so every
-// workgroup is resident and the per-lattice barriers below cannot deadlock.
-// One pass = one fused sweep of a tile (state -> ping-pong or back).  Before a
-// workgroup starts pass p on a lattice it waits until every workgroup that owns
-// tiles of that lattice has finished pass p-1 (an epoch counter per lattice),
-// which orders both the new reads after the old writes and the new writes after
-// the old halo reads.  Lattices never wait for each other.
+// Work list (persistent schedule): the lattices are split into eight groups of
+// about equal area, one per XCD, and every lattice is cut into TX x TY tiles.
+// The workgroups of the one launch find out which XCD they run on, and those on
+// XCD x split group x's tiles into contiguous ranges.  The grid never exceeds
+// what the GPU holds at once, so every workgroup is resident and the barriers
+// below cannot deadlock.  One pass = one fused sweep of a tile (state ->
+// ping-pong or back).  Before a workgroup starts pass p on a lattice it waits
+// until all of that lattice's tiles have finished pass p-1 (a counter of tiles
+// done per lattice), which orders both the new reads after the old writes and
+// the new writes after the old halo reads.  Lattices never wait for each other.
+// Every workgroup that touches a lattice runs on one XCD and so shares one L2:
+// the barrier needs no L2 write-back or invalidation, only the completion of the
+// workgroup's stores before it arrives and a drop of its L1 lines after it waits.
 //
 // The second schedule (XY_BATCH_PASSES) launches one kernel per pass over the
 // whole work list instead, one workgroup per tile, and lets the kernel boundary
@@ -52,8 +56,8 @@ struct LatDesc {
     int tiles_x;
     int first_tile;
     int ntiles;
-    int arrivals;         // workgroups owning tiles of this lattice
-    int reducer;          // workgroup that reduces this lattice's measurements
+    int xfirst;           // persistent schedule: first tile within its XCD group's list
+    int xcd;              // persistent schedule: the XCD group
     int wide;             // tiles of kWideX x kWideY instead of the batch's shape (per-sweep schedule)
     int resident;         // held in one workgroup's LDS for a whole call (per-sweep schedules, L <= 32)
     uint32_t key0, key1;
@@ -65,6 +69,17 @@ struct LatDesc {
 constexpr int kWideX = 256, kWideY = 16;
 // Lattices up to this size are LDS-resident under the per-sweep schedules.
 constexpr int kBatchResidentMaxL = 32;
+// XCDs of the GPU (workgroups of a launch are spread over all of them).
+constexpr int kXcd = 8;
+
+// Lattice groups of the persistent schedule: group x (run on XCD x) holds the
+// lattices ord[beg[x] .. beg[x+1]) (ord follows this struct in device memory)
+// with tiles[x] tiles in all.
+struct XcdPlan {
+    int beg[kXcd + 1];
+    int tiles[kXcd];
+    int pad[7];
+};
 
 struct Ctrl {
     uint32_t sweep0;      // absolute sweep index of the next pass (advanced by k_batch_advance)
@@ -78,49 +93,65 @@ struct Ctrl {
 // cycles each), several seconds at 2.4 GHz, far beyond any legitimate wait.
 static constexpr unsigned kSpinLimit = 1u << 27;
 
-// Barrier wait: thread 0 polls the counter with relaxed loads (no cache
-// maintenance per poll), then one agent-scope acquire fence makes the other
-// workgroups' writes visible before the workgroup reads them.  A wait that
-// reaches the spin limit flags ctrl->timed_out and lets the workgroup run on;
-// every wait, before and while it polls, leaves at once once that flag is set,
-// so after one wait has given up the whole grid drains without waiting again
-// (the sweeps then run on stale data, whose indices never depend on it, and
-// xy_batch_status reports XY_EBARRIER).
-__device__ __forceinline__ void wait_at_least(unsigned* ctr, unsigned target, Ctrl* ctrl)
+// The XCD a wave runs on: hardware register XCC_ID (20), bits 0..3.
+__device__ __forceinline__ int xcc_id()
 {
-    if (threadIdx.x == 0) {
-        const unsigned limit = ctrl->spin_limit;
-        unsigned spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(&ctrl->timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins >= limit) {
-                __hip_atomic_store(&ctrl->timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
+    return (int)(__builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & (kXcd - 1));
+}
+
+// Bounded poll of a counter by thread 0: relaxed agent-scope loads (no cache
+// maintenance per poll) until it reaches target.  A wait that reaches the spin
+// limit flags ctrl->timed_out and gives up; every wait, before and while it
+// polls, leaves at once once that flag is set, so after one wait has given up
+// the whole grid drains without waiting again (the sweeps then run on stale data,
+// whose indices never depend on it, and xy_batch_status reports XY_EBARRIER).
+__device__ __forceinline__ void poll_at_least(unsigned* ctr, unsigned target, Ctrl* ctrl)
+{
+    const unsigned limit = ctrl->spin_limit;
+    unsigned spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(&ctrl->timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) break;
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins >= limit) {
+            __hip_atomic_store(&ctrl->timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __syncthreads();
 }
 
-// Barrier arrival: the workgroup's writes are ordered before one agent-scope
-// release fence, then a relaxed increment.
-__device__ __forceinline__ void arrive(unsigned* ctr)
+// Barrier between workgroups of one XCD.  They share the XCD's L2 and the vector
+// L1 is write-through, so a release only has to wait until the workgroup's
+// stores have reached the L2: no L2 write-back, which an agent-scope release
+// would do (of the whole L2, for every workgroup and pass).  The acquire has to
+// drop the stale lines of the CU's L1 cache; outside thread-group-split mode the
+// workgroup-scope invalidate does not do that (stale halo rows were read with
+// it), so it is the agent-scope one, which drops this XCD's L2 copies of memory
+// it does not own as well.
+__device__ __forceinline__ void xcd_wait(unsigned* ctr, unsigned target, Ctrl* ctrl)
 {
-    __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        poll_at_least(ctr, target, ctrl);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);
     }
+    __syncthreads();
 }
 
-__device__ __forceinline__ int lattice_of(const LatDesc* d, int n, int tile)
+// Arrival: every wave waits for its stores, then thread 0 adds `add` to the counter.
+__device__ __forceinline__ void xcd_arrive(unsigned* ctr, unsigned add)
 {
-    int lo = 0, hi = n - 1;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Position in ord[beg .. end) of the lattice whose group-local tiles hold tile t.
+__device__ __forceinline__ int xlattice_of(const LatDesc* d, const int* ord, int beg, int end, int t)
+{
+    int lo = beg, hi = end - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (d[mid].first_tile <= tile) lo = mid; else hi = mid - 1;
+        if (d[ord[mid]].xfirst <= t) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -157,70 +188,96 @@ __device__ void reduce_lattice(const LatDesc& d, const double* part, xy_obs* out
     __syncthreads();
 }
 
+// The persistent kernel.  bar: one tiles-done counter per lattice, then kXcd + 1
+// registration counters (workgroups per XCD, all workgroups), all zero at launch.
+// Start: each workgroup takes a rank among the workgroups of its XCD and waits
+// until the whole grid has registered, so that it knows how many share its
+// group's tiles.  A group whose XCD runs no workgroup of the grid would be left
+// undone: that is flagged like a barrier time-out (it does not happen while the
+// grid, a multiple of 8 workgroups, is dealt out over the XCDs in turn).
 template <typename T, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT)
-k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ lat, int nlat, int total_tiles,
-        unsigned* __restrict__ bar, Ctrl* __restrict__ ctrl, int npass, int measure_every,
+k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ lat, const XcdPlan* __restrict__ plan,
+        int nlat, int total_tiles, unsigned* __restrict__ bar, Ctrl* __restrict__ ctrl, int npass, int measure_every,
         double* __restrict__ part /* [2][total_tiles][8] */, xy_obs* __restrict__ obs, int nrec)
 {
     extern __shared__ __align__(16) char smem[];
+    __shared__ int s_pos[2];
     using S = Tile1<TX, TY, NT>;
     double* red = (double*)(smem + S::lds_bytes);   // 7 doubles per wave, after the tile's LDS
-    const int G = gridDim.x, w = blockIdx.x;
-    const int t0 = (int)((long long)total_tiles * w / G);
-    const int t1 = (int)((long long)total_tiles * (w + 1) / G);
+    const int* ord = (const int*)(plan + 1);
+    unsigned* reg = bar + nlat;
+    const int x = xcc_id();
+    if (threadIdx.x == 0) {
+        const unsigned r = __hip_atomic_fetch_add(&reg[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&reg[kXcd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        poll_at_least(&reg[kXcd], gridDim.x, ctrl);
+        for (int y = 0; y < kXcd; ++y)
+            if (plan->tiles[y] > 0 && __hip_atomic_load(&reg[y], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u)
+                __hip_atomic_store(&ctrl->timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_pos[0] = (int)r;
+        s_pos[1] = (int)__hip_atomic_load(&reg[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // > r
+    }
+    __syncthreads();
+    const int rank = s_pos[0], nx = s_pos[1];
+    const int nt = plan->tiles[x], beg = plan->beg[x], end = plan->beg[x + 1];
+    const int t0 = (int)((long long)nt * rank / nx);
+    const int t1 = (int)((long long)nt * (rank + 1) / nx);
     const uint32_t sweep0 = ctrl->sweep0;
-    const int ilo = t1 > t0 ? lattice_of(lat, nlat, t0) : 0;
-    const int ihi = t1 > t0 ? lattice_of(lat, nlat, t1 - 1) : -1;
-    // measured passes: pass p is measured if (p + 1) % measure_every == 0
+    const int qlo = t1 > t0 ? xlattice_of(lat, ord, beg, end, t0) : 0;
+    const int qhi = t1 > t0 ? xlattice_of(lat, ord, beg, end, t1 - 1) : -1;
+    // measured passes: pass p is measured if (p + 1) % measure_every == 0; its
+    // records go to half (p / measure_every) & 1 of the partials
     auto measured = [&](int p) { return measure_every > 0 && obs != nullptr && ((p + 1) % measure_every) == 0; };
+    auto slots = [&](int p) {
+        return part + (size_t)((p / (measure_every > 0 ? measure_every : 1)) & 1) * (size_t)total_tiles * 8;
+    };
+    // the workgroup holding a lattice's first tile writes its records
+    auto reduce_if_owner = [&](const LatDesc& d, int i, int p) {
+        if (measured(p - 1) && t0 <= d.xfirst && d.xfirst < t1)
+            reduce_lattice<NT>(d, slots(p - 1), obs + (size_t)i * nrec + (p / measure_every - 1),
+                               (uint64_t)sweep0 + (uint64_t)p, red);
+    };
 
     for (int p = 0; p < npass; ++p) {
         T* src = (p & 1) ? pp : state;
         T* dst = (p & 1) ? state : pp;
         const bool meas = measured(p);
-        double* pslot = part + (size_t)((p / (measure_every > 0 ? measure_every : 1)) & 1) * total_tiles * 8;
-        for (int i = ilo; i <= ihi; ++i) {
+        double* cur = slots(p);
+        for (int q = qlo; q <= qhi; ++q) {
+            const int i = ord[q];
             const LatDesc d = lat[i];
             if (p > 0) {
-                wait_at_least(&bar[i], (unsigned)p * (unsigned)d.arrivals, ctrl);
-                // measurement of pass p-1 is complete: the reducer writes its record
-                if (measured(p - 1) && d.reducer == w) {
-                    const int r = p / measure_every - 1;
-                    const double* prev = part + (size_t)(((p - 1) / measure_every) & 1) * total_tiles * 8;
-                    reduce_lattice<NT>(d, prev, obs + (size_t)i * nrec + r, (uint64_t)sweep0 + (uint64_t)p, red);
-                }
+                xcd_wait(&bar[i], (unsigned)p * (unsigned)d.ntiles, ctrl);
+                reduce_if_owner(d, i, p);   // pass p-1 is complete
             }
-            const int a = max(t0, d.first_tile), b = min(t1, d.first_tile + d.ntiles);
+            const int a = max(t0, d.xfirst), b = min(t1, d.xfirst + d.ntiles);
             const Params prm{d.delta, d.nbl2e};
             for (int t = a; t < b; ++t) {
-                const int lt = t - d.first_tile;
+                const int lt = t - d.xfirst;
                 const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
                 tile1_program<T, TX, TY, NT>(src + d.off, dst + d.off, (unsigned)((size_t)d.L * d.L * sizeof(T)), d.L,
                                              tx * TX, ty * TY, sweep0 + (uint32_t)p, d.key0, d.key1, prm, meas,
-                                             pslot + (size_t)t * 8, smem, red);
+                                             cur + (size_t)(d.first_tile + lt) * 8, smem, red);
                 __syncthreads();   // the next tile reuses the LDS
             }
+            xcd_arrive(&bar[i], (unsigned)(b - a));   // done with lattice i in pass p
         }
-        for (int i = ilo; i <= ihi; ++i) arrive(&bar[i]);
     }
 
     // Epilogue: wait for the last pass, write the last record, and if the pass
     // count is odd copy this workgroup's tiles back into the caller's buffer.
     if (npass > 0) {
-        for (int i = ilo; i <= ihi; ++i) {
+        for (int q = qlo; q <= qhi; ++q) {
+            const int i = ord[q];
             const LatDesc d = lat[i];
-            wait_at_least(&bar[i], (unsigned)npass * (unsigned)d.arrivals, ctrl);
-            if (measured(npass - 1) && d.reducer == w) {
-                const int r = npass / measure_every - 1;
-                const double* prev = part + (size_t)(((npass - 1) / measure_every) & 1) * total_tiles * 8;
-                reduce_lattice<NT>(d, prev, obs + (size_t)i * nrec + r, (uint64_t)sweep0 + (uint64_t)npass, red);
-            }
+            xcd_wait(&bar[i], (unsigned)npass * (unsigned)d.ntiles, ctrl);
+            reduce_if_owner(d, i, npass);
             if (npass & 1) {
-                const int a = max(t0, d.first_tile), b = min(t1, d.first_tile + d.ntiles);
+                const int a = max(t0, d.xfirst), b = min(t1, d.xfirst + d.ntiles);
                 const int Hh = d.L >> 1;
                 for (int t = a; t < b; ++t) {
-                    const int lt = t - d.first_tile;
+                    const int lt = t - d.xfirst;
                     const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
                     for (int idx = threadIdx.x; idx < 2 * TY * (TX / 2); idx += NT) {
                         const int c = idx / (TY * (TX / 2));
@@ -435,7 +492,7 @@ static std::vector<Shape> candidates(int n, const int32_t* L)
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, res_off, tile_off, part_off, pt_off, total;
+    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, xplan_off, res_off, tile_off, part_off, pt_off, total;
     long long max_tiles;
 };
 
@@ -464,8 +521,9 @@ static Layout layout(int n, const int32_t* L, int precision)
     lo.pp_off = 0;
     lo.ctrl_off = align256(lo.state_bytes);
     lo.bar_off = lo.ctrl_off + 256;
-    lo.desc_off = align256(lo.bar_off + (size_t)n * sizeof(unsigned));
-    lo.res_off = align256(lo.desc_off + (size_t)n * sizeof(LatDesc));
+    lo.desc_off = align256(lo.bar_off + (size_t)(n + kXcd + 1) * sizeof(unsigned));
+    lo.xplan_off = align256(lo.desc_off + (size_t)n * sizeof(LatDesc));
+    lo.res_off = align256(lo.xplan_off + sizeof(XcdPlan) + (size_t)n * sizeof(int));
     lo.tile_off = align256(lo.res_off + (size_t)n * sizeof(int));
     lo.part_off = align256(lo.tile_off + (size_t)lo.max_tiles * sizeof(int));
     lo.pt_off = align256(lo.part_off + (size_t)2 * lo.max_tiles * 8 * sizeof(double));
@@ -667,24 +725,40 @@ static int plan_batch(xy_batch* b, Shape s)
         off += (long long)d.L * d.L;
     }
     if ((long long)total > b->lo.max_tiles) return XY_EINVAL;
-    // every workgroup must be resident at once for the barriers; keep a margin of
-    // one resident slot in ten in case part of the GPU is busy with other work
-    const int G = std::max(1, std::min(total, std::max(1, cus * per_cu * 9 / 10)));
-    for (int i = 0; i < b->n; ++i) {
-        LatDesc& d = b->desc[i];
-        // workgroups w with [t0(w), t1(w)) intersecting [first, first + ntiles)
-        int wlo = -1, whi = -1;
-        for (int w = 0; w < G; ++w) {
-            const long long t0 = (long long)total * w / G, t1 = (long long)total * (w + 1) / G;
-            if (t1 <= t0) continue;
-            if (t0 < d.first_tile + d.ntiles && t1 > d.first_tile) {
-                if (wlo < 0) wlo = w;
-                whi = w;
-            }
-        }
-        d.arrivals = whi - wlo + 1;
-        d.reducer = wlo;
+    // Persistent schedule: lattices into kXcd groups of about equal tile count,
+    // largest first onto the lightest group; within a group in lattice order.
+    std::vector<int> by_size(b->n);
+    for (int i = 0; i < b->n; ++i) by_size[i] = i;
+    std::stable_sort(by_size.begin(), by_size.end(),
+                     [&](int u, int v) { return b->desc[u].ntiles > b->desc[v].ntiles; });
+    long long load[kXcd] = {0};
+    for (int i : by_size) {
+        int best = 0;
+        for (int y = 1; y < kXcd; ++y)
+            if (load[y] < load[best]) best = y;
+        b->desc[i].xcd = best;
+        load[best] += b->desc[i].ntiles;
     }
+    XcdPlan plan{};
+    std::vector<int> ord;
+    for (int y = 0; y < kXcd; ++y) {
+        plan.beg[y] = (int)ord.size();
+        int t = 0;
+        for (int i = 0; i < b->n; ++i)
+            if (b->desc[i].xcd == y) {
+                b->desc[i].xfirst = t;
+                t += b->desc[i].ntiles;
+                ord.push_back(i);
+            }
+        plan.tiles[y] = t;
+    }
+    plan.beg[kXcd] = (int)ord.size();
+    // every workgroup must be resident at once for the barriers; keep a margin of
+    // one resident slot in ten in case part of the GPU is busy with other work.
+    // At most three workgroups per CU: more (up to the occupancy limit) were
+    // slower, as each adds waits to every barrier of its lattices.  A multiple of
+    // kXcd workgroups, so that each XCD gets the same number.
+    const int G = std::max(kXcd, std::min(total, std::min(cus * 3, cus * per_cu * 9 / 10)) / kXcd * kXcd);
     b->shape = s;
     b->grid = G;
     b->total_tiles = total;
@@ -699,6 +773,11 @@ static int plan_batch(xy_batch* b, Shape s)
     e = hipMemcpyAsync(b->work + b->lo.desc_off, b->desc.data(), sizeof(LatDesc) * b->n, hipMemcpyHostToDevice,
                        b->stream);
     if (e != hipSuccess) return xyr::hip_fail(e, "hipMemcpyAsync(desc)");
+    e = hipMemcpyAsync(b->work + b->lo.xplan_off, &plan, sizeof(XcdPlan), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->work + b->lo.xplan_off + sizeof(XcdPlan), ord.data(), sizeof(int) * ord.size(),
+                           hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return xyr::hip_fail(e, "hipMemcpyAsync(XCD groups)");
     if (b->nres > 0) {
         e = hipMemcpyAsync(b->work + b->lo.res_off, ridx.data(), sizeof(int) * ridx.size(), hipMemcpyHostToDevice,
                            b->stream);
@@ -726,13 +805,14 @@ static hipError_t enqueue_batch(xy_batch* b, hipStream_t s, int npass, int32_t m
     Ctrl* ctrl = (Ctrl*)(b->work + b->lo.ctrl_off);
     const LatDesc* desc = (const LatDesc*)(b->work + b->lo.desc_off);
     double* part = (double*)(b->work + b->lo.part_off);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, bar, b->n);
+    const XcdPlan* plan = (const XcdPlan*)(b->work + b->lo.xplan_off);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, bar, b->n + kXcd + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* pp = b->work + b->lo.pp_off;
     void* st = b->state;
     int nlat = b->n, tt = b->total_tiles;
-    void* args[] = {&st, &pp, &desc, &nlat, &tt, &bar, &ctrl, &npass, &me, &part, &obs, (void*)&nrec};
+    void* args[] = {&st, &pp, &desc, &plan, &nlat, &tt, &bar, &ctrl, &npass, &me, &part, &obs, (void*)&nrec};
     e = hipLaunchKernel(k, dim3(b->grid), dim3(kNT), args, lds, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(1), 0, s, ctrl, (uint32_t)npass);
@@ -952,15 +1032,15 @@ int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs*
     xy_obs* obs = me ? obs_dev : nullptr;
     const int64_t nrec = me ? n_sweeps / me : 0;   // records per lattice: the stride of obs_dev
     if (nrec > INT32_MAX) return XY_EINVAL;
-    // Split long calls: barrier targets are pass * arrivals in 32 bits and pass
+    // Split long calls: barrier targets are pass * tiles in 32 bits and pass
     // counts are ints (at most 2^30 sweeps per launch sequence), and the per-sweep
     // schedules capture one launch per sweep (at most kMaxGraphPasses per graph).
     // Chunks are multiples of measure_every, so the records of chunk c start at
     // record done / measure_every of every lattice, with the call's stride.
-    int max_arr = 1;
-    for (const LatDesc& d : b->desc) max_arr = std::max(max_arr, d.arrivals);
+    int max_tiles = 1;
+    for (const LatDesc& d : b->desc) max_tiles = std::max(max_tiles, d.ntiles);
     int64_t cap = std::min<int64_t>((int64_t)1 << 30,
-                                    std::max<int64_t>(1, (int64_t)(0xffffffffu / (unsigned)max_arr) - 1));
+                                    std::max<int64_t>(1, (int64_t)(0xffffffffu / (unsigned)max_tiles) - 1));
     if (b->sched != XY_BATCH_PERSISTENT) cap = std::min<int64_t>(cap, kMaxGraphPasses);
     if (me) cap = std::max<int64_t>(cap / me, 1) * me;
     for (int64_t done = 0; done < n_sweeps;) {

@@ -637,3 +637,31 @@ def test_high_seed_and_counter_trajectory(orc, L, plan, prec):
             lat.sweep(1)
         assert ei.value.code == xy.XY_ERANGE
         assert torch.equal(lat.state, before) and lat.sweep_count == 2 ** 32 - 2
+
+
+def test_scan96_persistent_equals_single_lattices():
+    """The 96-lattice scan under the persistent schedule (one launch; lattices in
+    eight groups, one per XCD, several lattices per workgroup and several
+    workgroups per lattice): bit-identical angles, accept counts and records
+    against each lattice run alone, over an odd sweep count with records every 3
+    sweeps, then an even one that crosses the first call's end."""
+    from paper_0811_2111_amd import workloads
+    sc = workloads.temperature_scan()
+    n = len(sc["Ls"])
+    b = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
+    b.set_schedule(xy.XY_BATCH_PERSISTENT)
+    ob1 = b.sweep(9, 3)
+    ob2 = b.sweep(4, 2)
+    b.status()
+    for i in range(n):
+        s = xy.Lattice(sc["Ls"][i], seed=sc["seeds"][i], beta=sc["betas"][i], delta=sc["deltas"][i])
+        os1 = s.sweep(9, 3)
+        os2 = s.sweep(4, 2)
+        assert torch.equal(b.lattice_state(i), s.state), i
+        for ob, os_ in [(ob1, os1), (ob2, os2)]:
+            rb, rs = xy.records(ob[i]), xy.records(os_)
+            assert np.array_equal(rb["sweep"], rs["sweep"]), i
+            assert np.array_equal(rb["n_accept"], rs["n_accept"]), i
+            for f in ["cx", "cy", "ix", "iy", "mx", "my"]:
+                np.testing.assert_allclose(rb[f], rs[f], rtol=0, atol=1e-7 * sc["Ls"][i] ** 2)
+        del s
