@@ -58,13 +58,13 @@ struct LatDesc {
     int ntiles;
     int xfirst;           // persistent schedule: first tile within its XCD group's list
     int xcd;              // persistent schedule: the XCD group
-    int wide;             // tiles of kWideX x kWideY instead of the batch's shape (per-sweep schedule)
+    int wide;             // tiles of kWideX x kWideY instead of the batch's shape (not under XY_BATCH_PASSES)
     int resident;         // held in one workgroup's LDS for a whole call (per-sweep schedules, L <= 32)
     uint32_t key0, key1;
     float delta, nbl2e;
 };
 
-// Tile shape of the lattices that take wide tiles under XY_BATCH_PASSES_WIDE:
+// Tile shape of the lattices that take wide tiles (XY_BATCH_PASSES_WIDE, XY_BATCH_PERSISTENT):
 // the fastest single-lattice shape.
 constexpr int kWideX = 256, kWideY = 16;
 // Lattices up to this size are LDS-resident under the per-sweep schedules.
@@ -188,7 +188,18 @@ __device__ void reduce_lattice(const LatDesc& d, const double* part, xy_obs* out
     __syncthreads();
 }
 
-// The persistent kernel.  bar: one tiles-done counter per lattice, then kXcd + 1
+// LDS of a batch kernel: the larger of the two tile programs it may run (the
+// batch's shape, and 256 x 16 for the lattices flagged wide), then the
+// workgroup's reduction slots.
+template <int TX, int TY, bool WIDE>
+constexpr size_t pass_lds()
+{
+    constexpr size_t a = Tile1<TX, TY, 256>::lds_bytes, w = Tile1<kWideX, kWideY, 256>::lds_bytes;
+    return (WIDE && w > a ? w : a) + Tile1<TX, TY, 256>::red_bytes;
+}
+
+// The persistent kernel.  Lattices flagged wide are cut into kWideX x kWideY tiles,
+// the others into TX x TY.  bar: one tiles-done counter per lattice, then kXcd + 1
 // registration counters (workgroups per XCD, all workgroups), all zero at launch.
 // Start: each workgroup takes a rank among the workgroups of its XCD and waits
 // until the whole grid has registered, so that it knows how many share its
@@ -203,8 +214,9 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_pos[2];
-    using S = Tile1<TX, TY, NT>;
-    double* red = (double*)(smem + S::lds_bytes);   // 7 doubles per wave, after the tile's LDS
+    static_assert(NT == 256, "four waves");
+    // 7 doubles per wave, after the tile programs' LDS
+    double* red = (double*)(smem + pass_lds<TX, TY, true>() - Tile1<TX, TY, NT>::red_bytes);
     const int* ord = (const int*)(plan + 1);
     unsigned* reg = bar + nlat;
     const int x = xcc_id();
@@ -253,12 +265,18 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
             }
             const int a = max(t0, d.xfirst), b = min(t1, d.xfirst + d.ntiles);
             const Params prm{d.delta, d.nbl2e};
+            const unsigned bytes = (unsigned)((size_t)d.L * d.L * sizeof(T));
             for (int t = a; t < b; ++t) {
                 const int lt = t - d.xfirst;
                 const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
-                tile1_program<T, TX, TY, NT>(src + d.off, dst + d.off, (unsigned)((size_t)d.L * d.L * sizeof(T)), d.L,
-                                             tx * TX, ty * TY, sweep0 + (uint32_t)p, d.key0, d.key1, prm, meas,
-                                             cur + (size_t)(d.first_tile + lt) * 8, smem, red);
+                double* rec = cur + (size_t)(d.first_tile + lt) * 8;
+                if (d.wide)
+                    tile1_program<T, kWideX, kWideY, NT>(src + d.off, dst + d.off, bytes, d.L, tx * kWideX,
+                                                         ty * kWideY, sweep0 + (uint32_t)p, d.key0, d.key1, prm, meas,
+                                                         rec, smem, red);
+                else
+                    tile1_program<T, TX, TY, NT>(src + d.off, dst + d.off, bytes, d.L, tx * TX, ty * TY,
+                                                 sweep0 + (uint32_t)p, d.key0, d.key1, prm, meas, rec, smem, red);
                 __syncthreads();   // the next tile reuses the LDS
             }
             xcd_arrive(&bar[i], (unsigned)(b - a));   // done with lattice i in pass p
@@ -276,14 +294,15 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
             if (npass & 1) {
                 const int a = max(t0, d.xfirst), b = min(t1, d.xfirst + d.ntiles);
                 const int Hh = d.L >> 1;
+                const int hx = (d.wide ? kWideX : TX) / 2, ry = d.wide ? kWideY : TY;   // tile: ry rows of hx entries
                 for (int t = a; t < b; ++t) {
                     const int lt = t - d.xfirst;
                     const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
-                    for (int idx = threadIdx.x; idx < 2 * TY * (TX / 2); idx += NT) {
-                        const int c = idx / (TY * (TX / 2));
-                        const int rem = idx - c * (TY * (TX / 2));
-                        const int rr = rem / (TX / 2), k = rem - rr * (TX / 2);
-                        const size_t e = (size_t)d.off + ((size_t)c * d.L + ty * TY + rr) * Hh + tx * (TX / 2) + k;
+                    for (int idx = threadIdx.x; idx < 2 * ry * hx; idx += NT) {
+                        const int c = idx / (ry * hx);
+                        const int rem = idx - c * (ry * hx);
+                        const int rr = rem / hx, k = rem - rr * hx;
+                        const size_t e = (size_t)d.off + ((size_t)c * d.L + ty * ry + rr) * Hh + tx * hx + k;
                         state[e] = pp[e];
                     }
                 }
@@ -313,15 +332,6 @@ __global__ void k_bhmc_finish(const xy_hmc_obs* __restrict__ staging, xy_hmc_obs
 }
 
 __global__ void k_bhmc_start(Ctrl* ctrl) { ctrl->hmc_round = 0u; }
-
-// LDS of a per-pass kernel: the larger of the two tile programs it may run, then
-// the workgroup's reduction slots.
-template <int TX, int TY, bool WIDE>
-constexpr size_t pass_lds()
-{
-    constexpr size_t a = Tile1<TX, TY, 256>::lds_bytes, w = Tile1<kWideX, kWideY, 256>::lds_bytes;
-    return (WIDE && w > a ? w : a) + Tile1<TX, TY, 256>::red_bytes;
-}
 
 // One pass of the per-pass schedule: workgroup b sweeps tile t (XCD-aware order:
 // each XCD takes a contiguous run of the work list, so neighbouring tiles share
@@ -568,7 +578,7 @@ static void* batch_kernel(int precision, Shape s, size_t* lds)
 {
 #define XYB_CASE(TXV, TYV)                                                                         \
     if (s.tx == TXV && s.ty == TYV) {                                                              \
-        *lds = Tile1<TXV, TYV, kNT>::lds_bytes + Tile1<TXV, TYV, kNT>::red_bytes;                  \
+        *lds = pass_lds<TXV, TYV, true>();                                                          \
         return precision == XY_FP16 ? kernel_ptr<__half, TXV, TYV>() : kernel_ptr<float, TXV, TYV>(); \
     }
     XYB_CASE(64, 32)
@@ -711,7 +721,7 @@ static int plan_batch(xy_batch* b, Shape s)
         d.off = off;
         d.L = b->L[i];
         d.resident = b->sched != XY_BATCH_PERSISTENT && d.L <= kBatchResidentMaxL && xyk::resident_supported(d.L);
-        d.wide = b->sched == XY_BATCH_PASSES_WIDE && d.L % kWideX == 0 && d.L % kWideY == 0;
+        d.wide = b->sched != XY_BATCH_PASSES && d.L % kWideX == 0 && d.L % kWideY == 0;
         const int tx = d.wide ? kWideX : s.tx, ty = d.wide ? kWideY : s.ty;
         d.tiles_x = d.L / tx;
         d.first_tile = total;
