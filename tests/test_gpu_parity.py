@@ -427,6 +427,25 @@ def test_batch_tile_shapes_and_small_lattices(Ls, sched):
         assert torch.equal(b.lattice_state(i), s.state), (b.tile, Ls[i])
 
 
+@pytest.mark.parametrize("sched", SCHEDULES)
+def test_batch_fp16_equals_single(sched):
+    """FP16 storage in a batch, every schedule (lattices of L % 256 == 0 take wide
+    tiles except under the plain per-sweep schedule; L = 32 is LDS-resident under
+    the per-sweep schedules): bit-identical FP16 angles and equal accept counts
+    against each lattice run alone, over an odd sweep count."""
+    Ls = [256, 64, 32, 128]
+    seeds, betas, deltas = [21, 22, 23, 24], [0.9, 1.1, 1.0, 1.25], [1.0, 1.1, 0.9, 1.0]
+    b = xy.Batch(Ls, seeds, betas, deltas, precision="fp16")
+    b.set_schedule(sched)
+    ob = b.sweep(7, 7)
+    b.status()
+    for i, L in enumerate(Ls):
+        s = xy.Lattice(L, seed=seeds[i], beta=betas[i], delta=deltas[i], precision="fp16")
+        os_ = s.sweep(7, 7)
+        assert torch.equal(b.lattice_state(i), s.state), (sched, L)
+        assert np.array_equal(xy.records(ob[i])["n_accept"], xy.records(os_)["n_accept"]), (sched, L)
+
+
 def test_batch_set_tile_invariance():
     """Every tile shape under every schedule, and a switch of schedule between
     calls, gives the same angles bit for bit (L = 256 and 512 take wide tiles under
