@@ -495,6 +495,11 @@ def extra_legs(stream, args=None):
     b.sweep(20)
     ms_b = timed(lambda: b.sweep(sc["sweeps"], sc["measure_every"], out=bobs), stream)
     g_b = float(sites) * sc["sweeps"] / (ms_b * 1e-3) / 1e9
+    # the same scan as one persistent launch per call (same tile shape)
+    b.set_schedule(xy.XY_BATCH_PERSISTENT)
+    b.sweep(20)
+    ms_pk = timed(lambda: b.sweep(sc["sweeps"], sc["measure_every"], out=bobs), stream)
+    g_pk = float(sites) * sc["sweeps"] / (ms_pk * 1e-3) / 1e9
     del b, bobs
     per_sweeps = 1000
     lats = [xy.Lattice(L, seed=s, beta=bb, delta=d) for L, s, bb, d in
@@ -512,7 +517,8 @@ def extra_legs(stream, args=None):
         "schedule": BATCH_SCHEDULES[sched],
         "batched_gupd_s": round(g_b, 2), "batched_ms": round(ms_b, 2),
         "per_lattice_gupd_s": round(g_p, 2), "per_lattice_sweeps_timed": per_sweeps,
-        "speedup": round(g_b / g_p, 2)}
+        "speedup": round(g_b / g_p, 2),
+        "persistent_gupd_s": round(g_pk, 2), "persistent_speedup": round(g_pk / g_p, 2)}
     del lats
     torch.cuda.empty_cache()
 
