@@ -138,9 +138,11 @@ __device__ __forceinline__ void xcd_wait(unsigned* ctr, unsigned target, Ctrl* c
 }
 
 // Arrival: every wave waits for its stores, then thread 0 adds `add` to the counter.
+// (The wait is an asm statement with a memory clobber, so that the compiler keeps
+// every store of the tile program above it.)
 __device__ __forceinline__ void xcd_arrive(unsigned* ctr, unsigned add)
 {
-    __builtin_amdgcn_s_waitcnt(0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -222,6 +224,9 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
     const int x = xcc_id();
     if (threadIdx.x == 0) {
         const unsigned r = __hip_atomic_fetch_add(&reg[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the rank is taken (the returning atomic has completed) before the
+        // workgroup counts as registered
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __hip_atomic_fetch_add(&reg[kXcd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         poll_at_least(&reg[kXcd], gridDim.x, ctrl);
         for (int y = 0; y < kXcd; ++y)
