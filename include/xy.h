@@ -302,6 +302,23 @@ int xy_hmc(xy_lattice* h, int64_t n_traj, int32_t n_md, double eps, void* hmc_wo
 int xy_hmc_set_steps_per_pass(xy_lattice* h, int32_t steps);
 int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
 
+/* Hybrid Monte Carlo on the four-replica texel (sections 1.2 and 3.2): the four
+ * replicas of a quad run their trajectories together, one pass over the float4
+ * state per leap-frog step, and the Metropolis step is a vector of four
+ * decisions z_r, each from the replica's own FP64 dH; replica r keeps
+ * z_r theta_new + (1 - z_r) theta_old.  Replica r follows bit for bit the
+ * trajectory that xy_hmc gives a single lattice with (seed_r, L, beta_r) and the
+ * same n_md and eps; its dH agrees to the rounding of FP64 sums taken in another
+ * order (a decision could differ only where u and exp(-dH) agree to that
+ * rounding).  Trajectories and xy_quad_sweep share the quad's counter, as for a
+ * lattice.  hmc_work: caller-owned device memory of at least
+ * xy_quad_hmc_work_bytes (momenta and saved angles, 32 L^2 bytes, plus partial
+ * sums).  obs_dev: NULL, or device memory for 4 n_traj records, replica r's
+ * record of trajectory j at obs_dev[j * 4 + r].  Errors as xy_hmc. */
+int xy_quad_hmc_work_bytes(int32_t L, size_t* bytes);
+int xy_quad_hmc(xy_quad* q, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
+                xy_hmc_obs* obs_dev);
+
 /* Batched hybrid Monte Carlo: n_traj trajectories of every lattice of an FP32
  * batch, the paper's update (section 1.2; see xy_hmc) applied to the replicas at
  * several temperatures of section 3.2 with one Metropolis accept per replica

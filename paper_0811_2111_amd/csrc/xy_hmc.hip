@@ -20,34 +20,23 @@
 #include <hip/hip_runtime.h>
 
 #include "xy_device.hpp"
+#include "xy_hmc_site.hpp"
 #include "xy_launch.hpp"
 #include "xy_reduce.hpp"
 
 using namespace xyd;
+using namespace xyd::hmc;
 
 namespace xyk {
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr float kMinus2Ln2 = -1.38629436111989061883f;   // -2 ln 2
 
 __device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-// Box-Muller, cosine branch: sqrt(-2 ln u1) cos(2 pi u2); the hardware log is
-// base 2 and the hardware cosine takes turns, so 2 pi u2 turns is u2.
-__device__ __forceinline__ float box_muller(uint32_t w1, uint32_t w2)
-{
-    const float r2 = kMinus2Ln2 * __builtin_amdgcn_logf(u01(w1));
-    return __builtin_sqrtf(r2) * __builtin_amdgcn_cosf(u01(w2));
-}
-
-// (cos, sin) of entry (c, y, k) and of its four neighbours in the other plane.
-struct Nb {
-    float c, s;                    // the site
-    float cl, sl, cr, sr, cu, su, cd, sd;
-};
-
+// The angle of entry (c, y, k) and the (cos, sin) of it and of its four
+// neighbours in the other plane.
 __device__ __forceinline__ Nb load_nb(const float* __restrict__ st, int L, int Hh, int c, int y, int k, float& th)
 {
     const int o = (c + y) & 1;
@@ -64,14 +53,6 @@ __device__ __forceinline__ Nb load_nb(const float* __restrict__ st, int L, int H
     sincos_turn(tu, n.su, n.cu);
     sincos_turn(td, n.sd, n.cd);
     return n;
-}
-
-// s_i sum c_j - c_i sum s_j = sum_j sin(theta_i - theta_j); F = -beta times this.
-__device__ __forceinline__ float sin_sum(const Nb& n)
-{
-    const float sc = nsum(n.cl, n.cr, n.cu, n.cd);
-    const float ss = nsum(n.sl, n.sr, n.su, n.sd);
-    return __fmaf_rn(n.s, sc, -__fmul_rn(n.c, ss));
 }
 
 // One partial record per wave: (Cx, Cy, Ix, Iy, Mx, My, K, 0).  Black sites add
@@ -617,29 +598,6 @@ __device__ void sum_records(const double* __restrict__ rec, int nrec, double out
 #pragma unroll
         for (int q = 0; q < 7; ++q) out[q] = (red[q] + red[7 + q]) + (red[14 + q] + red[21 + q]);
     __syncthreads();
-}
-
-// dH = H_new - H_old from the two sums (slot 6 = sum p^2/2, slots 0, 1 = the bond
-// cosines, H = K + beta E with E = -(Cx + Cy)); accept iff u < exp(-dH), u from
-// Philox (traj, 0, 3, 0).
-__device__ __forceinline__ void decide_core(const double o[7], const double n[7], double beta, uint32_t traj,
-                                            uint32_t k0, uint32_t k1, unsigned* __restrict__ flag,
-                                            xy_hmc_obs* __restrict__ obs)
-{
-    const double h_old = o[6] - beta * (o[0] + o[1]);
-    const double h_new = n[6] - beta * (n[0] + n[1]);
-    const double dH = h_new - h_old;
-    const u32x4 r = philox10(traj, 0u, 3u, 0u, k0, k1);
-    const double u = (double)u01(r.x);           // exact in FP32
-    const unsigned acc = u < exp(-dH) ? 1u : 0u;
-    *flag = acc;
-    if (obs) {
-        const double* s = acc ? n : o;
-        obs->traj = (uint64_t)traj + 1u;
-        obs->accepted = acc;
-        obs->dH = dH;
-        obs->cx = s[0]; obs->cy = s[1]; obs->ix = s[2]; obs->iy = s[3]; obs->mx = s[4]; obs->my = s[5];
-    }
 }
 
 // Metropolis step of the trajectory: one workgroup, on the chunk sums of the two

@@ -138,6 +138,31 @@ hipError_t launch_hmc_batch_trajectory(const BhLat* d, const uint32_t* start, in
                                        hipStream_t s);
 bool fused_supported(int L, int tile_x, int tile_y, int m);
 
+// ---- hybrid Monte Carlo on the four-replica texel (xy_quad_hmc.hip)
+struct QHmcKeys {
+    uint32_t k0[4], k1[4];        // Philox keys of the four replicas
+};
+struct QHmcBeta {
+    double b[4];
+};
+struct QuadHmcWork {
+    float4* p;          // momenta, one float4 per entry
+    float4* saved;      // angles at the start of the trajectory
+    unsigned* flag;     // the four accept decisions of the last trajectory
+    double* rec_old;    // partial records of H_old: replica r's at rec_old + r * records * 8
+    double* rec_new;
+    double* chunk_old;  // sums of 256 records each, per replica
+    double* chunk_new;
+};
+int quad_hmc_records(int L);          // partial records per replica and H sum
+size_t quad_hmc_work_bytes(int L);
+QuadHmcWork quad_hmc_carve(void* work, int L);
+// One trajectory of all four replicas of the float4 state (result back in
+// `state`, `pingpong` a second state-sized buffer); obs: NULL or 4 records.
+hipError_t launch_quad_hmc_trajectory(float4* state, float4* pingpong, const QuadHmcWork& w, int L,
+                                      const double beta[4], double eps, int n_md, uint32_t traj, const QHmcKeys& keys,
+                                      xy_hmc_obs* obs, hipStream_t s);
+
 // Fill n u64 words with zero (kernel, not a memset node: safe inside graphs).
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
 

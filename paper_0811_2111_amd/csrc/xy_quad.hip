@@ -310,6 +310,40 @@ int xy_quad_get_tile(const xy_quad* q, int32_t* tile_x, int32_t* tile_y)
     return XY_OK;
 }
 
+int xy_quad_hmc_work_bytes(int32_t L, size_t* bytes)
+{
+    if (!bytes) return XY_ESTATE;
+    if (!quad_L_ok(L)) return XY_EINVAL;
+    *bytes = xyk::quad_hmc_work_bytes(L);
+    return XY_OK;
+}
+
+int xy_quad_hmc(xy_quad* q, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
+                xy_hmc_obs* obs_dev)
+{
+    if (!quad_live(q)) return XY_ESTATE;
+    if (n_traj < 0 || n_md < 1 || !std::isfinite(eps) || !(eps > 0.0)) return XY_EINVAL;
+    if (!hmc_work) return XY_ESTATE;
+    if (hmc_len < xyk::quad_hmc_work_bytes(q->L)) return XY_ESIZE;
+    if (q->sweep + (uint64_t)n_traj >= 0xffffffffull) return XY_ERANGE;
+    const xyd::Params4 p = quad_params(q);
+    xyk::QHmcKeys keys;
+    for (int r = 0; r < 4; ++r) {
+        keys.k0[r] = p.k0[r];
+        keys.k1[r] = p.k1[r];
+    }
+    const xyk::QuadHmcWork w = xyk::quad_hmc_carve(hmc_work, q->L);
+    for (int64_t j = 0; j < n_traj; ++j) {
+        hipError_t e = XY_LAUNCH(xyk::launch_quad_hmc_trajectory(q->state, q->pingpong, w, q->L, q->beta, eps, n_md,
+                                                                 (uint32_t)q->sweep, keys,
+                                                                 obs_dev ? obs_dev + (size_t)j * 4 : nullptr,
+                                                                 q->stream));
+        if (e != hipSuccess) return xyr::hip_fail(e, "xy_quad_hmc: launch");
+        q->sweep += 1;
+    }
+    return XY_OK;
+}
+
 int xy_quad_free(xy_quad* q)
 {
     if (!quad_live(q)) return XY_ESTATE;

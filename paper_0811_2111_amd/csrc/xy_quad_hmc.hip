@@ -1,0 +1,309 @@
+// xy_quad_hmc.hip -- hybrid Monte Carlo (section 1.2) on the four-replica texel
+// (section 3.2): the four replicas of a float4 state run their leap-frog
+// trajectories together, one pass over the state per step, and the Metropolis
+// step is a vector of four decisions z_r, one per replica from its own FP64 dH;
+// replica r then keeps z_r theta_new + (1 - z_r) theta_old.
+//
+// Replica r follows bit for bit the trajectory of a single lattice with seed_r,
+// beta_r and the same eps and step count (xy_hmc): every per-site quantity is
+// formed by the single-lattice arithmetic (xy_hmc_site.hpp) from the replica's
+// own component, with the replica's key for its random numbers.  Only the
+// order of the FP64 sums of H differs, so dH agrees to rounding.
+//
+// One leap-frog step per launch: the angles ping-pong between the state and
+// the quad's second buffer, the momenta are updated in place.
+#include <hip/hip_runtime.h>
+
+#include "xy_device.hpp"
+#include "xy_hmc_site.hpp"
+#include "xy_launch.hpp"
+#include "xy_tile4.hpp"
+
+using namespace xyd;
+using namespace xyd::hmc;
+
+namespace xyk {
+
+namespace {
+
+constexpr int kQThreads = 256;
+
+__device__ __forceinline__ int qwrap(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// The four replicas' angles of entry (c, y, k) and of its four neighbours in the
+// other plane (the single-lattice neighbour rule, entries of 16 bytes).
+struct Nb4 {
+    float4 t, l, r, u, d;
+};
+
+__device__ __forceinline__ Nb4 load_nb4(const float4* __restrict__ st, int L, int Hh, int c, int y, int k)
+{
+    const int o = (c + y) & 1;
+    const float4* oth = st + (size_t)(1 - c) * L * Hh;
+    Nb4 n;
+    n.t = st[((size_t)c * L + y) * Hh + k];
+    n.l = oth[(size_t)y * Hh + qwrap(k + o - 1, Hh)];
+    n.r = oth[(size_t)y * Hh + qwrap(k + o, Hh)];
+    n.u = oth[(size_t)qwrap(y - 1, L) * Hh + k];
+    n.d = oth[(size_t)qwrap(y + 1, L) * Hh + k];
+    return n;
+}
+
+// Replica r's (cos, sin) of the entry and of its neighbours.
+__device__ __forceinline__ Nb replica_nb(const Nb4& a, int r)
+{
+    Nb n;
+    sincos_turn(f4c(a.t, r), n.s, n.c);
+    sincos_turn(f4c(a.l, r), n.sl, n.cl);
+    sincos_turn(f4c(a.r, r), n.sr, n.cr);
+    sincos_turn(f4c(a.u, r), n.su, n.cu);
+    sincos_turn(f4c(a.d, r), n.sd, n.cd);
+    return n;
+}
+
+// A site's terms of H (as the single-lattice records): a black site adds its four
+// bonds, its own spin and that of the red site to its right; every site adds p^2/2.
+__device__ __forceinline__ void add_site(double v[7], const Nb& n, int c, float kin)
+{
+    if (c == 1) {
+        Meas m{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        meas_black(m, n.c, n.s, n.cl, n.sl, n.cr, n.sr, n.cu, n.su, n.cd, n.sd);
+        v[0] += (double)m.cx; v[1] += (double)m.cy; v[2] += (double)m.ix;
+        v[3] += (double)m.iy; v[4] += (double)m.mx; v[5] += (double)m.my;
+    }
+    v[6] += (double)kin;
+}
+
+// One partial record per wave and replica: replica r's record of wave w of block
+// b at rec[(r nrec + b 4 + w) 8].
+__device__ __forceinline__ void write_records(double v[4][7], double* __restrict__ rec, int nrec, unsigned b)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int q = 0; q < 7; ++q) v[r][q] = wave_sum_last(v[r][q]);
+        if ((threadIdx.x & 63) == 63) {
+            double* o = rec + ((size_t)r * nrec + (size_t)b * (kQThreads / 64) + (threadIdx.x >> 6)) * 8;
+#pragma unroll
+            for (int q = 0; q < 7; ++q) o[q] = v[r][q];
+            o[7] = 0.0;
+        }
+    }
+}
+
+// Grid of the record-writing passes: cols x rb workgroups, cols = 2 ceil(Hh/256)
+// (column block, colour interleaved); block b takes column b % cols and the run
+// of R = ceil(L / rb) rows starting at (b / cols) R.
+struct QGrid {
+    int cols, rb;
+};
+
+// Momenta (Box-Muller of each replica's Philox purpose-2 words), saved angles,
+// partial records of H_old.
+__global__ void __launch_bounds__(kQThreads)
+k_qhmc_begin(const float4* __restrict__ st, float4* __restrict__ p, float4* __restrict__ saved, int L, uint32_t traj,
+             QHmcKeys keys, QGrid g, double* __restrict__ rec, int nrec)
+{
+    const int Hh = L >> 1, P = (Hh + 1) >> 1;
+    const unsigned b = blockIdx.x;
+    const int col = (int)(b % (unsigned)g.cols);
+    const int k = (col >> 1) * kQThreads + threadIdx.x;
+    const int c = col & 1;
+    double v[4][7] = {};
+    const int R = (L + g.rb - 1) / g.rb, y0 = (int)(b / (unsigned)g.cols) * R, y1 = y0 + R < L ? y0 + R : L;
+    if (k < Hh) {
+        for (int y = y0; y < y1; ++y) {
+            const Nb4 a = load_nb4(st, L, Hh, c, y, k);
+            const size_t i = ((size_t)c * L + y) * Hh + k;
+            saved[i] = a.t;
+            float4 pm;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const u32x4 w = philox10(traj, (uint32_t)c, 2u, (uint32_t)y * (uint32_t)P + (uint32_t)(k >> 1),
+                                         keys.k0[r], keys.k1[r]);
+                const float pr = (k & 1) ? box_muller(w.z, w.w) : box_muller(w.x, w.y);
+                f4set(pm, r, pr);
+                add_site(v[r], replica_nb(a, r), c, __fmul_rn(0.5f, __fmul_rn(pr, pr)));
+            }
+            p[i] = pm;
+        }
+    }
+    write_records(v, rec, nrec, b);       // every lane reaches the wave sums
+}
+
+// One leap-frog step of every replica: p += kick_r F, then a drift of
+// eps/(2 pi) p turns.  Grid (2 ceil(Hh/256), L).
+__global__ void __launch_bounds__(kQThreads)
+k_qhmc_step(const float4* __restrict__ src, float4* __restrict__ dst, float4* __restrict__ p, int L, float4 kick,
+            float drift)
+{
+    const int Hh = L >> 1;
+    const int k = (blockIdx.x >> 1) * kQThreads + threadIdx.x;
+    if (k >= Hh) return;
+    const int y = blockIdx.y, c = blockIdx.x & 1;
+    const Nb4 a = load_nb4(src, L, Hh, c, y, k);
+    const size_t i = ((size_t)c * L + y) * Hh + k;
+    float4 pv = p[i], th;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float pn = __fmaf_rn(f4c(kick, r), sin_sum(replica_nb(a, r)), f4c(pv, r));
+        f4set(pv, r, pn);
+        f4set(th, r, __builtin_amdgcn_fractf(__fmaf_rn(drift, pn, f4c(a.t, r))));
+    }
+    p[i] = pv;
+    dst[i] = th;
+}
+
+// Final half kick and the partial records of H_new; `copy` != NULL receives the
+// angles (the final ones may sit in the second buffer).
+__global__ void __launch_bounds__(kQThreads)
+k_qhmc_end(const float4* __restrict__ st, float4* __restrict__ copy, const float4* __restrict__ p, int L,
+           float4 kick, QGrid g, double* __restrict__ rec, int nrec)
+{
+    const int Hh = L >> 1;
+    const unsigned b = blockIdx.x;
+    const int col = (int)(b % (unsigned)g.cols);
+    const int k = (col >> 1) * kQThreads + threadIdx.x;
+    const int c = col & 1;
+    double v[4][7] = {};
+    const int R = (L + g.rb - 1) / g.rb, y0 = (int)(b / (unsigned)g.cols) * R, y1 = y0 + R < L ? y0 + R : L;
+    if (k < Hh) {
+        for (int y = y0; y < y1; ++y) {
+            const Nb4 a = load_nb4(st, L, Hh, c, y, k);
+            const size_t i = ((size_t)c * L + y) * Hh + k;
+            if (copy) copy[i] = a.t;
+            const float4 pv = p[i];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const Nb n = replica_nb(a, r);
+                const float pn = __fmaf_rn(f4c(kick, r), sin_sum(n), f4c(pv, r));
+                add_site(v[r], n, c, __fmul_rn(0.5f, __fmul_rn(pn, pn)));
+            }
+        }
+    }
+    write_records(v, rec, nrec, b);
+}
+
+// The vector Metropolis step: workgroup r sums replica r's chunk records of
+// H_old and H_new in a fixed order and takes its decision (flag[r], obs[r]).
+__global__ void __launch_bounds__(kQThreads)
+k_qhmc_decide(const double* __restrict__ chunk_old, const double* __restrict__ chunk_new, int nchunk, QHmcBeta beta,
+              uint32_t traj, QHmcKeys keys, unsigned* __restrict__ flag, xy_hmc_obs* __restrict__ obs)
+{
+    const int r = (int)blockIdx.x;
+    if (threadIdx.x != 0) return;
+    double o[7] = {}, n[7] = {};
+    const double* co = chunk_old + (size_t)r * nchunk * 8;
+    const double* cn = chunk_new + (size_t)r * nchunk * 8;
+    for (int j = 0; j < nchunk; ++j)
+#pragma unroll
+        for (int q = 0; q < 7; ++q) {
+            o[q] += co[(size_t)j * 8 + q];
+            n[q] += cn[(size_t)j * 8 + q];
+        }
+    decide_core(o, n, beta.b[r], traj, keys.k0[r], keys.k1[r], flag + r, obs ? obs + r : nullptr);
+}
+
+// Rejected replicas: their components of the saved angles back into the state.
+__global__ void __launch_bounds__(kQThreads)
+k_qhmc_restore(const unsigned* __restrict__ flag, const float4* __restrict__ saved, float4* __restrict__ st, size_t n)
+{
+    const unsigned z0 = flag[0], z1 = flag[1], z2 = flag[2], z3 = flag[3];
+    if (z0 & z1 & z2 & z3) return;
+    for (size_t i = (size_t)blockIdx.x * kQThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kQThreads) {
+        const float4 a = st[i], s = saved[i];
+        st[i] = make_float4(z0 ? a.x : s.x, z1 ? a.y : s.y, z2 ? a.z : s.z, z3 ? a.w : s.w);
+    }
+}
+
+QGrid qgrid(int L)
+{
+    QGrid g;
+    g.cols = 2 * (((L >> 1) + kQThreads - 1) / kQThreads);
+    const int rb = 4096 / g.cols;
+    g.rb = rb < L ? (rb > 0 ? rb : 1) : L;
+    return g;
+}
+
+}  // namespace
+
+int quad_hmc_records(int L)
+{
+    const QGrid g = qgrid(L);
+    return g.cols * g.rb * (kQThreads / 64);
+}
+
+size_t quad_hmc_work_bytes(int L)
+{
+    const size_t st = ((size_t)L * L * sizeof(float4) + 255) & ~(size_t)255;
+    const size_t nrec = (size_t)quad_hmc_records(L), nch = (nrec + 255) / 256;
+    return 2 * st + 256 + 2 * 4 * (nrec + nch) * 8 * sizeof(double);
+}
+
+QuadHmcWork quad_hmc_carve(void* work, int L)
+{
+    const size_t st = ((size_t)L * L * sizeof(float4) + 255) & ~(size_t)255;
+    const size_t nrec = (size_t)quad_hmc_records(L), nch = (nrec + 255) / 256;
+    char* b = (char*)work;
+    QuadHmcWork w;
+    w.p = (float4*)b;
+    b += st;
+    w.saved = (float4*)b;
+    b += st;
+    w.flag = (unsigned*)b;
+    b += 256;
+    w.rec_old = (double*)b;
+    b += 4 * nrec * 8 * sizeof(double);
+    w.rec_new = (double*)b;
+    b += 4 * nrec * 8 * sizeof(double);
+    w.chunk_old = (double*)b;
+    b += 4 * nch * 8 * sizeof(double);
+    w.chunk_new = (double*)b;
+    return w;
+}
+
+hipError_t launch_quad_hmc_trajectory(float4* state, float4* pingpong, const QuadHmcWork& w, int L,
+                                      const double beta[4], double eps, int n_md, uint32_t traj, const QHmcKeys& keys,
+                                      xy_hmc_obs* obs, hipStream_t s)
+{
+    const QGrid g = qgrid(L);
+    const int nrec = quad_hmc_records(L), nchunk = (nrec + 255) / 256;
+    const dim3 grec((unsigned)(g.cols * g.rb)), gstep((unsigned)g.cols, (unsigned)L), block(kQThreads);
+    // the single-lattice launcher's FP32 constants, per replica
+    const float drift = (float)(eps / (2.0 * 3.14159265358979323846));
+    float kh[4], kf[4];
+    QHmcBeta qb;
+    for (int r = 0; r < 4; ++r) {
+        kh[r] = (float)(-beta[r] * 0.5 * eps);
+        kf[r] = (float)(-beta[r] * eps);
+        qb.b[r] = beta[r];
+    }
+    const float4 kick_half = make_float4(kh[0], kh[1], kh[2], kh[3]);
+    const float4 kick_full = make_float4(kf[0], kf[1], kf[2], kf[3]);
+    hipLaunchKernelGGL(k_qhmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, keys, g, w.rec_old, nrec);
+    float4* src = state;
+    float4* dst = pingpong;
+    for (int q = 0; q < n_md; ++q) {
+        hipLaunchKernelGGL(k_qhmc_step, gstep, block, 0, s, src, dst, w.p, L, q == 0 ? kick_half : kick_full, drift);
+        float4* t = src;
+        src = dst;
+        dst = t;
+    }
+    hipLaunchKernelGGL(k_qhmc_end, grec, block, 0, s, src, src == state ? nullptr : state, w.p, L, kick_half, g,
+                       w.rec_new, nrec);
+    hipError_t e = hipGetLastError();
+    for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+        e = launch_reduce_chunks(w.rec_old + (size_t)r * nrec * 8, nrec, w.chunk_old + (size_t)r * nchunk * 8, s);
+        if (e == hipSuccess)
+            e = launch_reduce_chunks(w.rec_new + (size_t)r * nrec * 8, nrec, w.chunk_new + (size_t)r * nchunk * 8, s);
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_qhmc_decide, dim3(4), block, 0, s, w.chunk_old, w.chunk_new, nchunk, qb, traj, keys, w.flag,
+                       obs);
+    const size_t n = (size_t)L * (size_t)L;
+    const unsigned nb = (unsigned)((n + kQThreads * 8 - 1) / (kQThreads * 8));
+    hipLaunchKernelGGL(k_qhmc_restore, dim3(nb < 4096 ? nb : 4096), block, 0, s, w.flag, w.saved, state, n);
+    return hipGetLastError();
+}
+
+}  // namespace xyk

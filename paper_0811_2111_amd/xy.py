@@ -118,6 +118,8 @@ def _load():
         "xy_quad_get_tile": [vp, P(i32), P(i32)],
         "xy_quad_free": [vp],
         "xy_hmc": [vp, i64, i32, dbl, vp, sz, vp],
+        "xy_quad_hmc_work_bytes": [i32, P(sz)],
+        "xy_quad_hmc": [vp, i64, i32, dbl, vp, sz, vp],
         "xy_batch_set_spin_limit": [vp, ctypes.c_uint32],
         "xy_test_inject_failure": [i32],
         "xy_sweep_noalloc": [u64, i32, dbl, dbl, i32, u64, i64, i32, vp, sz, vp, vp],
@@ -548,6 +550,24 @@ class Quad:
             _check_out(out, nrec * 4 * 64, self.state.device, "xy_quad_sweep")
         check(_lib.xy_quad_sweep(self.h, int(n), int(measure_every), _ptr(out) if nrec else None), "xy_quad_sweep")
         return out
+
+    def hmc(self, n_traj: int, n_md: int, eps: float, out=None):
+        """n_traj HMC trajectories of all four replicas (n_md leap-frog steps of size
+        eps, one accept decision per replica); returns a device tensor (n_traj, 4, 9)
+        of xy_hmc_obs records (see hmc_records)."""
+        import torch
+        if getattr(self, "hmc_work", None) is None:
+            b = ctypes.c_size_t()
+            check(_lib.xy_quad_hmc_work_bytes(self.L, ctypes.byref(b)), "xy_quad_hmc_work_bytes")
+            self.hmc_work = torch.empty((b.value,), dtype=torch.uint8, device=self.state.device)
+        if out is None:
+            out = torch.empty((max(int(n_traj), 1), 4, 9), dtype=torch.float64, device=self.state.device)
+        if n_traj > 0:
+            _check_out(out, int(n_traj) * 4 * 72, self.state.device, "xy_quad_hmc")
+        rc = _lib.xy_quad_hmc(self.h, int(n_traj), int(n_md), float(eps), _ptr(self.hmc_work),
+                              _nbytes(self.hmc_work), _ptr(out) if n_traj > 0 else None)
+        check(rc, "xy_quad_hmc")
+        return out[: int(n_traj)]
 
     def set_params(self, betas, deltas):
         check(_lib.xy_quad_set_params(self.h, (ctypes.c_double * 4)(*betas), (ctypes.c_double * 4)(*deltas)),
