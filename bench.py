@@ -152,7 +152,8 @@ def parse():
                     help="fixed plan 'kind,tile_x,tile_y,sweeps_per_pass' instead of autotuning")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", choices=["l4096", "l4096_tuned", "l16384", "batch", "hmc", "hmc_batch", "quad", "fp16",
+    ap.add_argument("--workload", choices=["l4096", "l4096_tuned", "l16384", "batch", "hmc", "hmc_batch", "quad",
+                                           "quad_hmc", "fp16",
                                            "tempering", "small"],
                     default="l16384",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
@@ -444,6 +445,8 @@ def profile_leg(args, stream):
         ms = timed(lambda: b.sweep(args.steps, 10), stream)
         res["batch_2048"] = {"gupd_s": float(pc["L"]) ** 2 * n * args.steps / (ms * 1e-3) / 1e9}
         print(json.dumps({"workload": "L32", "sweeps": args.steps, **res}))
+    elif args.workload == "quad_hmc":
+        print(json.dumps({"workload": "quad HMC L4096", **quad_hmc_leg(stream, singles=False)}))
     elif args.workload == "tempering":
         sc = workloads.temperature_scan()
         tb = xy.Batch(sc["Ls"], sc["seeds"], sc["betas"], sc["deltas"])
@@ -580,6 +583,10 @@ def extra_legs(stream, args=None):
                         "four_single_lattices_gupd_s": round(upd / (ms_s * 1e-3) / 1e9, 2),
                         "sweeps": qc["sweeps"], "betas": qc["betas"]}
 
+    # HMC on the four-replica texel (a vector of four accept decisions) against the
+    # same trajectories of the four single lattices
+    ex["quad_hmc_L4096"] = quad_hmc_leg(stream)
+
     # batched HMC over the temperature scan (one accept per lattice) against the
     # same trajectories run lattice by lattice
     hb = workloads.HMC_SCAN
@@ -638,6 +645,45 @@ def extra_legs(stream, args=None):
         del lt, out
         torch.cuda.empty_cache()
     return ex
+
+
+def quad_hmc_leg(stream, singles=True):
+    import torch
+
+    from paper_0811_2111_amd import workloads, xy
+    hc = workloads.QUAD_HMC_4096
+    qd = xy.Quad(hc["L"], hc["seeds"], hc["betas"])
+    qd.sweep(hc["therm"])
+    qd.hmc(1, hc["n_md"], hc["eps"])
+    out = torch.empty((hc["traj"], 4, 9), dtype=torch.float64, device="cuda")
+    ms_q = timed(lambda: qd.hmc(hc["traj"], hc["n_md"], hc["eps"], out=out), stream)
+    r = xy.hmc_records(out)
+    del qd
+    torch.cuda.empty_cache()
+    steps = 4.0 * float(hc["L"]) ** 2 * hc["n_md"] * hc["traj"]
+    # algorithmic bytes per replica site of a trajectory, one step per pass: the
+    # begin (read 4, write 8), n_md steps of angle + momentum read and written
+    # (16 B), the end (read 8, plus the angles written back, 4, for an odd n_md)
+    traj_bytes = 12.0 + ALG_BYTES_HMC_STEP * hc["n_md"] + 8.0 + (4.0 if hc["n_md"] % 2 else 0.0)
+    gbs = 4.0 * float(hc["L"]) ** 2 * traj_bytes * hc["traj"] / (ms_q * 1e-3) / 1e9
+    res = {"g_replica_site_steps_s": round(steps / (ms_q * 1e-3) / 1e9, 2), "trajectories": hc["traj"],
+           "n_md": hc["n_md"], "eps": hc["eps"], "betas": hc["betas"], "ms": round(ms_q, 2),
+           "accept_rate": round(float(r["accepted"].mean()), 3), "alg_bytes_per_replica_site_traj": traj_bytes,
+           "hbm_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    if singles:
+        lats = [xy.Lattice(hc["L"], seed=s_, beta=b_) for s_, b_ in zip(hc["seeds"], hc["betas"])]
+        for lt in lats:
+            lt.sweep(hc["therm"])
+            lt.hmc(1, hc["n_md"], hc["eps"])
+
+        def four():
+            for lt in lats:
+                lt.hmc(hc["traj"], hc["n_md"], hc["eps"])
+        ms_s = timed(four, stream)
+        res["four_single_lattices_g_site_steps_s"] = round(steps / (ms_s * 1e-3) / 1e9, 2)
+        del lats
+        torch.cuda.empty_cache()
+    return res
 
 
 def cpu_baseline(cfg, sweeps):

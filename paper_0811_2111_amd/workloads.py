@@ -36,6 +36,8 @@ HMC_4096 = dict(L=4096, beta=1.0, eps=0.02, n_md=20, seed=1, therm=500, traj=50)
 HMC_16384 = dict(L=16384, beta=1.0, eps=0.01, n_md=20, seed=1, therm=200, traj=20)
 # batched HMC over the temperature scan (lattices of L = 64 .. 1024, their own beta)
 HMC_SCAN = dict(eps=0.04, n_md=20, therm=100, traj=20, traj_per_lattice_timed=5)
+# HMC on the four-replica texel: the quad's four temperatures, the L = 4096 step
+QUAD_HMC_4096 = dict(L=4096, seeds=[1, 2, 3, 4], betas=[0.9, 1.0, 1.12, 1.3], eps=0.02, n_md=20, therm=200, traj=10)
 
 
 def temperature_scan(n: int = 96, sizes=(64, 128, 256, 512, 1024), beta_lo: float = 0.80,
