@@ -143,3 +143,26 @@ def test_quad_hmc_error_codes():
     q.hmc(1, 5, 0.1)
     assert q.sweep_count == 2 ** 32 - 2
     torch.cuda.synchronize()
+
+
+def test_quad_hmc_bench_size_equals_single_lattices():
+    """The benchmark's configuration (L = 4096, beta 0.9 .. 1.3, eps = 0.02, 20
+    steps) after Metropolis sweeps: two trajectories, every replica's angles bit
+    for bit those of its single lattice (7-step passes on 64 x 64 tiles there,
+    one step per pass here)."""
+    from paper_0811_2111_amd import workloads
+    hc = workloads.QUAD_HMC_4096
+    L = hc["L"]
+    q = xy.Quad(L, hc["seeds"], hc["betas"])
+    q.sweep(3)
+    rec = xy.hmc_records(q.hmc(2, hc["n_md"], hc["eps"]))
+    for r in range(4):
+        lat = xy.Lattice(L, seed=hc["seeds"][r], beta=hc["betas"][r])
+        lat.sweep(3)
+        srec = xy.hmc_records(lat.hmc(2, hc["n_md"], hc["eps"]))
+        assert lat.hmc_steps_per_pass == 7
+        assert_replica_matches(rec, srec, r, L)
+        assert torch.equal(q.replica_state(r), lat.state), r
+        del lat
+    del q
+    torch.cuda.empty_cache()
