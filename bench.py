@@ -658,17 +658,20 @@ def quad_hmc_leg(stream, singles=True):
     out = torch.empty((hc["traj"], 4, 9), dtype=torch.float64, device="cuda")
     ms_q = timed(lambda: qd.hmc(hc["traj"], hc["n_md"], hc["eps"], out=out), stream)
     r = xy.hmc_records(out)
+    k = qd.hmc_steps_per_pass
     del qd
     torch.cuda.empty_cache()
     steps = 4.0 * float(hc["L"]) ** 2 * hc["n_md"] * hc["traj"]
-    # algorithmic bytes per replica site of a trajectory, one step per pass: the
-    # begin (read 4, write 8), n_md steps of angle + momentum read and written
-    # (16 B), the end (read 8, plus the angles written back, 4, for an odd n_md)
-    traj_bytes = 12.0 + ALG_BYTES_HMC_STEP * hc["n_md"] + 8.0 + (4.0 if hc["n_md"] % 2 else 0.0)
+    # algorithmic bytes per replica site of a trajectory: the begin (read 4, write
+    # 8), ceil(n_md / k) passes of angle + momentum read and written (16 B), the
+    # end (read 8, plus the angles written back, 4, when the pass count is odd)
+    passes = -(-hc["n_md"] // k)
+    traj_bytes = 12.0 + ALG_BYTES_HMC_STEP * passes + 8.0 + (4.0 if passes % 2 else 0.0)
     gbs = 4.0 * float(hc["L"]) ** 2 * traj_bytes * hc["traj"] / (ms_q * 1e-3) / 1e9
     res = {"g_replica_site_steps_s": round(steps / (ms_q * 1e-3) / 1e9, 2), "trajectories": hc["traj"],
            "n_md": hc["n_md"], "eps": hc["eps"], "betas": hc["betas"], "ms": round(ms_q, 2),
-           "accept_rate": round(float(r["accepted"].mean()), 3), "alg_bytes_per_replica_site_traj": traj_bytes,
+           "accept_rate": round(float(r["accepted"].mean()), 3), "steps_per_pass": k,
+           "alg_bytes_per_replica_site_traj": traj_bytes,
            "hbm_GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     if singles:
         lats = [xy.Lattice(hc["L"], seed=s_, beta=b_) for s_, b_ in zip(hc["seeds"], hc["betas"])]

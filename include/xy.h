@@ -312,12 +312,20 @@ int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
  * order (a decision could differ only where u and exp(-dH) agree to that
  * rounding).  Trajectories and xy_quad_sweep share the quad's counter, as for a
  * lattice.  hmc_work: caller-owned device memory of at least
- * xy_quad_hmc_work_bytes (momenta and saved angles, 32 L^2 bytes, plus partial
- * sums).  obs_dev: NULL, or device memory for 4 n_traj records, replica r's
- * record of trajectory j at obs_dev[j * 4 + r].  Errors as xy_hmc. */
+ * xy_quad_hmc_work_bytes (two momentum buffers and the saved angles, 48 L^2
+ * bytes, plus partial sums).  obs_dev: NULL, or device memory for 4 n_traj
+ * records, replica r's record of trajectory j at obs_dev[j * 4 + r].  Errors as
+ * xy_hmc. */
 int xy_quad_hmc_work_bytes(int32_t L, size_t* bytes);
 int xy_quad_hmc(xy_quad* q, int64_t n_traj, int32_t n_md, double eps, void* hmc_work, size_t hmc_len,
                 xy_hmc_obs* obs_dev);
+/* Leap-frog steps per pass of xy_quad_hmc (1 .. 4, default 4; XY_EINVAL
+ * otherwise): with more than one, a workgroup loads a 32 x 32 tile grown by that
+ * many sites on every side, runs the steps on it and writes the tile back, as
+ * xy_hmc_set_steps_per_pass does for a lattice; 1: one step per pass over the
+ * state.  The trajectory is bit for bit the same. */
+int xy_quad_hmc_set_steps_per_pass(xy_quad* q, int32_t steps);
+int xy_quad_hmc_get_steps_per_pass(const xy_quad* q, int32_t* steps);
 
 /* Batched hybrid Monte Carlo: n_traj trajectories of every lattice of an FP32
  * batch, the paper's update (section 1.2; see xy_hmc) applied to the replicas at

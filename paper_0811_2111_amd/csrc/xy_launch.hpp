@@ -148,6 +148,7 @@ struct QHmcBeta {
 struct QuadHmcWork {
     float4* p;          // momenta, one float4 per entry
     float4* saved;      // angles at the start of the trajectory
+    float4* p2;         // second momentum buffer (passes of several steps)
     unsigned* flag;     // the four accept decisions of the last trajectory
     double* rec_old;    // partial records of H_old: replica r's at rec_old + r * records * 8
     double* rec_new;
@@ -159,9 +160,11 @@ size_t quad_hmc_work_bytes(int L);
 QuadHmcWork quad_hmc_carve(void* work, int L);
 // One trajectory of all four replicas of the float4 state (result back in
 // `state`, `pingpong` a second state-sized buffer); obs: NULL or 4 records.
+// steps_per_pass > 1: leap-frog steps in passes of up to min(steps_per_pass, 4)
+// (L % 32 == 0, as every quad); 1: one step per launch.  Same trajectory.
 hipError_t launch_quad_hmc_trajectory(float4* state, float4* pingpong, const QuadHmcWork& w, int L,
-                                      const double beta[4], double eps, int n_md, uint32_t traj, const QHmcKeys& keys,
-                                      xy_hmc_obs* obs, hipStream_t s);
+                                      const double beta[4], double eps, int n_md, int steps_per_pass, uint32_t traj,
+                                      const QHmcKeys& keys, xy_hmc_obs* obs, hipStream_t s);
 
 // Fill n u64 words with zero (kernel, not a memset node: safe inside graphs).
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);

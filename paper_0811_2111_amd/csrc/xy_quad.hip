@@ -157,6 +157,7 @@ struct xy_quad {
     hipStream_t stream;
     uint64_t sweep;
     int32_t tile_x, tile_y;
+    int32_t hmc_steps;     // leap-frog steps per pass of xy_quad_hmc (1 .. 4)
 };
 
 static bool quad_live(const xy_quad* q) { return q && q->magic == kQuadMagic; }
@@ -215,6 +216,7 @@ int xy_quad_init(xy_quad** out, const uint64_t* seeds, int32_t L, const double* 
     q->sweep = 0;
     q->tile_x = L % 128 == 0 ? 128 : 32;
     q->tile_y = L % 128 == 0 ? 8 : 16;
+    q->hmc_steps = 4;
     const int Hh = L / 2, P = (Hh + 1) / 2;
     hipLaunchKernelGGL(xyk::k_quad_init, dim3((P + 63) / 64, (L + 3) / 4, 2), dim3(64, 4), 0, q->stream, q->state, L,
                        quad_params(q), start == XY_HOT ? 1 : 0);
@@ -335,12 +337,27 @@ int xy_quad_hmc(xy_quad* q, int64_t n_traj, int32_t n_md, double eps, void* hmc_
     const xyk::QuadHmcWork w = xyk::quad_hmc_carve(hmc_work, q->L);
     for (int64_t j = 0; j < n_traj; ++j) {
         hipError_t e = XY_LAUNCH(xyk::launch_quad_hmc_trajectory(q->state, q->pingpong, w, q->L, q->beta, eps, n_md,
-                                                                 (uint32_t)q->sweep, keys,
+                                                                 q->hmc_steps, (uint32_t)q->sweep, keys,
                                                                  obs_dev ? obs_dev + (size_t)j * 4 : nullptr,
                                                                  q->stream));
         if (e != hipSuccess) return xyr::hip_fail(e, "xy_quad_hmc: launch");
         q->sweep += 1;
     }
+    return XY_OK;
+}
+
+int xy_quad_hmc_set_steps_per_pass(xy_quad* q, int32_t steps)
+{
+    if (!quad_live(q)) return XY_ESTATE;
+    if (steps < 1 || steps > 4) return XY_EINVAL;
+    q->hmc_steps = steps;
+    return XY_OK;
+}
+
+int xy_quad_hmc_get_steps_per_pass(const xy_quad* q, int32_t* steps)
+{
+    if (!quad_live(q) || !steps) return XY_ESTATE;
+    *steps = q->hmc_steps;
     return XY_OK;
 }
 

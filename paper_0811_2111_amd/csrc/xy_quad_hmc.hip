@@ -10,8 +10,9 @@
 // own component, with the replica's key for its random numbers.  Only the
 // order of the FP64 sums of H differs, so dH agrees to rounding.
 //
-// One leap-frog step per launch: the angles ping-pong between the state and
-// the quad's second buffer, the momenta are updated in place.
+// The angles ping-pong between the state and the quad's second buffer: one
+// leap-frog step per launch (momenta updated in place), or passes of up to four
+// steps on 32 x 32 tiles grown by the step count (momenta ping-pong too).
 #include <hip/hip_runtime.h>
 
 #include "xy_device.hpp"
@@ -154,6 +155,129 @@ k_qhmc_step(const float4* __restrict__ src, float4* __restrict__ dst, float4* __
     dst[i] = th;
 }
 
+// K leap-frog steps per pass (temporal blocking, as the single lattice's passes):
+// a workgroup owns a 32 x 32 tile of sites (natural coordinates) and loads the
+// float4 angles and momenta of the tile grown by K sites on every side into
+// registers; step q updates the sites more than q from the edge of the grown
+// tile; the tile itself is then exact and is written to dst / pdst (the momenta
+// ping-pong too, since other tiles read this tile's old momenta as their halo).
+// The four replicas' (cos, sin) sit in one LDS buffer (32 bytes a site): every
+// update of a step reads its neighbours, barrier, the new values are written,
+// barrier.  Per replica and site the arithmetic is that of k_qhmc_step.
+constexpr int kQTile = 32;
+constexpr int kQMaxSteps = 4;
+
+__device__ __forceinline__ unsigned qxcd_band(unsigned b, unsigned nb)
+{
+    if ((nb & 7u) != 0u) return b;
+    return (b & 7u) * (nb >> 3) + (b >> 3);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kQThreads)
+k_qhmc_multi(const float4* __restrict__ src, float4* __restrict__ dst, const float4* __restrict__ psrc,
+             float4* __restrict__ pdst, int L, float4 kick0, float4 kick, float drift)
+{
+    constexpr int T = kQTile, E = T + 2 * K, NE = E * E, M = (NE + kQThreads - 1) / kQThreads;
+    __shared__ float4 cs[2 * NE];          // site i: cos at 2i, sin at 2i + 1
+    const int Hh = L >> 1, nt = L / T;
+    const int b = (int)qxcd_band(blockIdx.x, gridDim.x);
+    const int ty = b / nt, tx = b - ty * nt;
+    const int x0 = tx * T - K, y0 = ty * T - K;
+    float4 th[M], pm[M];
+    unsigned off[M];
+    int dep[M];       // distance of the slot's site from the grown tile's edge (-1: no site)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = threadIdx.x + m * kQThreads;
+        dep[m] = -1;
+        if (i < NE) {
+            const int ye = i / E, xe = i - ye * E;
+            dep[m] = min(min(xe, E - 1 - xe), min(ye, E - 1 - ye));
+            const int x = qwrap(x0 + xe, L), y = qwrap(y0 + ye, L);
+            off[m] = (unsigned)((((x + y) & 1) * L + y) * Hh + (x >> 1));
+            th[m] = src[off[m]];
+            pm[m] = psrc[off[m]];
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int i = threadIdx.x + m * kQThreads;
+        if (i < NE) {
+            float4 c4, s4;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float sn, cn;
+                sincos_turn(f4c(th[m], r), sn, cn);
+                f4set(c4, r, cn);
+                f4set(s4, r, sn);
+            }
+            cs[2 * i] = c4;
+            cs[2 * i + 1] = s4;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const float4 kq = q == 0 ? kick0 : kick;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int i = threadIdx.x + m * kQThreads;
+            if (dep[m] > q) {
+                const float4 oc = cs[2 * i], os = cs[2 * i + 1];
+                const float4 lc = cs[2 * (i - 1)], ls = cs[2 * (i - 1) + 1];
+                const float4 rc = cs[2 * (i + 1)], rs = cs[2 * (i + 1) + 1];
+                const float4 uc = cs[2 * (i - E)], us = cs[2 * (i - E) + 1];
+                const float4 dc = cs[2 * (i + E)], ds = cs[2 * (i + E) + 1];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    Nb n;
+                    n.c = f4c(oc, r); n.s = f4c(os, r);
+                    n.cl = f4c(lc, r); n.sl = f4c(ls, r); n.cr = f4c(rc, r); n.sr = f4c(rs, r);
+                    n.cu = f4c(uc, r); n.su = f4c(us, r); n.cd = f4c(dc, r); n.sd = f4c(ds, r);
+                    const float pn = __fmaf_rn(f4c(kq, r), sin_sum(n), f4c(pm[m], r));
+                    f4set(pm[m], r, pn);
+                    f4set(th[m], r, __builtin_amdgcn_fractf(__fmaf_rn(drift, pn, f4c(th[m], r))));
+                }
+            }
+        }
+        if (q + 1 < K) {
+            __syncthreads();          // every read of this step is done
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int i = threadIdx.x + m * kQThreads;
+                if (dep[m] > q) {
+                    float4 c4, s4;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float sn, cn;
+                        sincos_turn(f4c(th[m], r), sn, cn);
+                        f4set(c4, r, cn);
+                        f4set(s4, r, sn);
+                    }
+                    cs[2 * i] = c4;
+                    cs[2 * i + 1] = s4;
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        if (dep[m] >= K) {           // the tile itself
+            dst[off[m]] = th[m];
+            pdst[off[m]] = pm[m];
+        }
+    }
+}
+
+template <int K>
+static void launch_qmulti(unsigned nb, hipStream_t s, const float4* src, float4* dst, const float4* psrc,
+                          float4* pdst, int L, float4 kick0, float4 kick, float drift)
+{
+    hipLaunchKernelGGL(k_qhmc_multi<K>, dim3(nb), dim3(kQThreads), 0, s, src, dst, psrc, pdst, L, kick0, kick, drift);
+}
+
 // Final half kick and the partial records of H_new; `copy` != NULL receives the
 // angles (the final ones may sit in the second buffer).
 __global__ void __launch_bounds__(kQThreads)
@@ -237,7 +361,7 @@ size_t quad_hmc_work_bytes(int L)
 {
     const size_t st = ((size_t)L * L * sizeof(float4) + 255) & ~(size_t)255;
     const size_t nrec = (size_t)quad_hmc_records(L), nch = (nrec + 255) / 256;
-    return 2 * st + 256 + 2 * 4 * (nrec + nch) * 8 * sizeof(double);
+    return 3 * st + 256 + 2 * 4 * (nrec + nch) * 8 * sizeof(double);
 }
 
 QuadHmcWork quad_hmc_carve(void* work, int L)
@@ -249,6 +373,8 @@ QuadHmcWork quad_hmc_carve(void* work, int L)
     w.p = (float4*)b;
     b += st;
     w.saved = (float4*)b;
+    b += st;
+    w.p2 = (float4*)b;
     b += st;
     w.flag = (unsigned*)b;
     b += 256;
@@ -263,8 +389,8 @@ QuadHmcWork quad_hmc_carve(void* work, int L)
 }
 
 hipError_t launch_quad_hmc_trajectory(float4* state, float4* pingpong, const QuadHmcWork& w, int L,
-                                      const double beta[4], double eps, int n_md, uint32_t traj, const QHmcKeys& keys,
-                                      xy_hmc_obs* obs, hipStream_t s)
+                                      const double beta[4], double eps, int n_md, int steps_per_pass, uint32_t traj,
+                                      const QHmcKeys& keys, xy_hmc_obs* obs, hipStream_t s)
 {
     const QGrid g = qgrid(L);
     const int nrec = quad_hmc_records(L), nchunk = (nrec + 255) / 256;
@@ -283,13 +409,39 @@ hipError_t launch_quad_hmc_trajectory(float4* state, float4* pingpong, const Qua
     hipLaunchKernelGGL(k_qhmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, keys, g, w.rec_old, nrec);
     float4* src = state;
     float4* dst = pingpong;
-    for (int q = 0; q < n_md; ++q) {
-        hipLaunchKernelGGL(k_qhmc_step, gstep, block, 0, s, src, dst, w.p, L, q == 0 ? kick_half : kick_full, drift);
-        float4* t = src;
-        src = dst;
-        dst = t;
+    float4* p = w.p;
+    if (steps_per_pass > 1) {
+        // passes of up to min(steps_per_pass, kQMaxSteps) steps; the momenta ping-pong between p and p2
+        float4* pn = w.p2;
+        const unsigned nb = (unsigned)((L / kQTile) * (L / kQTile));
+        const int kmax = steps_per_pass < kQMaxSteps ? steps_per_pass : kQMaxSteps;
+        for (int q = 0; q < n_md;) {
+            const int k = n_md - q < kmax ? n_md - q : kmax;
+            const float4 k0 = q == 0 ? kick_half : kick_full;
+            switch (k) {
+            case 1: launch_qmulti<1>(nb, s, src, dst, p, pn, L, k0, kick_full, drift); break;
+            case 2: launch_qmulti<2>(nb, s, src, dst, p, pn, L, k0, kick_full, drift); break;
+            case 3: launch_qmulti<3>(nb, s, src, dst, p, pn, L, k0, kick_full, drift); break;
+            default: launch_qmulti<4>(nb, s, src, dst, p, pn, L, k0, kick_full, drift); break;
+            }
+            float4* t = src;
+            src = dst;
+            dst = t;
+            t = p;
+            p = pn;
+            pn = t;
+            q += k;
+        }
+    } else {
+        for (int q = 0; q < n_md; ++q) {
+            hipLaunchKernelGGL(k_qhmc_step, gstep, block, 0, s, src, dst, p, L, q == 0 ? kick_half : kick_full,
+                               drift);
+            float4* t = src;
+            src = dst;
+            dst = t;
+        }
     }
-    hipLaunchKernelGGL(k_qhmc_end, grec, block, 0, s, src, src == state ? nullptr : state, w.p, L, kick_half, g,
+    hipLaunchKernelGGL(k_qhmc_end, grec, block, 0, s, src, src == state ? nullptr : state, p, L, kick_half, g,
                        w.rec_new, nrec);
     hipError_t e = hipGetLastError();
     for (int r = 0; r < 4 && e == hipSuccess; ++r) {

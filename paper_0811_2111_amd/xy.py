@@ -120,6 +120,8 @@ def _load():
         "xy_hmc": [vp, i64, i32, dbl, vp, sz, vp],
         "xy_quad_hmc_work_bytes": [i32, P(sz)],
         "xy_quad_hmc": [vp, i64, i32, dbl, vp, sz, vp],
+        "xy_quad_hmc_set_steps_per_pass": [vp, i32],
+        "xy_quad_hmc_get_steps_per_pass": [vp, P(i32)],
         "xy_batch_set_spin_limit": [vp, ctypes.c_uint32],
         "xy_test_inject_failure": [i32],
         "xy_sweep_noalloc": [u64, i32, dbl, dbl, i32, u64, i64, i32, vp, sz, vp, vp],
@@ -550,6 +552,15 @@ class Quad:
             _check_out(out, nrec * 4 * 64, self.state.device, "xy_quad_sweep")
         check(_lib.xy_quad_sweep(self.h, int(n), int(measure_every), _ptr(out) if nrec else None), "xy_quad_sweep")
         return out
+
+    @property
+    def hmc_steps_per_pass(self) -> int:
+        v = ctypes.c_int32()
+        check(_lib.xy_quad_hmc_get_steps_per_pass(self.h, ctypes.byref(v)), "xy_quad_hmc_get_steps_per_pass")
+        return v.value
+
+    def set_hmc_steps_per_pass(self, steps: int):
+        check(_lib.xy_quad_hmc_set_steps_per_pass(self.h, int(steps)), "xy_quad_hmc_set_steps_per_pass")
 
     def hmc(self, n_traj: int, n_md: int, eps: float, out=None):
         """n_traj HMC trajectories of all four replicas (n_md leap-frog steps of size

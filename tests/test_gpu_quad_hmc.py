@@ -149,7 +149,7 @@ def test_quad_hmc_bench_size_equals_single_lattices():
     """The benchmark's configuration (L = 4096, beta 0.9 .. 1.3, eps = 0.02, 20
     steps) after Metropolis sweeps: two trajectories, every replica's angles bit
     for bit those of its single lattice (7-step passes on 64 x 64 tiles there,
-    one step per pass here)."""
+    4-step passes on 32 x 32 tiles here)."""
     from paper_0811_2111_amd import workloads
     hc = workloads.QUAD_HMC_4096
     L = hc["L"]
@@ -166,3 +166,33 @@ def test_quad_hmc_bench_size_equals_single_lattices():
         del lat
     del q
     torch.cuda.empty_cache()
+
+
+def test_quad_hmc_steps_per_pass_bit_identical():
+    """One step per pass over the state and passes of 2, 3 or 4 steps on grown
+    32 x 32 tiles (step counts that leave a short last pass, odd and even pass
+    counts) give the same trajectory bit for bit; settings outside 1 .. 4 are
+    refused."""
+    L = 96
+    ref = None
+    for steps in (1, 2, 3, 4):
+        q = xy.Quad(L, SEEDS, BETAS)
+        q.set_hmc_steps_per_pass(steps)
+        assert q.hmc_steps_per_pass == steps
+        q.sweep(1)
+        rec = xy.hmc_records(q.hmc(2, 9, 0.15))
+        q.hmc(1, 10, 0.15)
+        got = (q.state.clone(), rec)
+        if ref is None:
+            ref = got
+        else:
+            assert torch.equal(got[0], ref[0]), steps
+            assert np.array_equal(got[1]["accepted"], ref[1]["accepted"]), steps
+            np.testing.assert_allclose(got[1]["dH"], ref[1]["dH"], rtol=0, atol=1e-9 * L * L)
+        del q
+    q = xy.Quad(32, SEEDS, BETAS)
+    for bad in (0, 5):
+        with pytest.raises(xy.XYError) as ei:
+            q.set_hmc_steps_per_pass(bad)
+        assert ei.value.code == xy.XY_EINVAL
+    assert q.hmc_steps_per_pass == 4
