@@ -303,8 +303,9 @@ int xy_hmc_set_steps_per_pass(xy_lattice* h, int32_t steps);
 int xy_hmc_get_steps_per_pass(const xy_lattice* h, int32_t* steps);
 
 /* Hybrid Monte Carlo on the four-replica texel (sections 1.2 and 3.2): the four
- * replicas of a quad run their trajectories together, one pass over the float4
- * state per leap-frog step, and the Metropolis step is a vector of four
+ * replicas of a quad run their trajectories together (each pass over the
+ * float4 state advances all four by the same leap-frog steps; see
+ * xy_quad_hmc_set_steps_per_pass), and the Metropolis step is a vector of four
  * decisions z_r, each from the replica's own FP64 dH; replica r keeps
  * z_r theta_new + (1 - z_r) theta_old.  Replica r follows bit for bit the
  * trajectory that xy_hmc gives a single lattice with (seed_r, L, beta_r) and the
