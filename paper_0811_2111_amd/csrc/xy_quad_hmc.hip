@@ -1,7 +1,7 @@
 // xy_quad_hmc.hip -- hybrid Monte Carlo (section 1.2) on the four-replica texel
 // (section 3.2): the four replicas of a float4 state run their leap-frog
-// trajectories together, one pass over the state per step, and the Metropolis
-// step is a vector of four decisions z_r, one per replica from its own FP64 dH;
+// trajectories together, each pass over the state advancing all four, and the
+// Metropolis step is a vector of four decisions z_r, one per replica from its own FP64 dH;
 // replica r then keeps z_r theta_new + (1 - z_r) theta_old.
 //
 // Replica r follows bit for bit the trajectory of a single lattice with seed_r,
