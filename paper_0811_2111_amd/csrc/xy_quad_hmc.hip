@@ -18,6 +18,7 @@
 #include "xy_device.hpp"
 #include "xy_hmc_site.hpp"
 #include "xy_launch.hpp"
+#include "xy_reduce.hpp"
 #include "xy_tile4.hpp"
 
 using namespace xyd;
@@ -309,23 +310,27 @@ k_qhmc_end(const float4* __restrict__ st, float4* __restrict__ copy, const float
 }
 
 // The vector Metropolis step: workgroup r sums replica r's chunk records of
-// H_old and H_new in a fixed order and takes its decision (flag[r], obs[r]).
+// H_old and H_new in a fixed order (thread t: chunks t, t + 256, ..., then the
+// workgroup sum) and takes its decision (flag[r], obs[r]).
 __global__ void __launch_bounds__(kQThreads)
 k_qhmc_decide(const double* __restrict__ chunk_old, const double* __restrict__ chunk_new, int nchunk, QHmcBeta beta,
               uint32_t traj, QHmcKeys keys, unsigned* __restrict__ flag, xy_hmc_obs* __restrict__ obs)
 {
+    __shared__ double red[4 * 7];
     const int r = (int)blockIdx.x;
-    if (threadIdx.x != 0) return;
     double o[7] = {}, n[7] = {};
     const double* co = chunk_old + (size_t)r * nchunk * 8;
     const double* cn = chunk_new + (size_t)r * nchunk * 8;
-    for (int j = 0; j < nchunk; ++j)
+    for (int j = threadIdx.x; j < nchunk; j += kQThreads)
 #pragma unroll
         for (int q = 0; q < 7; ++q) {
             o[q] += co[(size_t)j * 8 + q];
             n[q] += cn[(size_t)j * 8 + q];
         }
-    decide_core(o, n, beta.b[r], traj, keys.k0[r], keys.k1[r], flag + r, obs ? obs + r : nullptr);
+    block_sum7_256(o, red);
+    __syncthreads();                      // red is reused
+    block_sum7_256(n, red);
+    if (threadIdx.x == 0) decide_core(o, n, beta.b[r], traj, keys.k0[r], keys.k1[r], flag + r, obs ? obs + r : nullptr);
 }
 
 // Rejected replicas: their components of the saved angles back into the state.
