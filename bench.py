@@ -89,6 +89,14 @@ def measured_traffic(L, plan, measured=False):
     """HBM bytes per launch of the plan's sweep kernel (measured or unmeasured
     sweep) from the committed counter profile, if it was taken on the current
     kernel sources for this lattice and tile; else None."""
+    e = counter_entry(L, plan, measured)
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def counter_entry(L, plan, measured=False):
+    """The committed counter record of the plan's sweep kernel (HBM bytes, and
+    for the headline kernel its VALU counters) if it was taken on the current
+    kernel sources for this lattice and tile; else None."""
     kind = plan[0]
     path = TRAFFIC_FILE if kind == 2 else TRAFFIC_FILES.get(kind)
     if path is None:
@@ -104,7 +112,7 @@ def measured_traffic(L, plan, measured=False):
     e = t.get("entries", {}).get(key)
     if e is None and not measured and kind == 2:
         e = t.get("entries", {}).get("%d/%d,%d,%d" % (L, plan[1], plan[2], plan[3]))
-    return None if e is None else e.get("bytes_per_launch")
+    return e
 
 
 def host_cpu():
@@ -275,6 +283,12 @@ def main():
     roofline["alu"] = {"achieved": round(slots, 2), "peak": round(VALU_PEAK_TSLOTS, 2), "unit": "T VALU-slot/s",
                        "frac": round(slots / VALU_PEAK_TSLOTS, 4),
                        "alg_slots_per_update": ALG_SLOTS_PER_UPDATE + ALG_SLOTS_MEAS_PER_UPDATE}
+    # the committed counter record of this kernel (same sources): vector
+    # instructions per update and rocprof's VALU-busy measure
+    # (100 SQ_ACTIVE_INST_VALU / 256 CUs / (GRBM_GUI_ACTIVE / 8 XCDs)); None if stale
+    ce = counter_entry(L, plan, measured=True)
+    roofline["alu"]["valu_insts_per_update"] = None if ce is None else ce.get("valu_insts_per_update")
+    roofline["alu"]["valu_busy_pct"] = None if ce is None else ce.get("valu_busy_pct")
     out = {
         "metric": "site-updates/sec (Gupd/s) at 1 MI355X; % HBM roofline; batched vs per-lattice speedup",
         "value": round(gupd, 3),
