@@ -350,8 +350,11 @@ k_batch_pass(const T* __restrict__ src, T* __restrict__ dst, const LatDesc* __re
 {
     extern __shared__ __align__(16) char smem[];
     double* red = (double*)(smem + pass_lds<TX, TY, WIDE>() - Tile1<TX, TY, 256>::red_bytes);
+    // the grid is the tile count rounded up to a multiple of 8; the last blocks of
+    // XCD 7's run have no tile
     const int b = (int)blockIdx.x;
-    const int t = (total_tiles & 7) ? b : (b & 7) * (total_tiles >> 3) + (b >> 3);
+    const int t = (b & 7) * (int)(gridDim.x >> 3) + (b >> 3);
+    if (t >= total_tiles) return;
     const LatDesc d = lat[tile_lat[t]];      // a table, not a search: two loads before the tile starts
     const int lt = t - d.first_tile;
     const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
@@ -871,7 +874,8 @@ static hipError_t enqueue_passes(xy_batch* b, hipStream_t s, int npass, int32_t 
         int pv = p;
         const int* tile_lat = (const int*)(b->work + b->lo.tile_off);
         void* args[] = {&src, &dst, &desc, &tile_lat, &tt, &ctrl, &pv, &part};
-        if ((e = hipLaunchKernel(k, dim3(tt), dim3(kNT), args, lds, s)) != hipSuccess) return e;
+        const unsigned grid = (unsigned)((tt + 7) & ~7);
+        if ((e = hipLaunchKernel(k, dim3(grid), dim3(kNT), args, lds, s)) != hipSuccess) return e;
         if (meas) {
             hipLaunchKernelGGL(k_batch_reduce, dim3(nlat), dim3(kNT), 0, s, desc, (const Ctrl*)ctrl, p,
                                (const double*)part, obs, nrec, (p + 1) / me - 1);
