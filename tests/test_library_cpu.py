@@ -192,3 +192,25 @@ def test_tuned_plan_cache_survives_malformed_files(tmp_path):
         assert rc in (xy.XY_OK, xy.XY_EINVAL), name
         if rc == xy.XY_OK:   # whatever was parsed must be a plan the library accepts
             assert plan.kind in (1, 2, 3, 4), name
+
+
+@pytest.mark.parametrize("L", [32, 96, 4096])
+def test_quad_hmc_work_bytes_and_null_handles(L):
+    """Workspace of the four-replica HMC: three float4 state-sized buffers (two
+    momenta, saved angles; each rounded to 256 bytes), the flags, and per replica
+    the partial records of H_old and H_new with their chunk sums; bad L and NULL
+    handles are refused without device work."""
+    L_ = xy.lib()
+    s = ctypes.c_size_t()
+    assert L_.xy_quad_hmc_work_bytes(L, ctypes.byref(s)) == xy.XY_OK
+    st = (16 * L * L + 255) // 256 * 256
+    cols = 2 * ((L // 2 + 255) // 256)
+    rb = min(L, max(1, 4096 // cols))
+    nrec = cols * rb * 4
+    assert s.value == 3 * st + 256 + 2 * 4 * (nrec + (nrec + 255) // 256) * 64
+    assert L_.xy_quad_hmc_work_bytes(L + 16, ctypes.byref(s)) == xy.XY_EINVAL   # L % 32 != 0
+    assert L_.xy_quad_hmc_work_bytes(L, None) == xy.XY_ESTATE
+    assert L_.xy_quad_hmc(None, 1, 1, 0.1, None, 0, None) == xy.XY_ESTATE
+    assert L_.xy_quad_hmc_set_steps_per_pass(None, 2) == xy.XY_ESTATE
+    v = ctypes.c_int32()
+    assert L_.xy_quad_hmc_get_steps_per_pass(None, ctypes.byref(v)) == xy.XY_ESTATE
