@@ -405,9 +405,10 @@ int xy_tuned_plan(const char* cache_path, int32_t L, int32_t precision, xy_plan*
  *   XY_BATCH_PERSISTENT: one persistent kernel per call; the lattices are split
  *     into eight groups of about equal area, one per XCD; the workgroups running
  *     on an XCD split its group's tiles into contiguous ranges, and each waits,
- *     before a pass over a lattice, for the previous pass of that lattice (a
- *     tiles-done counter per lattice in device memory, synchronised within the
- *     XCD only); 256 x 16 tiles for every lattice whose L is a multiple of 256;
+ *     before a pass over its range of a lattice, for the previous pass of the
+ *     tiles around that range (a passes-done counter per tile in device memory,
+ *     synchronised within the XCD only); 256 x 16 tiles for every lattice whose
+ *     L is a multiple of 256;
  *   XY_BATCH_PASSES: one launch per sweep over all tiles of all lattices, one
  *     workgroup per tile; the kernel boundary orders the sweeps;
  *   XY_BATCH_PASSES_WIDE (default): the same, with 256 x 16 tiles for every

@@ -9,15 +9,18 @@
 // about equal area, one per XCD, and every lattice is cut into TX x TY tiles.
 // The workgroups of the one launch find out which XCD they run on, and those on
 // XCD x split group x's tiles into contiguous ranges.  The grid never exceeds
-// what the GPU holds at once, so every workgroup is resident and the barriers
+// what the GPU holds at once, so every workgroup is resident and the waits
 // below cannot deadlock.  One pass = one fused sweep of a tile (state ->
-// ping-pong or back).  Before a workgroup starts pass p on a lattice it waits
-// until all of that lattice's tiles have finished pass p-1 (a counter of tiles
-// done per lattice), which orders both the new reads after the old writes and
-// the new writes after the old halo reads.  Lattices never wait for each other.
-// Every workgroup that touches a lattice runs on one XCD and so shares one L2:
-// the barrier needs no L2 write-back or invalidation, only the completion of the
-// workgroup's stores before it arrives and a drop of its L1 lines after it waits.
+// ping-pong or back).  Every tile has a counter of the passes it has finished;
+// before a workgroup starts pass p on its range of a lattice it waits until the
+// tiles around the range (those whose halos it reads and those that read its
+// halos) have finished pass p-1, which orders both the new reads after the old
+// writes and the new writes after the old halo reads.  Workgroups wait only
+// for their neighbours, lattices never for each other; a lattice's records wait
+// for all of its tiles.  Every workgroup that touches a lattice runs on one XCD
+// and so shares one L2: a wait needs no L2 write-back, only the completion of
+// the workgroup's stores before it publishes and a drop of its L1 lines after
+// it waits.
 //
 // The second schedule (XY_BATCH_PASSES) launches one kernel per pass over the
 // whole work list instead, one workgroup per tile, and lets the kernel boundary
@@ -137,14 +140,62 @@ __device__ __forceinline__ void xcd_wait(unsigned* ctr, unsigned target, Ctrl* c
     __syncthreads();
 }
 
-// Arrival: every wave waits for its stores, then thread 0 adds `add` to the counter.
-// (The wait is an asm statement with a memory clobber, so that the compiler keeps
-// every store of the tile program above it.)
-__device__ __forceinline__ void xcd_arrive(unsigned* ctr, unsigned add)
+// Wait until every tile in the neighbourhood of this workgroup's range [la, lb)
+// of a lattice (lattice-local tile indices, n tiles, tx per tile row) has
+// finished `target` passes: the tiles up to 2 tx before the range and after it,
+// modulo n, which hold every halo the range reads and every tile that reads the
+// range.  The workgroup's threads poll the counters side by side; a poll that
+// reaches the spin limit flags ctrl->timed_out, and every wait leaves at once
+// once that flag is set.  Then the acquire of xcd_wait.
+__device__ __forceinline__ void window_wait(const unsigned* __restrict__ td, int la, int lb, int n, int tx,
+                                            unsigned target, Ctrl* ctrl)
 {
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const int w = 2 * tx;
+    const unsigned limit = ctrl->spin_limit;
+    for (unsigned spins = 0;; ++spins) {
+        int ok = 1;
+        for (int k = threadIdx.x; k < 2 * w; k += 256) {
+            int lt = k < w ? la - w + k : lb + (k - w);
+            lt %= n;
+            if (lt < 0) lt += n;
+            if (lt >= la && lt < lb) continue;          // this workgroup's own tile
+            if (__hip_atomic_load(&td[lt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) ok = 0;
+        }
+        const int stop = __hip_atomic_load(&ctrl->timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        if (__syncthreads_and(ok | stop)) break;
+        if (threadIdx.x == 0 && spins + 1 >= limit)
+            __hip_atomic_store(&ctrl->timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_sleep(2);
+    }
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);
+    }
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until all n tile counters of a lattice have reached `target` (the
+// workgroup polls them side by side, as window_wait), then the acquire.  A sum
+// of counters would not do: with only neighbours coupled, one workgroup can be
+// a pass ahead while another is a pass behind.
+__device__ __forceinline__ void all_wait(const unsigned* __restrict__ td, int n, unsigned target, Ctrl* ctrl)
+{
+    const unsigned limit = ctrl->spin_limit;
+    for (unsigned spins = 0;; ++spins) {
+        int ok = 1;
+        for (int k = threadIdx.x; k < n; k += 256)
+            if (__hip_atomic_load(&td[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) ok = 0;
+        const int stop = __hip_atomic_load(&ctrl->timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+        if (__syncthreads_and(ok | stop)) break;
+        if (threadIdx.x == 0 && spins + 1 >= limit)
+            __hip_atomic_store(&ctrl->timed_out, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_sleep(2);
+    }
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
 }
 
 // Position in ord[beg .. end) of the lattice whose group-local tiles hold tile t.
@@ -201,8 +252,9 @@ constexpr size_t pass_lds()
 }
 
 // The persistent kernel.  Lattices flagged wide are cut into kWideX x kWideY tiles,
-// the others into TX x TY.  bar: one tiles-done counter per lattice, then kXcd + 1
-// registration counters (workgroups per XCD, all workgroups), all zero at launch.
+// the others into TX x TY.  bar: records written per lattice, then kXcd + 1
+// registration counters (workgroups per XCD, all workgroups); tdone: passes
+// finished per tile (work-list order); all zero at launch.
 // Start: each workgroup takes a rank among the workgroups of its XCD and waits
 // until the whole grid has registered, so that it knows how many share its
 // group's tiles.  A group whose XCD runs no workgroup of the grid would be left
@@ -211,8 +263,9 @@ constexpr size_t pass_lds()
 template <typename T, int TX, int TY, int NT>
 __global__ void __launch_bounds__(NT)
 k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ lat, const XcdPlan* __restrict__ plan,
-        int nlat, int total_tiles, unsigned* __restrict__ bar, Ctrl* __restrict__ ctrl, int npass, int measure_every,
-        double* __restrict__ part /* [2][total_tiles][8] */, xy_obs* __restrict__ obs, int nrec)
+        int nlat, int total_tiles, unsigned* __restrict__ bar, unsigned* __restrict__ tdone, Ctrl* __restrict__ ctrl,
+        int npass, int measure_every, double* __restrict__ part /* [2][total_tiles][8] */, xy_obs* __restrict__ obs,
+        int nrec)
 {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_pos[2];
@@ -220,6 +273,7 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
     // 7 doubles per wave, after the tile programs' LDS
     double* red = (double*)(smem + pass_lds<TX, TY, true>() - Tile1<TX, TY, NT>::red_bytes);
     const int* ord = (const int*)(plan + 1);
+    unsigned* rdone = bar;                    // records written per lattice
     unsigned* reg = bar + nlat;
     const int x = xcc_id();
     if (threadIdx.x == 0) {
@@ -249,13 +303,21 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
     auto slots = [&](int p) {
         return part + (size_t)((p / (measure_every > 0 ? measure_every : 1)) & 1) * (size_t)total_tiles * 8;
     };
-    // the workgroup holding a lattice's first tile writes its records
+    // the workgroup holding a lattice's first tile writes its records once every
+    // tile of the lattice has finished the measured pass (a lattice-wide wait,
+    // only at measured passes), and counts them in rdone
     auto reduce_if_owner = [&](const LatDesc& d, int i, int p) {
-        if (measured(p - 1) && t0 <= d.xfirst && d.xfirst < t1)
+        if (measured(p - 1) && t0 <= d.xfirst && d.xfirst < t1) {
+            all_wait(tdone + d.first_tile, d.ntiles, (unsigned)p, ctrl);
             reduce_lattice<NT>(d, slots(p - 1), obs + (size_t)i * nrec + (p / measure_every - 1),
                                (uint64_t)sweep0 + (uint64_t)p, red);
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(&rdone[i], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     };
 
+    // A workgroup starts pass p on its tiles of a lattice as soon as the tiles
+    // around them have finished pass p-1 (tdone), not the whole lattice, so
+    // workgroups wait only for their neighbours.
     for (int p = 0; p < npass; ++p) {
         T* src = (p & 1) ? pp : state;
         T* dst = (p & 1) ? state : pp;
@@ -264,11 +326,19 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
         for (int q = qlo; q <= qhi; ++q) {
             const int i = ord[q];
             const LatDesc d = lat[i];
+            const int a = max(t0, d.xfirst), b = min(t1, d.xfirst + d.ntiles);
+            unsigned* td = tdone + d.first_tile;
             if (p > 0) {
-                xcd_wait(&bar[i], (unsigned)p * (unsigned)d.ntiles, ctrl);
+                window_wait(td, a - d.xfirst, b - d.xfirst, d.ntiles, d.tiles_x, (unsigned)p, ctrl);
                 reduce_if_owner(d, i, p);   // pass p-1 is complete
             }
-            const int a = max(t0, d.xfirst), b = min(t1, d.xfirst + d.ntiles);
+            // this measured pass reuses the partials half of the records two
+            // before it: those must have been read (a read before a write: no
+            // cache maintenance needed)
+            if (meas && p / measure_every >= 2) {
+                if (threadIdx.x == 0) poll_at_least(&rdone[i], (unsigned)(p / measure_every - 1), ctrl);
+                __syncthreads();
+            }
             const Params prm{d.delta, d.nbl2e};
             const unsigned bytes = (unsigned)((size_t)d.L * d.L * sizeof(T));
             for (int t = a; t < b; ++t) {
@@ -284,7 +354,12 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
                                                  sweep0 + (uint32_t)p, d.key0, d.key1, prm, meas, rec, smem, red);
                 __syncthreads();   // the next tile reuses the LDS
             }
-            xcd_arrive(&bar[i], (unsigned)(b - a));   // done with lattice i in pass p
+            // done with lattice i in pass p: its stores complete, then the tiles' counters
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            for (int k = threadIdx.x; k < b - a; k += NT)
+                __hip_atomic_store(&td[a - d.xfirst + k], (unsigned)(p + 1), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 
@@ -294,10 +369,11 @@ k_batch(T* __restrict__ state, T* __restrict__ pp, const LatDesc* __restrict__ l
         for (int q = qlo; q <= qhi; ++q) {
             const int i = ord[q];
             const LatDesc d = lat[i];
-            xcd_wait(&bar[i], (unsigned)npass * (unsigned)d.ntiles, ctrl);
+            const int a = max(t0, d.xfirst), b = min(t1, d.xfirst + d.ntiles);
+            // the neighbours have finished the last pass (and its reads of `state`)
+            window_wait(tdone + d.first_tile, a - d.xfirst, b - d.xfirst, d.ntiles, d.tiles_x, (unsigned)npass, ctrl);
             reduce_if_owner(d, i, npass);
             if (npass & 1) {
-                const int a = max(t0, d.xfirst), b = min(t1, d.xfirst + d.ntiles);
                 const int Hh = d.L >> 1;
                 const int hx = (d.wide ? kWideX : TX) / 2, ry = d.wide ? kWideY : TY;   // tile: ry rows of hx entries
                 for (int t = a; t < b; ++t) {
@@ -510,7 +586,8 @@ static std::vector<Shape> candidates(int n, const int32_t* L)
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, xplan_off, res_off, tile_off, part_off, pt_off, total;
+    size_t state_bytes, pp_off, ctrl_off, bar_off, desc_off, xplan_off, res_off, tile_off, part_off, td_off, pt_off,
+        total;
     long long max_tiles;
 };
 
@@ -544,7 +621,8 @@ static Layout layout(int n, const int32_t* L, int precision)
     lo.res_off = align256(lo.xplan_off + sizeof(XcdPlan) + (size_t)n * sizeof(int));
     lo.tile_off = align256(lo.res_off + (size_t)n * sizeof(int));
     lo.part_off = align256(lo.tile_off + (size_t)lo.max_tiles * sizeof(int));
-    lo.pt_off = align256(lo.part_off + (size_t)2 * lo.max_tiles * 8 * sizeof(double));
+    lo.td_off = align256(lo.part_off + (size_t)2 * lo.max_tiles * 8 * sizeof(double));
+    lo.pt_off = align256(lo.td_off + (size_t)lo.max_tiles * sizeof(unsigned));
     lo.total = lo.pt_off + pt_bytes(n);
     return lo;
 }
@@ -824,13 +902,16 @@ static hipError_t enqueue_batch(xy_batch* b, hipStream_t s, int npass, int32_t m
     const LatDesc* desc = (const LatDesc*)(b->work + b->lo.desc_off);
     double* part = (double*)(b->work + b->lo.part_off);
     const XcdPlan* plan = (const XcdPlan*)(b->work + b->lo.xplan_off);
+    unsigned* tdone = (unsigned*)(b->work + b->lo.td_off);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, s, bar, b->n + kXcd + 1);
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min(1024, (b->total_tiles + 255) / 256 + 1)), dim3(256), 0, s,
+                       tdone, b->total_tiles);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* pp = b->work + b->lo.pp_off;
     void* st = b->state;
     int nlat = b->n, tt = b->total_tiles;
-    void* args[] = {&st, &pp, &desc, &plan, &nlat, &tt, &bar, &ctrl, &npass, &me, &part, &obs, (void*)&nrec};
+    void* args[] = {&st, &pp, &desc, &plan, &nlat, &tt, &bar, &tdone, &ctrl, &npass, &me, &part, &obs, (void*)&nrec};
     e = hipLaunchKernel(k, dim3(b->grid), dim3(kNT), args, lds, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(1), 0, s, ctrl, (uint32_t)npass);
@@ -1051,8 +1132,8 @@ int xy_batch_sweep(xy_batch* b, int64_t n_sweeps, int32_t measure_every, xy_obs*
     xy_obs* obs = me ? obs_dev : nullptr;
     const int64_t nrec = me ? n_sweeps / me : 0;   // records per lattice: the stride of obs_dev
     if (nrec > INT32_MAX) return XY_EINVAL;
-    // Split long calls: barrier targets are pass * tiles in 32 bits and pass
-    // counts are ints (at most 2^30 sweeps per launch sequence), and the per-sweep
+    // Split long calls: pass counts are ints and counters 32 bits (at most 2^30
+    // sweeps per launch sequence, fewer for huge tile counts), and the per-sweep
     // schedules capture one launch per sweep (at most kMaxGraphPasses per graph).
     // Chunks are multiples of measure_every, so the records of chunk c start at
     // record done / measure_every of every lattice, with the call's stride.
