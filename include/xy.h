@@ -379,7 +379,8 @@ int xy_kernel_timer_read(xy_lattice* h, double* total_ms, int64_t* launches);
 int xy_debug_sweep(xy_lattice* h, uint8_t* accept_dev, float* dE_dev);
 
 /* Time each candidate plan for `sweeps_per_trial` sweeps (after one untimed
- * trial) on the handle's stream and select the fastest; *best receives it and
+ * trial) on the handle's stream, in two rounds over the candidates, and select
+ * the one with the fastest trial; *best receives it and
  * the handle keeps it.  The plans differ in how sublattices are staged through
  * on-chip memory with duplicated borders (section 2.2), never in the trajectory.
  * The trials advance the handle's state and counter: run it on a scratch

@@ -620,7 +620,11 @@ int xy_autotune(xy_lattice* h, int32_t sweeps_per_trial, const char* cache_path,
     double best_t = 1e300;
     xy_plan best_p = saved;
     int rc = XY_OK;
-    for (const xy_plan& p : cands) {
+    // two rounds over the candidates, each candidate's best trial counting, so
+    // that one slow trial (a clock change, another process) does not decide
+    std::vector<xy_plan> trials(cands);
+    trials.insert(trials.end(), cands.begin(), cands.end());
+    for (const xy_plan& p : trials) {
         h->plan = p;
         if (h->sweep + 2ull * (uint64_t)sweeps_per_trial + 2 >= 0xffffffffull) h->sweep = 0;
         rc = xy_sweep(h, sweeps_per_trial, 0, nullptr);  // warm-up (sets LDS attributes, caches)
