@@ -161,7 +161,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 256 MiB device-to-device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", choices=["l4096", "l4096_tuned", "l16384", "batch", "hmc", "hmc_batch", "quad",
-                                           "quad_hmc", "fp16",
+                                           "quad_hmc", "fp16", "l8192",
                                            "tempering", "small"],
                     default="l16384",
                     help="with --kernel-only: which configuration's sweeps to run (for profiler runs)")
@@ -431,14 +431,16 @@ def profile_leg(args, stream):
         ms = timed(lambda: qd.sweep(args.steps, qc["measure_every"], out=qobs), stream)
         print(json.dumps({"workload": "quad L4096", "sweeps": args.steps, "ms": ms,
                           "gupd_s": 4.0 * float(qc["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}))
-    elif args.workload == "fp16":
+    elif args.workload in ("fp16", "l8192"):
+        # the L = 8192 storage comparison, FP16 or FP32 angles
         pc = workloads.PRECISION
+        prec = "fp16" if args.workload == "fp16" else "fp32"
         plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
-        lat = xy.Lattice(pc["L"], seed=pc["seed"], beta=1.0, delta=pc["delta"], precision="fp16", plan=plan)
+        lat = xy.Lattice(pc["L"], seed=pc["seed"], beta=1.0, delta=pc["delta"], precision=prec, plan=plan)
         lat.sweep(args.warmup)
         ms = timed(lambda: lat.sweep(args.steps, 10), stream)
-        print(json.dumps({"workload": "FP16 L8192", "sweeps": args.steps, "ms": ms, "plan": list(lat.plan),
-                          "gupd_s": float(pc["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}))
+        print(json.dumps({"workload": "%s L8192" % prec.upper(), "sweeps": args.steps, "ms": ms,
+                          "plan": list(lat.plan), "gupd_s": float(pc["L"]) ** 2 * args.steps / (ms * 1e-3) / 1e9}))
     elif args.workload == "small":
         # the parity configuration (L = 32, a record every sweep) on the LDS-resident
         # plan and on the streaming plan, then a batch of 2048 such lattices

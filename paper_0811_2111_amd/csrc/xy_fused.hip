@@ -28,10 +28,18 @@ constexpr size_t fused_lds()
     else return TileShape<TX, TY, M, NT>::lds_bytes;
 }
 
+// Lattices whose two buffers (state and ping-pong) together exceed the 256 MiB
+// MALL are read back from HBM every sweep; their single-sweep tiles store with
+// the non-temporal hint, so the stored rows do not crowd the halo rows the tiles
+// beside still have to read out of the L2 (L = 8192 in FP32: 5% less time per
+// sweep).  Within the MALL the hint costs more than it saves (L = 4096: 12% more).
+constexpr size_t kStreamBytes = (size_t)256 << 20;
+
 // MEAS (single-sweep tiles only): 1 = this sweep is measured, one partial record
 // per wave (tile-major); 0 = not measured.  The two-sweep tile takes the mask of
-// measured sub-sweeps at run time, one record per tile and sub-sweep.
-template <typename T, int TX, int TY, int M, int NT, int MEAS>
+// measured sub-sweeps at run time, one record per tile and sub-sweep.  ST
+// (single-sweep tiles only): non-temporal stores.
+template <typename T, int TX, int TY, int M, int NT, int MEAS, bool ST>
 __global__ void __launch_bounds__(NT)
 k_fused(const T* __restrict__ src, T* __restrict__ dst, int L, uint32_t sweep0, uint32_t k0, uint32_t k1, Params p,
         unsigned meas_mask, double* __restrict__ partials)
@@ -43,7 +51,7 @@ k_fused(const T* __restrict__ src, T* __restrict__ dst, int L, uint32_t sweep0, 
     const int ty = b / tiles_x, tx = b - ty * tiles_x;
     double* red = (double*)(smem + fused_lds<TX, TY, M, NT>());
     if constexpr (M == 1)
-        tile1_program<T, TX, TY, NT, MEAS>(src, dst, (unsigned)((size_t)L * L * sizeof(T)), L, tx * TX, ty * TY,
+        tile1_program<T, TX, TY, NT, MEAS, ST>(src, dst, (unsigned)((size_t)L * L * sizeof(T)), L, tx * TX, ty * TY,
                                            sweep0, k0, k1, p, MEAS != 0, partials + (size_t)b * (NT / 64) * 8, smem,
                                            red);
     else
@@ -51,12 +59,12 @@ k_fused(const T* __restrict__ src, T* __restrict__ dst, int L, uint32_t sweep0, 
                                        partials + (size_t)b * 8, (size_t)ntiles * 8, smem, red);
 }
 
-template <typename T, int TX, int TY, int M, int NT, int MEAS>
+template <typename T, int TX, int TY, int M, int NT, int MEAS, bool ST>
 static hipError_t run_fused_k(const SweepArgs& a, unsigned meas_mask, double* partials, hipStream_t s)
 {
     constexpr size_t lds = fused_lds<TX, TY, M, NT>() + (size_t)(NT / 64) * 7 * sizeof(double);
     static bool attr_set = false;
-    auto kern = k_fused<T, TX, TY, M, NT, MEAS>;
+    auto kern = k_fused<T, TX, TY, M, NT, MEAS, ST>;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
@@ -73,10 +81,14 @@ template <typename T, int TX, int TY, int M, int NT>
 static hipError_t run_fused(const SweepArgs& a, unsigned meas_mask, double* partials, hipStream_t s)
 {
     if constexpr (M == 1) {
-        if (meas_mask & 1u) return run_fused_k<T, TX, TY, M, NT, 1>(a, meas_mask, partials, s);
-        return run_fused_k<T, TX, TY, M, NT, 0>(a, meas_mask, partials, s);
+        const bool st = 2 * (size_t)a.L * (size_t)a.L * sizeof(T) > kStreamBytes;
+        if (meas_mask & 1u)
+            return st ? run_fused_k<T, TX, TY, M, NT, 1, true>(a, meas_mask, partials, s)
+                      : run_fused_k<T, TX, TY, M, NT, 1, false>(a, meas_mask, partials, s);
+        return st ? run_fused_k<T, TX, TY, M, NT, 0, true>(a, meas_mask, partials, s)
+                  : run_fused_k<T, TX, TY, M, NT, 0, false>(a, meas_mask, partials, s);
     } else {
-        return run_fused_k<T, TX, TY, M, NT, -1>(a, meas_mask, partials, s);
+        return run_fused_k<T, TX, TY, M, NT, -1, false>(a, meas_mask, partials, s);
     }
 }
 

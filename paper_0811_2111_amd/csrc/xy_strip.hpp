@@ -24,6 +24,13 @@
 // same way.  Per sweep the strip recomputes SH+2 red rows and SH+2 ring entries
 // for SH rows, against TY+2 rows per TY in a square tile.
 //
+// The edge columns are read before the walk, while the strips beside read the same
+// cache lines as their walks reach those rows; the lines are L2 hits for them only
+// if the L2 still holds them then.  So the walk's row loads and all its stores
+// carry the non-temporal hint: the rows streamed through once per sweep leave the
+// L2 early and more of the edge lines stay (at L = 16384: 2-3% less time per
+// sweep, reads 1.26 -> 1.22 x one load per angle with the same XCD mapping).
+//
 // As in every other kernel, a site is updated by xyd::site_update with neighbour
 // sums (left + right) + (up + down), and the random numbers of a site depend only
 // on (seed, sweep, colour, row, pair), so the trajectory is that of any other
@@ -131,8 +138,8 @@ struct StripWalk {
     {
         const int rel = j * S::R + g.rt;
         const int yr = wrapi(g.y0 - 1 + rel, g.L), yb = wrapi(g.y0 + rel, g.L);
-        r = bio<T>::ld2(rs, (unsigned)yr * Hh + col);
-        b = bio<T>::ld2(rs, (Lu + (unsigned)yb) * Hh + col);
+        r = bio<T>::template ld2<true>(rs, (unsigned)yr * Hh + col);
+        b = bio<T>::template ld2<true>(rs, (Lu + (unsigned)yb) * Hh + col);
     }
 
     // KIND: 0 = step 0 (no black update; red row y0-1 not stored); 1 = a step
@@ -185,7 +192,7 @@ struct StripWalk {
             if (O ? g.s == 0 : g.s == S::TQ - 1) row[O ? 1 : TX / 2 + 2] = re[rel];
             if (KIND == 1 || KIND == 2 || (rel >= 1 && rel <= SH)) {
                 acc += aa + ab;
-                bio<T>::st2(rd, (unsigned)(g.y0 - 1 + rel) * Hh + col, ta, tb);
+                bio<T>::template st2<true>(rd, (unsigned)(g.y0 - 1 + rel) * Hh + col, ta, tb);
             }
             if constexpr (MEAS) pin_sums(acc);
         }
@@ -204,7 +211,7 @@ struct StripWalk {
             const int ab = site_update<T>(tb, cb, sb, nsum(n.lb.x, n.rb.x, n.ub.x, n.db.x),
                                           nsum(n.lb.y, n.rb.y, n.ub.y, n.db.y), wb.z, wb.w, p);
             acc += aa + ab;
-            bio<T>::st2(rd, (Lu + (unsigned)ybu) * Hh + col, ta, tb);
+            bio<T>::template st2<true>(rd, (Lu + (unsigned)ybu) * Hh + col, ta, tb);
             if constexpr (MEAS) {
                 meas_acc(m, ca, sa, n.la, n.ra, n.ua, n.da);
                 meas_acc(m, cb, sb, n.lb, n.rb, n.ub, n.db);

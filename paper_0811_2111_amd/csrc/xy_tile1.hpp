@@ -29,30 +29,39 @@ namespace xyd {
 
 typedef unsigned int xu2 __attribute__((ext_vector_type(2)));
 
+// Loads and stores of the state.  ST = true sets the non-temporal hint (cache
+// policy bit NT): the L2 keeps such lines only briefly, so a kernel that streams
+// a lattice larger than the caches through once per sweep does not push out the
+// lines it means to reuse (a strip's edge columns, a tile's halo rows).
+constexpr int kCpolNT = 2;
+
 template <typename T> struct bio;
 template <> struct bio<float> {
+    template <bool ST = false>
     static __device__ __forceinline__ float2 ld2(__amdgpu_buffer_rsrc_t r, unsigned off_elems)
     {
-        const xu2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off_elems * 4u, 0, 0);
+        const xu2 v = __builtin_amdgcn_raw_buffer_load_b64(r, off_elems * 4u, 0, ST ? kCpolNT : 0);
         return make_float2(__uint_as_float(v.x), __uint_as_float(v.y));
     }
     static __device__ __forceinline__ float ld1(__amdgpu_buffer_rsrc_t r, unsigned off_elems)
     {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off_elems * 4u, 0, 0));
     }
+    template <bool ST = false>
     static __device__ __forceinline__ void st2(__amdgpu_buffer_rsrc_t r, unsigned off_elems, float a, float b)
     {
         xu2 v;
         v.x = __float_as_uint(a);
         v.y = __float_as_uint(b);
-        __builtin_amdgcn_raw_buffer_store_b64(v, r, off_elems * 4u, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, off_elems * 4u, 0, ST ? kCpolNT : 0);
     }
     static constexpr unsigned bytes = 4;
 };
 template <> struct bio<__half> {
+    template <bool ST = false>
     static __device__ __forceinline__ float2 ld2(__amdgpu_buffer_rsrc_t r, unsigned off_elems)
     {
-        const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, off_elems * 2u, 0, 0);
+        const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, off_elems * 2u, 0, ST ? kCpolNT : 0);
         return make_float2(__half2float(__ushort_as_half((unsigned short)(v & 0xffffu))),
                            __half2float(__ushort_as_half((unsigned short)(v >> 16))));
     }
@@ -61,11 +70,12 @@ template <> struct bio<__half> {
         const unsigned short v = __builtin_amdgcn_raw_buffer_load_b16(r, off_elems * 2u, 0, 0);
         return __half2float(__ushort_as_half(v));
     }
+    template <bool ST = false>
     static __device__ __forceinline__ void st2(__amdgpu_buffer_rsrc_t r, unsigned off_elems, float a, float b)
     {
         const unsigned v = (unsigned)__half_as_ushort(__float2half_rn(a)) |
                            ((unsigned)__half_as_ushort(__float2half_rn(b)) << 16);
-        __builtin_amdgcn_raw_buffer_store_b32(v, r, off_elems * 2u, 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, off_elems * 2u, 0, ST ? kCpolNT : 0);
     }
     static constexpr unsigned bytes = 2;
 };
@@ -214,7 +224,7 @@ template <typename S> __device__ __forceinline__ int black_row(const T1Geom& g, 
 
 // Red half-sweep (rows y0-1 .. y0+TY, columns kb-1 .. kb+TX/2); O = parity of this
 // thread's red rows.
-template <typename T, int TX, int TY, int NT, int O>
+template <typename T, int TX, int TY, int NT, int O, bool ST>
 __device__ __forceinline__ void tile1_red(const T1Geom& g, float2* __restrict__ cs, float2 (&thr)[Tile1<TX, TY, NT>::NQR],
                                           __amdgpu_buffer_rsrc_t dst, uint32_t sweep, uint32_t k0, uint32_t k1,
                                           const Params& p, float the, int e, int e_row, int e_col, int e_red, int e_k,
@@ -251,7 +261,8 @@ __device__ __forceinline__ void tile1_red(const T1Geom& g, float2* __restrict__ 
             *(float4*)&cs[row * S::WS + c0] = own;
             if (q < FULL || (row >= 1 && row <= TY)) {
                 acc += aa + ab;
-                bio<T>::st2(dst, (unsigned)(g.y0 - 1 + row) * (unsigned)g.Hh + (unsigned)(g.kb + 2 * g.s), ta, tb);
+                bio<T>::template st2<ST>(dst, (unsigned)(g.y0 - 1 + row) * (unsigned)g.Hh +
+                                                  (unsigned)(g.kb + 2 * g.s), ta, tb);
             }
         }
     }
@@ -274,7 +285,7 @@ __device__ __forceinline__ void tile1_red(const T1Geom& g, float2* __restrict__ 
 
 // Black half-sweep of the interior rows y0 .. y0+TY-1 (black LDS rows 2 .. TY+1);
 // O = parity of this thread's black rows.
-template <typename T, int TX, int TY, int NT, int O, bool MEAS>
+template <typename T, int TX, int TY, int NT, int O, bool MEAS, bool ST>
 __device__ __forceinline__ void tile1_black(const T1Geom& g, const float2* __restrict__ cs,
                                             float2 (&thb)[Tile1<TX, TY, NT>::NQB], __amdgpu_buffer_rsrc_t dst,
                                             uint32_t sweep, uint32_t k0, uint32_t k1, const Params& p, int& acc,
@@ -307,7 +318,8 @@ __device__ __forceinline__ void tile1_black(const T1Geom& g, const float2* __res
             const int ab = site_update<T>(tb, cb, sb, nsum(n.lb.x, n.rb.x, n.ub.x, n.db.x),
                                           nsum(n.lb.y, n.rb.y, n.ub.y, n.db.y), r.z, r.w, p);
             acc += aa + ab;
-            bio<T>::st2(dst, ((unsigned)g.L + (unsigned)y) * (unsigned)g.Hh + (unsigned)(g.kb + 2 * g.s), ta, tb);
+            bio<T>::template st2<ST>(dst, ((unsigned)g.L + (unsigned)y) * (unsigned)g.Hh + (unsigned)(g.kb + 2 * g.s),
+                                     ta, tb);
             if constexpr (MEAS) {
                 meas_acc(m, ca, sa, n.la, n.ra, n.ua, n.da);
                 meas_acc(m, cb, sb, n.lb, n.rb, n.ub, n.db);
@@ -428,8 +440,8 @@ __device__ __forceinline__ void tile1_fill(const T1Geom& g, float2* __restrict__
 }
 
 // Both half-sweeps of a filled tile (after the fill's barrier); the updated angles
-// go to rd.  MEAS as for tile1_program.  Ends with the black updates (no barrier).
-template <typename T, int TX, int TY, int NT, int MEAS>
+// go to rd.  MEAS and ST as for tile1_program.  Ends with the black updates (no barrier).
+template <typename T, int TX, int TY, int NT, int MEAS, bool ST = false>
 __device__ __forceinline__ void tile1_sweep(const T1Geom& g, float2* __restrict__ cs, T1Regs<TX, TY, NT>& a,
                                             __amdgpu_buffer_rsrc_t rd, uint32_t sweep, uint32_t k0, uint32_t k1,
                                             const Params& p, bool meas, double* part, double* red)
@@ -442,17 +454,17 @@ __device__ __forceinline__ void tile1_sweep(const T1Geom& g, float2* __restrict_
     // wave instead of running both parity variants under exec masks
     const bool red_odd = __builtin_amdgcn_readfirstlane((g.y0 + g.rt) & 1) != 0;
     if (red_odd)
-        tile1_red<T, TX, TY, NT, 1>(g, cs, a.thr, rd, sweep, k0, k1, p, a.the, e, a.e_row, a.e_col, a.e_red, a.e_k,
+        tile1_red<T, TX, TY, NT, 1, ST>(g, cs, a.thr, rd, sweep, k0, k1, p, a.the, e, a.e_row, a.e_col, a.e_red, a.e_k,
                                     acc);
     else
-        tile1_red<T, TX, TY, NT, 0>(g, cs, a.thr, rd, sweep, k0, k1, p, a.the, e, a.e_row, a.e_col, a.e_red, a.e_k,
+        tile1_red<T, TX, TY, NT, 0, ST>(g, cs, a.thr, rd, sweep, k0, k1, p, a.the, e, a.e_row, a.e_col, a.e_red, a.e_k,
                                     acc);
     __syncthreads();
     if (MEAS == 1 || (MEAS == -1 && meas)) {
         if (red_odd)
-            tile1_black<T, TX, TY, NT, 0, true>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
+            tile1_black<T, TX, TY, NT, 0, true, ST>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
         else
-            tile1_black<T, TX, TY, NT, 1, true>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
+            tile1_black<T, TX, TY, NT, 1, true, ST>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
         double v[7] = {(double)m.cx, (double)m.cy, (double)m.ix, (double)m.iy, (double)m.mx, (double)m.my,
                        (double)acc};
         if constexpr (MEAS == 1) {
@@ -474,9 +486,9 @@ __device__ __forceinline__ void tile1_sweep(const T1Geom& g, float2* __restrict_
         }
     } else {
         if (red_odd)
-            tile1_black<T, TX, TY, NT, 0, false>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
+            tile1_black<T, TX, TY, NT, 0, false, ST>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
         else
-            tile1_black<T, TX, TY, NT, 1, false>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
+            tile1_black<T, TX, TY, NT, 1, false, ST>(g, cs, a.thb, rd, sweep, k0, k1, p, acc, m);
     }
 }
 
@@ -488,7 +500,9 @@ __device__ __forceinline__ void tile1_sweep(const T1Geom& g, float2* __restrict_
 //              a fixed order);
 //   MEAS = -1: measure if `meas`, one partial record per tile at part[0 .. 8].
 // A record is (Cx, Cy, Ix, Iy, Mx, My, accepts, 0).
-template <typename T, int TX, int TY, int NT, int MEAS = -1>
+// ST: the updated angles are stored with the non-temporal hint (for lattices
+// larger than the caches: the stored lines are read again only a sweep later).
+template <typename T, int TX, int TY, int NT, int MEAS = -1, bool ST = false>
 __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __restrict__ dst, unsigned state_bytes,
                                               int L, int x0, int y0, uint32_t sweep, uint32_t k0, uint32_t k1,
                                               const Params& p, bool meas, double* part, char* smem, double* red)
@@ -504,7 +518,8 @@ __device__ __forceinline__ void tile1_program(const T* __restrict__ src, T* __re
     tile1_fill<TX, TY, NT>(g, cs, a);
     __syncthreads();
     __builtin_amdgcn_s_setprio(0);
-    tile1_sweep<T, TX, TY, NT, MEAS>(g, cs, a, make_rsrc(dst, state_bytes), sweep, k0, k1, p, meas, part, red);
+    tile1_sweep<T, TX, TY, NT, MEAS, ST>(g, cs, a, make_rsrc(dst, state_bytes), sweep, k0, k1, p, meas, part,
+                                         red);
 }
 
 }  // namespace xyd

@@ -267,8 +267,7 @@ FULL_SIZE_CASES = [(4096, 1.12, 1.0, (2, 256, 16, 1))] + \
 @pytest.mark.parametrize("L,beta,delta,plan", FULL_SIZE_CASES)
 def test_full_size_sampled_sites(orc, L, beta, delta, plan):
     """At the benchmark sizes, with every plan the autotuner picks among at
-    L = 16384 (streaming, every fused tile, every strip segment, the XCD band
-    remap of the 512-wide strips included):
+    L = 16384 (streaming, every fused tile, every strip segment):
     two sweeps on the device, then 1500 sampled sites (edges included) against the
     oracle's site-by-site evaluation of their light cones; the two FP64 records
     against a float64 recomputation from the device state."""
