@@ -100,11 +100,13 @@ typedef struct xy_obs {
  *                   the tile to the other buffer of a ping-pong pair.  Needs
  *                   L % 4 == 0, tile_x % 4 == 0, tile_x | L, tile_y | L.
  *   XY_PLAN_STRIP : one launch per sweep; a workgroup walks down a segment of
- *                   tile_x columns (128 or 256) and tile_y rows, a few rows of each
- *                   colour at a time, with (cos, sin) of the rows in flight in LDS
- *                   rings and the next rows' loads issued ahead; the halo is one
- *                   red row above and below the segment plus one red entry per row
- *                   beside it, recomputed.  Needs tile_x | L, tile_y | L, (tile_x,
+ *                   tile_x columns (128, 256 or 512) and tile_y rows, a few rows
+ *                   of each colour at a time, with (cos, sin) of the rows in
+ *                   flight in LDS rings and the next rows' loads issued ahead;
+ *                   the halo is one red row above and below the segment plus one
+ *                   red entry per row beside it, recomputed.  Made for lattices
+ *                   far beyond the caches: its row loads and stores carry the
+ *                   non-temporal hint.  Needs tile_x | L, tile_y | L, (tile_x,
  *                   tile_y) one of (128, 32|64|128), (256, 32|64|128|256),
  *                   (512, 64|128|256), sweeps_per_pass = 1.
  *   XY_PLAN_RESIDENT: every sweep of a call in one launch of one workgroup that
