@@ -114,7 +114,11 @@ typedef struct xy_obs {
  *                   (cos, sin) of one colour, 8 L^2 bytes): no halo and no HBM
  *                   traffic between sweeps.  Needs L <= 128, L % 4 == 0; tile_x,
  *                   tile_y ignored, sweeps_per_pass = 1.
- *   XY_PLAN_AUTO  : the tuned plan for (L, precision) if one is cached, else a default. */
+ *   XY_PLAN_AUTO  : the tuned plan for (L, precision) if one is cached, else a
+ *                   default: strip 512 x 64 for an FP32 lattice whose state and
+ *                   ping-pong copy exceed 256 MiB, else the first fused tile of
+ *                   256 x 16, 128 x 32, 64 x 32, 64 x 16 that L allows, else
+ *                   XY_PLAN_STREAM. */
 enum { XY_PLAN_AUTO = 0, XY_PLAN_STREAM = 1, XY_PLAN_FUSED = 2, XY_PLAN_STRIP = 3, XY_PLAN_RESIDENT = 4 };
 typedef struct xy_plan {
     int32_t kind;

@@ -66,8 +66,15 @@ xyk::SweepArgs sweep_args(uint64_t seed, int L, int precision, double beta, doub
     return a;
 }
 
-xy_plan default_plan(int32_t L)
+xy_plan default_plan(int32_t L, int32_t precision)
 {
+    // An FP32 lattice whose state and ping-pong copy exceed the 256 MiB MALL is
+    // read from HBM every sweep; there the strip segments are the fastest plan
+    // (over the 256 x 16 tiles: 2% at L = 8192, 17% at L = 16384 with a record
+    // every sweep).  FP16 lattices keep the tiles.
+    if (precision == XY_FP32 && 2ull * (uint64_t)L * (uint64_t)L * 4ull > (256ull << 20) &&
+        xyk::strip_supported(L, 512, 64))
+        return xy_plan{XY_PLAN_STRIP, 512, 64, 1};
     xy_plan p{XY_PLAN_STREAM, 0, 0, 1};
     static const int cand[][3] = {{256, 16, 1}, {128, 32, 1}, {64, 32, 1}, {64, 16, 1}};
     for (auto& c : cand)
@@ -239,7 +246,7 @@ static int make_handle(xy_lattice** out, uint64_t seed, int32_t L, double beta, 
     h->tcap = h->tn = 0;
     h->w = xyk::carve(work_dev, L, precision);
     xy_plan p;
-    if (!cache_lookup(env_cache_path(), L, precision, &p)) p = default_plan(L);
+    if (!cache_lookup(env_cache_path(), L, precision, &p)) p = default_plan(L, precision);
     h->plan = p;
     *out = h;
     return XY_OK;
@@ -508,7 +515,7 @@ int xy_set_plan(xy_lattice* h, const xy_plan* plan)
     if (!live(h) || !plan) return XY_ESTATE;
     xy_plan p = *plan;
     if (p.kind == XY_PLAN_AUTO) {
-        if (!cache_lookup(env_cache_path(), h->L, h->precision, &p)) p = default_plan(h->L);
+        if (!cache_lookup(env_cache_path(), h->L, h->precision, &p)) p = default_plan(h->L, h->precision);
     }
     if (!plan_ok(h->L, p)) return XY_EINVAL;
     h->plan = p;
@@ -689,7 +696,7 @@ int xyr::sweep_on_work(uint64_t seed, int32_t L, double beta, double delta, int3
     h.tev = nullptr;
     h.tcap = h.tn = 0;
     h.w = xyk::carve(work, L, precision);
-    h.plan = default_plan(L);
+    h.plan = default_plan(L, precision);
     // the workspace keeps the previous call's contents: the accept and arrival
     // counters must start at zero (a kernel, so the call may be graph-captured)
     hipError_t e = XY_LAUNCH(xyk::launch_zero_u64(h.w.counter, 4, stream));

@@ -18,7 +18,7 @@ bool inject_due();
 bool valid_L(int32_t L);
 bool valid_beta_delta(double beta, double delta);
 xyk::SweepArgs sweep_args(uint64_t seed, int L, int precision, double beta, double delta);
-xy_plan default_plan(int32_t L);
+xy_plan default_plan(int32_t L, int32_t precision);
 bool plan_ok(int32_t L, const xy_plan& p);
 bool cache_lookup(const char* path, int32_t L, int32_t precision, xy_plan* plan);
 const char* env_cache_path();

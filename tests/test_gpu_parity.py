@@ -10,6 +10,7 @@ sites are the only allowed differences, after which the trajectories are free
 from __future__ import annotations
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -209,6 +210,24 @@ def test_schedule_invariance(L, prec):
         assert np.array_equal(r["sweep"], r0["sweep"]), plan
         for f in ["cx", "cy", "ix", "iy", "mx", "my"]:
             np.testing.assert_allclose(r[f], r0[f], rtol=0, atol=1e-7 * L * L)
+
+
+@pytest.mark.skipif(bool(os.environ.get("XY_TUNE_CACHE")), reason="a tune cache overrides the default plan")
+def test_default_plan_by_size_and_precision():
+    """Without a tuned plan an FP32 lattice whose two buffers exceed the 256 MiB
+    MALL runs strip segments of 512 x 64; smaller and FP16 lattices run 256 x 16
+    tiles.  The default plan's sweeps equal the streaming plan's bit for bit."""
+    assert xy.Lattice(4096, seed=1).plan == (2, 256, 16, 1)
+    assert xy.Lattice(8192, seed=1, precision="fp16").plan == (2, 256, 16, 1)
+    a = xy.Lattice(8192, seed=2, beta=1.0, delta=1.2)
+    assert a.plan == (3, 512, 64, 1)
+    ra = xy.records(a.sweep(3, 1))
+    b = xy.Lattice(8192, seed=2, beta=1.0, delta=1.2, plan=STREAM)
+    rb = xy.records(b.sweep(3, 1))
+    assert torch.equal(a.state, b.state)
+    assert np.array_equal(ra["n_accept"], rb["n_accept"])
+    del a, b
+    torch.cuda.empty_cache()
 
 
 def test_odd_and_even_sweep_counts_agree():
