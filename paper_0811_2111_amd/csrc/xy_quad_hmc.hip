@@ -93,45 +93,11 @@ __device__ __forceinline__ void write_records(double v[4][7], double* __restrict
     }
 }
 
-// Grid of the record-writing passes: cols x rb workgroups, cols = 2 ceil(Hh/256)
-// (column block, colour interleaved); block b takes column b % cols and the run
-// of R = ceil(L / rb) rows starting at (b / cols) R.
+// Grid of the record-writing trajectory ends: cols x rb workgroups, cols =
+// 2 ceil(Hh/256), each writing one partial record per wave and replica.
 struct QGrid {
     int cols, rb;
 };
-
-// Momenta (Box-Muller of each replica's Philox purpose-2 words), saved angles,
-// partial records of H_old.
-__global__ void __launch_bounds__(kQThreads)
-k_qhmc_begin(const float4* __restrict__ st, float4* __restrict__ p, float4* __restrict__ saved, int L, uint32_t traj,
-             QHmcKeys keys, QGrid g, double* __restrict__ rec, int nrec)
-{
-    const int Hh = L >> 1, P = (Hh + 1) >> 1;
-    const unsigned b = blockIdx.x;
-    const int col = (int)(b % (unsigned)g.cols);
-    const int k = (col >> 1) * kQThreads + threadIdx.x;
-    const int c = col & 1;
-    double v[4][7] = {};
-    const int R = (L + g.rb - 1) / g.rb, y0 = (int)(b / (unsigned)g.cols) * R, y1 = y0 + R < L ? y0 + R : L;
-    if (k < Hh) {
-        for (int y = y0; y < y1; ++y) {
-            const Nb4 a = load_nb4(st, L, Hh, c, y, k);
-            const size_t i = ((size_t)c * L + y) * Hh + k;
-            saved[i] = a.t;
-            float4 pm;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const u32x4 w = philox10(traj, (uint32_t)c, 2u, (uint32_t)y * (uint32_t)P + (uint32_t)(k >> 1),
-                                         keys.k0[r], keys.k1[r]);
-                const float pr = (k & 1) ? box_muller(w.z, w.w) : box_muller(w.x, w.y);
-                f4set(pm, r, pr);
-                add_site(v[r], replica_nb(a, r), c, __fmul_rn(0.5f, __fmul_rn(pr, pr)));
-            }
-            p[i] = pm;
-        }
-    }
-    write_records(v, rec, nrec, b);       // every lane reaches the wave sums
-}
 
 // One leap-frog step of every replica: p += kick_r F, then a drift of
 // eps/(2 pi) p turns.  Grid (2 ceil(Hh/256), L).
@@ -279,34 +245,109 @@ static void launch_qmulti(unsigned nb, hipStream_t s, const float4* src, float4*
     hipLaunchKernelGGL(k_qhmc_multi<K>, dim3(nb), dim3(kQThreads), 0, s, src, dst, psrc, pdst, L, kick0, kick, drift);
 }
 
-// Final half kick and the partial records of H_new; `copy` != NULL receives the
-// angles (the final ones may sit in the second buffer).
-__global__ void __launch_bounds__(kQThreads)
-k_qhmc_end(const float4* __restrict__ st, float4* __restrict__ copy, const float4* __restrict__ p, int L,
-           float4 kick, QGrid g, double* __restrict__ rec, int nrec)
+// The trajectory ends by runs of rows.  A thread takes entry k of both planes
+// down a run of consecutive rows: each plane's entries of the rows above, at and
+// below sit in registers with the four replicas' (cos, sin), and each row adds
+// one edge entry of each plane (k - 1 or k + 1, the side the other plane's site
+// needs), so a float4 is read once as its own entry and once as an edge, and a
+// replica site costs two sines and cosines (a thread per site reading its four
+// neighbours costs five, and took 243 and 212 us at L = 4096 where these take
+// 198 and 164).  BEGIN: momenta (Box-Muller of each replica's Philox purpose-2
+// words, as the single lattice's), saved angles, partial records of H_old; else
+// the final half kick and the records of H_new, and `copy` != NULL receives the
+// angles (the final ones may sit in the second buffer).  Block b of the record
+// grid (QGrid) takes column block b % (cols / 2) of both planes and run
+// b / (cols / 2) of 2 rb runs of rows.
+struct CS4 {
+    float c[4], s[4];
+};
+__device__ __forceinline__ CS4 cs4(float4 t)
 {
-    const int Hh = L >> 1;
+    CS4 q;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sincos_turn(f4c(t, r), q.s[r], q.c[r]);
+    return q;
+}
+__device__ __forceinline__ Nb nb_of(const CS4& own, const CS4& l, const CS4& rt, const CS4& u, const CS4& d, int r)
+{
+    Nb n;
+    n.c = own.c[r]; n.s = own.s[r];
+    n.cl = l.c[r]; n.sl = l.s[r];
+    n.cr = rt.c[r]; n.sr = rt.s[r];
+    n.cu = u.c[r]; n.su = u.s[r];
+    n.cd = d.c[r]; n.sd = d.s[r];
+    return n;
+}
+
+template <bool BEGIN>
+__global__ void __launch_bounds__(kQThreads)
+k_qhmc_ends(const float4* __restrict__ st, float4* __restrict__ p, float4* __restrict__ copy, int L, uint32_t traj,
+            QHmcKeys keys, float4 kick, QGrid g, double* __restrict__ rec, int nrec)
+{
+    const int Hh = L >> 1, P = (Hh + 1) >> 1;
     const unsigned b = blockIdx.x;
-    const int col = (int)(b % (unsigned)g.cols);
-    const int k = (col >> 1) * kQThreads + threadIdx.x;
-    const int c = col & 1;
+    const int cols2 = g.cols >> 1, runs = 2 * g.rb;
+    const int k = (int)(b % (unsigned)cols2) * kQThreads + (int)threadIdx.x;
+    const int run = (int)(b / (unsigned)cols2);
     double v[4][7] = {};
-    const int R = (L + g.rb - 1) / g.rb, y0 = (int)(b / (unsigned)g.cols) * R, y1 = y0 + R < L ? y0 + R : L;
-    if (k < Hh) {
+    const int R = (L + runs - 1) / runs, y0 = run * R, y1 = y0 + R < L ? y0 + R : L;
+    if (k < Hh && y0 < y1) {
+        const float4* pl0 = st;
+        const float4* pl1 = st + (size_t)L * Hh;
+        float4 t0 = pl0[(size_t)y0 * Hh + k], t1 = pl1[(size_t)y0 * Hh + k];
+        const int ym = qwrap(y0 - 1, L);
+        CS4 u0 = cs4(pl0[(size_t)ym * Hh + k]), u1 = cs4(pl1[(size_t)ym * Hh + k]);
+        CS4 h0 = cs4(t0), h1 = cs4(t1);
+        const int km = qwrap(k - 1, Hh), kp = qwrap(k + 1, Hh);
         for (int y = y0; y < y1; ++y) {
-            const Nb4 a = load_nb4(st, L, Hh, c, y, k);
-            const size_t i = ((size_t)c * L + y) * Hh + k;
-            if (copy) copy[i] = a.t;
-            const float4 pv = p[i];
+            const int yd = qwrap(y + 1, L);
+            const float4 n0 = pl0[(size_t)yd * Hh + k], n1 = pl1[(size_t)yd * Hh + k];
+            // plane 0's site has o = y & 1 (neighbours in plane 1 at k + o - 1 and
+            // k + o), plane 1's the other parity: each needs one edge entry
+            const int o = y & 1;
+            const CS4 e1 = cs4(pl1[(size_t)y * Hh + (o ? kp : km)]);
+            const CS4 e0 = cs4(pl0[(size_t)y * Hh + (o ? km : kp)]);
+            const CS4 d0 = cs4(n0), d1 = cs4(n1);
+            const size_t i0 = (size_t)y * Hh + k, i1 = ((size_t)L + y) * Hh + k;
+            if (BEGIN || copy) {
+                copy[i0] = t0;
+                copy[i1] = t1;
+            }
+            float4 pv0 = make_float4(0.f, 0.f, 0.f, 0.f), pv1 = pv0, pm0, pm1;
+            if constexpr (!BEGIN) {
+                pv0 = p[i0];
+                pv1 = p[i1];
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const Nb n = replica_nb(a, r);
-                const float pn = __fmaf_rn(f4c(kick, r), sin_sum(n), f4c(pv, r));
-                add_site(v[r], n, c, __fmul_rn(0.5f, __fmul_rn(pn, pn)));
+                const Nb na = nb_of(h0, o ? h1 : e1, o ? e1 : h1, u1, d1, r);
+                const Nb nb = nb_of(h1, o ? e0 : h0, o ? h0 : e0, u0, d0, r);
+                float pa, pb;
+                if constexpr (BEGIN) {
+                    const uint32_t j = (uint32_t)y * (uint32_t)P + (uint32_t)(k >> 1);
+                    const u32x4 wa = philox10(traj, 0u, 2u, j, keys.k0[r], keys.k1[r]);
+                    const u32x4 wb = philox10(traj, 1u, 2u, j, keys.k0[r], keys.k1[r]);
+                    pa = (k & 1) ? box_muller(wa.z, wa.w) : box_muller(wa.x, wa.y);
+                    pb = (k & 1) ? box_muller(wb.z, wb.w) : box_muller(wb.x, wb.y);
+                } else {
+                    pa = __fmaf_rn(f4c(kick, r), sin_sum(na), f4c(pv0, r));
+                    pb = __fmaf_rn(f4c(kick, r), sin_sum(nb), f4c(pv1, r));
+                }
+                f4set(pm0, r, pa);
+                f4set(pm1, r, pb);
+                add_site(v[r], na, 0, __fmul_rn(0.5f, __fmul_rn(pa, pa)));
+                add_site(v[r], nb, 1, __fmul_rn(0.5f, __fmul_rn(pb, pb)));
             }
+            if constexpr (BEGIN) {
+                p[i0] = pm0;
+                p[i1] = pm1;
+            }
+            u0 = h0; u1 = h1;
+            h0 = d0; h1 = d1;
+            t0 = n0; t1 = n1;
         }
     }
-    write_records(v, rec, nrec, b);
+    write_records(v, rec, nrec, b);       // every lane reaches the wave sums
 }
 
 // The vector Metropolis step: workgroup r sums replica r's chunk records of
@@ -411,7 +452,8 @@ hipError_t launch_quad_hmc_trajectory(float4* state, float4* pingpong, const Qua
     }
     const float4 kick_half = make_float4(kh[0], kh[1], kh[2], kh[3]);
     const float4 kick_full = make_float4(kf[0], kf[1], kf[2], kf[3]);
-    hipLaunchKernelGGL(k_qhmc_begin, grec, block, 0, s, state, w.p, w.saved, L, traj, keys, g, w.rec_old, nrec);
+    hipLaunchKernelGGL(k_qhmc_ends<true>, grec, block, 0, s, state, w.p, w.saved, L, traj, keys, kick_half, g,
+                       w.rec_old, nrec);
     float4* src = state;
     float4* dst = pingpong;
     float4* p = w.p;
@@ -446,8 +488,8 @@ hipError_t launch_quad_hmc_trajectory(float4* state, float4* pingpong, const Qua
             dst = t;
         }
     }
-    hipLaunchKernelGGL(k_qhmc_end, grec, block, 0, s, src, src == state ? nullptr : state, p, L, kick_half, g,
-                       w.rec_new, nrec);
+    hipLaunchKernelGGL(k_qhmc_ends<false>, grec, block, 0, s, src, p, src == state ? nullptr : state, L, traj, keys,
+                       kick_half, g, w.rec_new, nrec);
     hipError_t e = hipGetLastError();
     for (int r = 0; r < 4 && e == hipSuccess; ++r) {
         e = launch_reduce_chunks(w.rec_old + (size_t)r * nrec * 8, nrec, w.chunk_old + (size_t)r * nchunk * 8, s);
