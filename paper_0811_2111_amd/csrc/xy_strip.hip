@@ -17,7 +17,8 @@ namespace xyk {
 // the same XCD's L2, and only the 8 band boundaries cross XCDs.  (With bands of
 // whole strips instead, the lines beside a band's outer strips come from another
 // XCD: reads 1.22 x one load per angle at L = 16384 against 1.08 x.)  A lattice
-// with fewer than 8 segment rows per XCD takes bands of strips, else the plain order.
+// whose segment rows do not split into 8 equal bands takes bands of whole strips
+// if its strips do, else the plain order.
 __device__ __forceinline__ void xcd_strip(int b, int nsx, int nsy, int& sx, int& sy)
 {
     if ((nsy & 7) == 0) {
