@@ -115,7 +115,7 @@ typedef struct xy_obs {
  *                   traffic between sweeps.  Needs L <= 128, L % 4 == 0; tile_x,
  *                   tile_y ignored, sweeps_per_pass = 1.
  *   XY_PLAN_AUTO  : the tuned plan for (L, precision) if one is cached, else a
- *                   default: strip 512 x 64 for an FP32 lattice whose state and
+ *                   default: strip 512 x 64 for a lattice whose state and
  *                   ping-pong copy exceed 256 MiB, else the first fused tile of
  *                   256 x 16, 128 x 32, 64 x 32, 64 x 16 that L allows, else
  *                   XY_PLAN_STREAM. */

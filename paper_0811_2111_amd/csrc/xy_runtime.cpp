@@ -68,12 +68,13 @@ xyk::SweepArgs sweep_args(uint64_t seed, int L, int precision, double beta, doub
 
 xy_plan default_plan(int32_t L, int32_t precision)
 {
-    // An FP32 lattice whose state and ping-pong copy exceed the 256 MiB MALL is
-    // read from HBM every sweep; there the strip segments are the fastest plan
-    // (over the 256 x 16 tiles: 2% at L = 8192, 17% at L = 16384 with a record
-    // every sweep).  FP16 lattices keep the tiles.
-    if (precision == XY_FP32 && 2ull * (uint64_t)L * (uint64_t)L * 4ull > (256ull << 20) &&
-        xyk::strip_supported(L, 512, 64))
+    // A lattice whose state and ping-pong copy exceed the 256 MiB MALL is read
+    // from HBM every sweep; there the strip segments are the fastest plan (over
+    // the 256 x 16 tiles, FP32: 2% at L = 8192, 17% at L = 16384 with a record
+    // every sweep; FP16: 10% at L = 16384, while at L = 8192, whose two FP16
+    // buffers just fit the MALL, the tiles are 4% ahead).
+    const uint64_t elem = precision == XY_FP16 ? 2ull : 4ull;
+    if (2ull * (uint64_t)L * (uint64_t)L * elem > (256ull << 20) && xyk::strip_supported(L, 512, 64))
         return xy_plan{XY_PLAN_STRIP, 512, 64, 1};
     xy_plan p{XY_PLAN_STREAM, 0, 0, 1};
     static const int cand[][3] = {{256, 16, 1}, {128, 32, 1}, {64, 32, 1}, {64, 16, 1}};

@@ -213,16 +213,19 @@ def test_schedule_invariance(L, prec):
 
 
 @pytest.mark.skipif(bool(os.environ.get("XY_TUNE_CACHE")), reason="a tune cache overrides the default plan")
-def test_default_plan_by_size_and_precision():
-    """Without a tuned plan an FP32 lattice whose two buffers exceed the 256 MiB
-    MALL runs strip segments of 512 x 64; smaller and FP16 lattices run 256 x 16
-    tiles.  The default plan's sweeps equal the streaming plan's bit for bit."""
-    assert xy.Lattice(4096, seed=1).plan == (2, 256, 16, 1)
-    assert xy.Lattice(8192, seed=1, precision="fp16").plan == (2, 256, 16, 1)
-    a = xy.Lattice(8192, seed=2, beta=1.0, delta=1.2)
+@pytest.mark.parametrize("L,prec", [(8192, "fp32"), (16384, "fp16")])
+def test_default_plan_by_size_and_precision(L, prec):
+    """Without a tuned plan a lattice whose two buffers exceed the 256 MiB MALL
+    runs strip segments of 512 x 64; one whose buffers fit (L = 4096 in FP32,
+    L = 8192 in FP16) runs 256 x 16 tiles.  The default plan's sweeps equal the
+    streaming plan's bit for bit."""
+    small = 4096 if prec == "fp32" else 8192
+    assert xy.Lattice(small, seed=1, precision=prec).plan == (2, 256, 16, 1)
+    torch.cuda.empty_cache()
+    a = xy.Lattice(L, seed=2, beta=1.0, delta=1.2, precision=prec)
     assert a.plan == (3, 512, 64, 1)
     ra = xy.records(a.sweep(3, 1))
-    b = xy.Lattice(8192, seed=2, beta=1.0, delta=1.2, plan=STREAM)
+    b = xy.Lattice(L, seed=2, beta=1.0, delta=1.2, precision=prec, plan=STREAM)
     rb = xy.records(b.sweep(3, 1))
     assert torch.equal(a.state, b.state)
     assert np.array_equal(ra["n_accept"], rb["n_accept"])
